@@ -1,0 +1,636 @@
+/*
+ * gpe_oracle.c -- plain FP64 CPU reference for the 2D split-step Gross-Pitaevskii
+ * propagation of arXiv:2404.14401.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file; it exists so that the GPU library can be checked against an
+ * independent, slow and obviously correct implementation.  It shares no code,
+ * header, table or constant with the HIP path.
+ *
+ * Everything is double precision, one operation per loop, in the order the
+ * paper states it:
+ *   - the GPE and its Hamiltonian split T + V                 (Sec. 2, Eq. 1; Sec. 3.1)
+ *   - symmetric split-step: half potential kick, kinetic
+ *     propagation in Fourier space, half potential kick       (Sec. 3.1, Eqs. 3-4; the
+ *                                                              V/2-T-V/2 ordering of the
+ *                                                              same factorisation)
+ *   - the FFT imposes periodic boundaries on the grid         (Sec. 3.1)
+ *   - the non-linear potential is re-evaluated on the most
+ *     recent wave function at every kick                      (Sec. 3.1)
+ *   - dimensionless oscillator units, hbar = m = 1            (Sec. 3.2)
+ *   - imaginary time dt -> -i dtau, normalise after every
+ *     step                                                    (Sec. 3.3)
+ *   - optical lattice V0 cos^2(k y)                           (Sec. 5.2, Eq. 12)
+ *   - cavity potential V_t + V_p + V_c + V_i                  (Sec. 5.3, Eqs. 13-16)
+ *   - cavity field driven by the overlap
+ *     <psi| cos kx cos ky |psi>                               (Sec. 5.3, Eq. 17), here as
+ *                                                              the driven-damped ODE
+ *     d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta, whose fixed point is Eq. 17
+ *     with eta standing for N sqrt(V0 U0) and the undressed detuning.
+ *
+ * The FFT is an iterative radix-2 Cooley-Tukey transform (bit reversal, then
+ * butterflies) with every twiddle factor taken from cos/sin of its own index.
+ * A literal O(N^2) DFT is provided next to it so the FFT can be pinned.
+ *
+ * Conventions: psi is stored row-major [ny][nx] (x fastest); x_i = -Lx/2 + i Lx/Nx;
+ * k_j = (2 pi / L)(j - N [j >= N/2]); forward transform exp(-2 pi i jk/N) unscaled,
+ * inverse exp(+2 pi i jk/N) scaled by 1/N.
+ *
+ * OpenMP is used only to run independent rows / columns / instances at once; every
+ * reduction is a serial loop in a fixed order, so results do not depend on the
+ * thread count.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------ problem */
+
+/* Lattice-depth schedule.  kind 0: constant v0.  kind 1: linear ramp from v0 at t0
+ * to v1 at t1, clamped outside.  kind 2: piecewise-linear through nknots values
+ * placed evenly on [t0, t1], clamped outside. */
+typedef struct {
+    int kind;
+    int nknots;
+    double v0, v1, t0, t1;
+    const double *knots;
+} orc_sched;
+
+typedef struct {
+    int nx, ny;
+    double lx, ly;
+    double dt;
+    double g;
+    /* harmonic trap 1/2 wx^2 (x-x0)^2 + 1/2 wy^2 (y-y0)^2 (Sec. 5.1) */
+    double wx, wy, x0, y0;
+    /* lattices Vx(t) cos^2(kx x) and Vy(t) cos^2(ky y) (Sec. 5.2) */
+    double kx_lat, ky_lat;
+    orc_sched sx, sy;
+    /* cavity (Sec. 5.3): the pump is the y lattice, depth Vy(t), wavenumber kc */
+    int cavity;
+    double vc, kc, delta_c, kappa, eta;
+    /* optional extra static potential [ny][nx] (may be NULL) */
+    const double *vuser;
+} orc_problem;
+
+/* Propagation state carried between calls. */
+typedef struct {
+    double t;          /* current real time */
+    double alpha_re;   /* cavity field */
+    double alpha_im;
+    double theta;      /* Theta_n of the current psi */
+    double theta_prev; /* Theta_{n-1} */
+    int have_theta;    /* 0 before the first real-time step */
+} orc_state;
+
+static double sched_eval(const orc_sched *s, double t)
+{
+    if (s->kind == 0) return s->v0;
+    if (s->kind == 1) {
+        if (t <= s->t0) return s->v0;
+        if (t >= s->t1) return s->v1;
+        return s->v0 + (s->v1 - s->v0) * (t - s->t0) / (s->t1 - s->t0);
+    }
+    /* kind 2: knots */
+    int m = s->nknots;
+    if (m == 1 || t <= s->t0) return s->knots[0];
+    if (t >= s->t1) return s->knots[m - 1];
+    double u = (t - s->t0) / (s->t1 - s->t0) * (m - 1);
+    int i = (int)floor(u);
+    if (i >= m - 1) i = m - 2;
+    double w = u - i;
+    return (1.0 - w) * s->knots[i] + w * s->knots[i + 1];
+}
+
+static double xcoord(const orc_problem *p, int i) { return -0.5 * p->lx + i * (p->lx / p->nx); }
+static double ycoord(const orc_problem *p, int j) { return -0.5 * p->ly + j * (p->ly / p->ny); }
+
+static double kval(int j, int n, double len)
+{
+    int m = (j >= n / 2) ? j - n : j;
+    return 2.0 * M_PI * m / len;
+}
+
+/* External potential at a point (Sec. 5.1-5.3).  Cavity terms: U0|alpha|^2 cos^2(kx)
+ * and 2 sqrt(V0 U0) Re(alpha) cos(kx) cos(ky) with V0 the current pump depth. */
+static double potential(const orc_problem *p, int i, int j, double t, cplx alpha)
+{
+    double x = xcoord(p, i), y = ycoord(p, j);
+    double v = 0.5 * p->wx * p->wx * (x - p->x0) * (x - p->x0)
+             + 0.5 * p->wy * p->wy * (y - p->y0) * (y - p->y0);
+    double vx = sched_eval(&p->sx, t), vy = sched_eval(&p->sy, t);
+    double cx = cos(p->kx_lat * x), cy = cos(p->ky_lat * y);
+    v += vx * cx * cx + vy * cy * cy;
+    if (p->cavity) {
+        double ccx = cos(p->kc * x), ccy = cos(p->kc * y);
+        double a2 = creal(alpha) * creal(alpha) + cimag(alpha) * cimag(alpha);
+        v += p->vc * a2 * ccx * ccx;
+        v += 2.0 * sqrt(vy * p->vc) * creal(alpha) * ccx * ccy;
+    }
+    if (p->vuser) v += p->vuser[(size_t)j * p->nx + i];
+    return v;
+}
+
+/* ---------------------------------------------------------------------- FFT */
+
+/* Literal DFT of one line: X_k = sum_j x_j exp(-+2 pi i jk/n), inverse scaled 1/n. */
+void orc_dft1d(const cplx *in, cplx *out, int n, int inverse)
+{
+    double sgn = inverse ? 1.0 : -1.0;
+    for (int k = 0; k < n; k++) {
+        cplx s = 0;
+        for (int j = 0; j < n; j++) {
+            double ang = sgn * 2.0 * M_PI * (double)(((int64_t)j * k) % n) / n;
+            s += in[j] * (cos(ang) + I * sin(ang));
+        }
+        out[k] = inverse ? s / n : s;
+    }
+}
+
+/* Literal 2D DFT, the double sum written out (tiny grids only). */
+void orc_dft2d(const cplx *in, cplx *out, int nx, int ny, int inverse)
+{
+    double sgn = inverse ? 1.0 : -1.0;
+    for (int ky = 0; ky < ny; ky++)
+        for (int kx = 0; kx < nx; kx++) {
+            cplx s = 0;
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++) {
+                    double ang = sgn * 2.0 * M_PI *
+                        ((double)(((int64_t)x * kx) % nx) / nx + (double)(((int64_t)y * ky) % ny) / ny);
+                    s += in[(size_t)y * nx + x] * (cos(ang) + I * sin(ang));
+                }
+            out[(size_t)ky * nx + kx] = inverse ? s / ((double)nx * ny) : s;
+        }
+}
+
+/* Twiddles w[j] = exp(-2 pi i j / n), j < n/2, each from cos/sin of its own index. */
+static cplx *make_twiddles(int n)
+{
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)(n / 2 > 0 ? n / 2 : 1));
+    for (int j = 0; j < n / 2; j++) {
+        double ang = -2.0 * M_PI * j / n;
+        w[j] = cos(ang) + I * sin(ang);
+    }
+    return w;
+}
+
+/* In-place iterative radix-2 FFT of length n (a power of two). */
+static void fft_line(cplx *a, int n, int inverse, const cplx *w)
+{
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { cplx t = a[i]; a[i] = a[j]; a[j] = t; }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, step = n / len;
+        for (int i = 0; i < n; i += len)
+            for (int j = 0; j < half; j++) {
+                cplx tw = inverse ? conj(w[j * step]) : w[j * step];
+                cplx u = a[i + j], v = a[i + j + half] * tw;
+                a[i + j] = u + v;
+                a[i + j + half] = u - v;
+            }
+    }
+    if (inverse)
+        for (int i = 0; i < n; i++) a[i] /= n;
+}
+
+void orc_fft1d(cplx *a, int n, int inverse)
+{
+    cplx *w = make_twiddles(n);
+    fft_line(a, n, inverse, w);
+    free(w);
+}
+
+/* 2D transform: every row, then every column. */
+void orc_fft2d(cplx *a, int nx, int ny, int inverse)
+{
+    cplx *wx = make_twiddles(nx), *wy = make_twiddles(ny);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; j++) fft_line(a + (size_t)j * nx, nx, inverse, wx);
+#pragma omp parallel
+    {
+        cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+#pragma omp for schedule(static)
+        for (int i = 0; i < nx; i++) {
+            for (int j = 0; j < ny; j++) col[j] = a[(size_t)j * nx + i];
+            fft_line(col, ny, inverse, wy);
+            for (int j = 0; j < ny; j++) a[(size_t)j * nx + i] = col[j];
+        }
+        free(col);
+    }
+    free(wx);
+    free(wy);
+}
+
+/* ------------------------------------------------------------ split step */
+
+/* Potential kick psi <- psi exp(-i (V + g|psi|^2) h) in real time, or
+ * psi <- psi exp(-(V + g|psi|^2) h) in imaginary time (Sec. 3.1, Sec. 3.3). */
+static void kick(const orc_problem *p, cplx *psi, double t, cplx alpha, double h, int imag)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+            double th = (potential(p, i, j, t, alpha) + p->g * dens) * h;
+            if (imag)
+                psi[q] *= exp(-th);
+            else
+                psi[q] *= cos(th) - I * sin(th);
+        }
+}
+
+/* Kinetic propagation over a full dt in Fourier space: exp(-i k^2 dt / 2)
+ * (imaginary time: exp(-k^2 dt / 2)), hbar = m = 1 (Sec. 3.1-3.3). */
+static void kinetic(const orc_problem *p, cplx *psi, int imag)
+{
+    orc_fft2d(psi, p->nx, p->ny, 0);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; j++) {
+        double ky = kval(j, p->ny, p->ly);
+        for (int i = 0; i < p->nx; i++) {
+            double kx = kval(i, p->nx, p->lx);
+            double ph = 0.5 * (kx * kx + ky * ky) * p->dt;
+            size_t q = (size_t)j * p->nx + i;
+            if (imag)
+                psi[q] *= exp(-ph);
+            else
+                psi[q] *= cos(ph) - I * sin(ph);
+        }
+    }
+    orc_fft2d(psi, p->nx, p->ny, 1);
+}
+
+/* Reductions over the real-space wave function, dA = dx dy (Sec. 3.3, Sec. 5.3). */
+double orc_norm(const orc_problem *p, const cplx *psi)
+{
+    double s = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
+    for (size_t q = 0; q < (size_t)p->nx * p->ny; q++)
+        s += creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+    return s * da;
+}
+
+/* Theta = integral cos(kc x) cos(kc y) |psi|^2 dx dy  (Sec. 5.3, Eq. 17 numerator). */
+double orc_theta(const orc_problem *p, const cplx *psi)
+{
+    double s = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
+    for (int j = 0; j < p->ny; j++) {
+        double cy = cos(p->kc * ycoord(p, j));
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+            s += cos(p->kc * xcoord(p, i)) * cy * dens;
+        }
+    }
+    return s * da;
+}
+
+/* <x>, <y> (unnormalised integrals of x|psi|^2 and y|psi|^2). */
+void orc_moments(const orc_problem *p, const cplx *psi, double *mx, double *my)
+{
+    double sx = 0, sy = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+            sx += xcoord(p, i) * dens;
+            sy += ycoord(p, j) * dens;
+        }
+    *mx = sx * da;
+    *my = sy * da;
+}
+
+/* Cavity-field update over one step: exponential integrator of
+ * d alpha/dt = lambda alpha - i eta Theta(t), lambda = i Delta_c - kappa, with the
+ * forcing extrapolated to second order, Theta_bar = (3 Theta_n - Theta_{n-1}) / 2:
+ *   alpha_{n+1} = e^{lambda dt} alpha_n + (e^{lambda dt} - 1)/lambda * (-i eta Theta_bar).
+ * Exact when Theta is constant.  (The adiabatic value of Sec. 5.3, Eq. 17, is this
+ * ODE's fixed point.) */
+static cplx cavity_advance(const orc_problem *p, cplx alpha, double theta_n, double theta_prev)
+{
+    cplx lam = I * p->delta_c - p->kappa;
+    cplx e = cexp(lam * p->dt);
+    double tb = 0.5 * (3.0 * theta_n - theta_prev);
+    cplx phi1 = (cabs(lam) > 0) ? (e - 1.0) / lam : p->dt;
+    return e * alpha + phi1 * (-I * p->eta * tb);
+}
+
+/* Optional per-step observables: for each step n, record
+ * {norm, Theta, Re alpha, Im alpha, <x>, <y>} of psi_{n+1}.  */
+#define ORC_NOBS 6
+
+static void record(const orc_problem *p, const cplx *psi, cplx alpha, double theta, double *obs)
+{
+    if (!obs) return;
+    obs[0] = orc_norm(p, psi);
+    obs[1] = theta;
+    obs[2] = creal(alpha);
+    obs[3] = cimag(alpha);
+    orc_moments(p, psi, &obs[4], &obs[5]);
+}
+
+/* Real-time split step, n times (Sec. 3.1):
+ *   1. (cavity) alpha_{n+1} from alpha_n, Theta_n, Theta_{n-1}
+ *   2. psi' = psi_n exp(-i [V(t_n; alpha_n) + g|psi_n|^2] dt/2)
+ *   3. psi* = IFFT2( exp(-i k^2 dt/2) FFT2(psi') )
+ *   4. psi_{n+1} = psi* exp(-i [V(t_{n+1}; alpha_{n+1}) + g|psi*|^2] dt/2)
+ *   5. (cavity) Theta_{n+1} from psi_{n+1}
+ * obs (nullable): nsteps * ORC_NOBS doubles. */
+int orc_step_real(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps, double *obs)
+{
+    double h = 0.5 * p->dt;
+    cplx alpha = s->alpha_re + I * s->alpha_im;
+    if (p->cavity && !s->have_theta) {
+        s->theta = orc_theta(p, psi);
+        s->theta_prev = s->theta;
+        s->have_theta = 1;
+    }
+    for (int64_t n = 0; n < nsteps; n++) {
+        double tn = s->t, tn1 = s->t + p->dt;
+        cplx alpha1 = alpha;
+        if (p->cavity) alpha1 = cavity_advance(p, alpha, s->theta, s->theta_prev);
+        kick(p, psi, tn, alpha, h, 0);
+        kinetic(p, psi, 0);
+        kick(p, psi, tn1, alpha1, h, 0);
+        double th = 0;
+        if (p->cavity || obs) th = orc_theta(p, psi);
+        if (p->cavity) {
+            s->theta_prev = s->theta;
+            s->theta = th;
+        }
+        alpha = alpha1;
+        s->t = tn1;
+        record(p, psi, alpha, th, obs ? obs + n * ORC_NOBS : NULL);
+    }
+    s->alpha_re = creal(alpha);
+    s->alpha_im = cimag(alpha);
+    return 0;
+}
+
+/* Imaginary-time split step (Sec. 3.3): dt -> -i dtau in every factor, potential
+ * frozen at time s->t, cavity field held fixed, then psi <- psi / sqrt(norm). */
+int orc_step_imag(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps, double *obs)
+{
+    double h = 0.5 * p->dt;
+    cplx alpha = s->alpha_re + I * s->alpha_im;
+    size_t npts = (size_t)p->nx * p->ny;
+    for (int64_t n = 0; n < nsteps; n++) {
+        kick(p, psi, s->t, alpha, h, 1);
+        kinetic(p, psi, 1);
+        kick(p, psi, s->t, alpha, h, 1);
+        double nrm = orc_norm(p, psi);
+        double sc = 1.0 / sqrt(nrm);
+        for (size_t q = 0; q < npts; q++) psi[q] *= sc;
+        if (obs) {
+            double *o = obs + n * ORC_NOBS;
+            record(p, psi, alpha, orc_theta(p, psi), o);
+            o[0] = nrm; /* pre-normalisation norm: -ln(o[0]) / (2 dtau) estimates mu */
+        }
+    }
+    return 0;
+}
+
+/* Energy functional of psi at time t (validation, Sec. 5.1):
+ *   E_kin = dA/(NxNy) sum_k |k|^2/2 |FFT2(psi)_k|^2
+ *   E_pot = dA sum V |psi|^2,  E_int = g/2 dA sum |psi|^4
+ *   mu = E_kin + E_pot + 2 E_int; every term divided by the norm.
+ * out = {E_kin, E_pot, E_int, E, mu, norm}. */
+void orc_energy(const orc_problem *p, const cplx *psi, double t, double alpha_re, double alpha_im,
+                double *out)
+{
+    size_t npts = (size_t)p->nx * p->ny;
+    double da = (p->lx / p->nx) * (p->ly / p->ny);
+    cplx alpha = alpha_re + I * alpha_im;
+    cplx *f = (cplx *)malloc(sizeof(cplx) * npts);
+    memcpy(f, psi, sizeof(cplx) * npts);
+    orc_fft2d(f, p->nx, p->ny, 0);
+    double ek = 0, ep = 0, ei = 0, nrm = 0;
+    for (int j = 0; j < p->ny; j++) {
+        double ky = kval(j, p->ny, p->ly);
+        for (int i = 0; i < p->nx; i++) {
+            double kx = kval(i, p->nx, p->lx);
+            size_t q = (size_t)j * p->nx + i;
+            double a2 = creal(f[q]) * creal(f[q]) + cimag(f[q]) * cimag(f[q]);
+            ek += 0.5 * (kx * kx + ky * ky) * a2;
+        }
+    }
+    ek *= da / (double)npts;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+            ep += potential(p, i, j, t, alpha) * dens;
+            ei += dens * dens;
+            nrm += dens;
+        }
+    ep *= da;
+    ei *= 0.5 * p->g * da;
+    nrm *= da;
+    free(f);
+    out[0] = ek / nrm;
+    out[1] = ep / nrm;
+    out[2] = ei / nrm;
+    out[3] = (ek + ep + ei) / nrm;
+    out[4] = (ek + ep + 2.0 * ei) / nrm;
+    out[5] = nrm;
+}
+
+/* Potential on the whole grid (for tests and plots). */
+void orc_potential_grid(const orc_problem *p, double t, double alpha_re, double alpha_im, double *v)
+{
+    cplx alpha = alpha_re + I * alpha_im;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) v[(size_t)j * p->nx + i] = potential(p, i, j, t, alpha);
+}
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------- adjoint */
+/*
+ * Discrete adjoint of the real-time split step with respect to the knot values
+ * c_m of a piecewise-linear lattice-depth schedule Vx(t) = sum_m c_m w_m(t) (the
+ * time-dependent lattice of Sec. 5.2 used as a control).  The paper has no
+ * gradient; this is the exact reverse-mode derivative of the discrete map defined
+ * by orc_step_real (cavity off), written in the real-gradient convention
+ *   G = dL/d(Re psi) + i dL/d(Im psi),  dL = Re sum conj(G) d psi.
+ * Per kick psi' = psi e^{-i theta}, theta = (V + g|psi|^2) h:
+ *   s = Im(conj(G') psi'),  G = G' e^{+i theta} + 2 g h s psi,  dL/dV(x) = h s(x).
+ * Per kinetic propagation psi* = U psi' (U = IFFT2 M FFT2, unitary):
+ *   G = IFFT2(conj(M) FFT2(G')).
+ * Losses: kind 0, L = 1 - |<target|psi(T)>|^2 with <a|b> = sum conj(a) b dA
+ *   (terminal G = -2 c target dA, c = <target|psi(T)>);
+ *   kind 1, L = E_kin + E_pot + E_int of psi(T) at time T (norm conserved in real time;
+ *   terminal G = 2 dA (T psi + V psi + g|psi|^2 psi)).
+ * Forward states are kept as checkpoints every `ckpt` steps; each segment is
+ * recomputed forward before it is swept backward, so the gradient is the exact
+ * adjoint of this file's own forward map.
+ */
+
+static void hat_weights(const orc_sched *s, double t, int *i0, double *w0, double *w1)
+{
+    int m = s->nknots;
+    if (m == 1 || t <= s->t0) { *i0 = 0; *w0 = 1; *w1 = 0; return; }
+    if (t >= s->t1) { *i0 = m - 2; *w0 = 0; *w1 = 1; return; }
+    double u = (t - s->t0) / (s->t1 - s->t0) * (m - 1);
+    int i = (int)floor(u);
+    if (i >= m - 1) i = m - 2;
+    *i0 = i;
+    *w1 = u - i;
+    *w0 = 1.0 - *w1;
+}
+
+/* Backward through one kick at time t.  zout is the kick's output; on return z holds
+ * its input (reconstructed exactly as zout e^{+i theta}, |z| = |zout|) and G the
+ * gradient with respect to it.  Accumulates dL/dc into grad. */
+static void kick_adjoint(const orc_problem *p, const cplx *zout, cplx *z, cplx *G, double t, double h,
+                         double *grad)
+{
+    double lat_sum = 0;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(zout[q]) * creal(zout[q]) + cimag(zout[q]) * cimag(zout[q]);
+            double th = (potential(p, i, j, t, 0) + p->g * dens) * h;
+            cplx e = cos(th) + I * sin(th);
+            cplx zin = zout[q] * e;
+            double s = cimag(conj(G[q]) * zout[q]);
+            G[q] = G[q] * e + 2.0 * p->g * h * s * zin;
+            z[q] = zin;
+            double c = cos(p->kx_lat * xcoord(p, i));
+            lat_sum += h * s * c * c;
+        }
+    if (grad && p->sx.kind == 2) {
+        int i0; double w0, w1;
+        hat_weights(&p->sx, t, &i0, &w0, &w1);
+        grad[i0] += w0 * lat_sum;
+        grad[i0 + 1] += w1 * lat_sum;
+    }
+}
+
+/* Backward through the kinetic propagation: G <- IFFT2(conj(M) FFT2(G)). */
+static void kinetic_adjoint(const orc_problem *p, cplx *G)
+{
+    orc_fft2d(G, p->nx, p->ny, 0);
+    for (int j = 0; j < p->ny; j++) {
+        double ky = kval(j, p->ny, p->ly);
+        for (int i = 0; i < p->nx; i++) {
+            double kx = kval(i, p->nx, p->lx);
+            double ph = 0.5 * (kx * kx + ky * ky) * p->dt;
+            G[(size_t)j * p->nx + i] *= cos(ph) + I * sin(ph);
+        }
+    }
+    orc_fft2d(G, p->nx, p->ny, 1);
+}
+
+int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *target, int64_t nsteps,
+                int64_t ckpt, int loss_kind, double *loss, double *grad, cplx *psi_final)
+{
+    if (p->cavity || p->sx.kind != 2 || nsteps < 1) return -1;
+    if (ckpt < 1) ckpt = 1;
+    size_t npts = (size_t)p->nx * p->ny;
+    double da = (p->lx / p->nx) * (p->ly / p->ny), h = 0.5 * p->dt;
+    int64_t nck = (nsteps + ckpt - 1) / ckpt;
+    cplx *ck = (cplx *)malloc(sizeof(cplx) * npts * (size_t)nck);
+    cplx *seg = (cplx *)malloc(sizeof(cplx) * npts * (size_t)(ckpt + 1));
+    cplx *psi = (cplx *)malloc(sizeof(cplx) * npts);
+    cplx *G = (cplx *)malloc(sizeof(cplx) * npts);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * npts);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * npts);
+    orc_state st = {0};
+
+    /* forward sweep, keeping a checkpoint at the start of every segment */
+    memcpy(psi, psi0, sizeof(cplx) * npts);
+    st.t = t0;
+    for (int64_t c = 0; c < nck; c++) {
+        memcpy(ck + (size_t)c * npts, psi, sizeof(cplx) * npts);
+        int64_t len = (c == nck - 1) ? nsteps - c * ckpt : ckpt;
+        orc_step_real(p, &st, psi, len, NULL);
+    }
+    double T = t0 + nsteps * p->dt;
+    if (psi_final) memcpy(psi_final, psi, sizeof(cplx) * npts);
+
+    /* terminal gradient */
+    for (int m = 0; m < p->sx.nknots; m++) grad[m] = 0;
+    if (loss_kind == 0) {
+        cplx c = 0;
+        for (size_t q = 0; q < npts; q++) c += conj(target[q]) * psi[q];
+        c *= da;
+        *loss = 1.0 - (creal(c) * creal(c) + cimag(c) * cimag(c));
+        for (size_t q = 0; q < npts; q++) G[q] = -2.0 * c * target[q] * da;
+    } else {
+        double e[6];
+        orc_energy(p, psi, T, 0, 0, e);
+        *loss = (e[0] + e[1] + e[2]) * e[5];
+        memcpy(G, psi, sizeof(cplx) * npts);
+        orc_fft2d(G, p->nx, p->ny, 0);
+        for (int j = 0; j < p->ny; j++) {
+            double ky = kval(j, p->ny, p->ly);
+            for (int i = 0; i < p->nx; i++) {
+                double kx = kval(i, p->nx, p->lx);
+                G[(size_t)j * p->nx + i] *= 0.5 * (kx * kx + ky * ky);
+            }
+        }
+        orc_fft2d(G, p->nx, p->ny, 1);
+        double lat_sum = 0;
+        for (int j = 0; j < p->ny; j++)
+            for (int i = 0; i < p->nx; i++) {
+                size_t q = (size_t)j * p->nx + i;
+                double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+                G[q] = 2.0 * da * (G[q] + (potential(p, i, j, T, 0) + p->g * dens) * psi[q]);
+                double cx = cos(p->kx_lat * xcoord(p, i));
+                lat_sum += da * cx * cx * dens;
+            }
+        int i0; double w0, w1;
+        hat_weights(&p->sx, T, &i0, &w0, &w1);
+        grad[i0] += w0 * lat_sum;
+        grad[i0 + 1] += w1 * lat_sum;
+    }
+
+    /* backward sweep, segment by segment */
+    for (int64_t c = nck - 1; c >= 0; c--) {
+        int64_t n0 = c * ckpt;
+        int64_t len = (c == nck - 1) ? nsteps - n0 : ckpt;
+        memcpy(seg, ck + (size_t)c * npts, sizeof(cplx) * npts);
+        orc_state s2 = {0};
+        s2.t = t0 + n0 * p->dt;
+        for (int64_t k = 0; k < len; k++) {
+            memcpy(seg + (size_t)(k + 1) * npts, seg + (size_t)k * npts, sizeof(cplx) * npts);
+            orc_step_real(p, &s2, seg + (size_t)(k + 1) * npts, 1, NULL);
+        }
+        for (int64_t k = len - 1; k >= 0; k--) {
+            double tn = t0 + (n0 + k) * p->dt, tn1 = tn + p->dt;
+            const cplx *zout = seg + (size_t)(k + 1) * npts;
+            /* second kick at t_{n+1}: output psi_{n+1}, input psi* -> a */
+            kick_adjoint(p, zout, a, G, tn1, h, grad);
+            /* kinetic: psi' = U^H psi* -> b */
+            memcpy(b, a, sizeof(cplx) * npts);
+            kinetic_adjoint(p, b);
+            kinetic_adjoint(p, G);
+            /* first kick at t_n: output psi', input psi_n */
+            kick_adjoint(p, b, a, G, tn, h, grad);
+        }
+    }
+    free(ck); free(seg); free(psi); free(G); free(a); free(b);
+    return 0;
+}

@@ -1,0 +1,192 @@
+"""Seeded synthetic workloads: grid/potential parameters and initial wave functions.
+
+This module holds data only -- box sizes, step counts, potential parameters and
+seeded initial states -- and none of the split-step arithmetic.  Both the GPU
+path's tests/benchmarks and the CPU oracle's tests draw their inputs from here, so
+the two sides always start from the same complex64-rounded values.
+
+Units are the dimensionless oscillator units of the paper (Sec. 3.2): hbar = m = 1,
+lengths in l = sqrt(hbar/(m w)), times in 1/w.  Grids are x_i = -L/2 + i L/N.
+
+The five workloads follow the method's use in the paper: imaginary-time ground
+states (Sec. 3.3, Sec. 5.1), real-time lattice dynamics (Sec. 5.2), the
+self-consistent cavity potential (Sec. 5.3), plus a batched parameter sweep and an
+optimal-control gradient of the lattice depth.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+
+@dataclass
+class Schedule:
+    """Lattice depth vs time: 'const' (v0), 'ramp' (v0 -> v1 on [t0, t1], clamped)
+    or 'knots' (piecewise-linear through `knots` spread evenly on [t0, t1])."""
+
+    kind: str = "const"
+    v0: float = 0.0
+    v1: float = 0.0
+    t0: float = 0.0
+    t1: float = 1.0
+    knots: np.ndarray | None = None
+
+
+@dataclass
+class Setup:
+    """One condensate: grid, step, interaction and external potential."""
+
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    dt: float
+    g: float = 0.0
+    wx: float = 1.0
+    wy: float = 1.0
+    x0: float = 0.0
+    y0: float = 0.0
+    kx_lat: float = 0.0
+    ky_lat: float = 0.0
+    sx: Schedule = field(default_factory=Schedule)
+    sy: Schedule = field(default_factory=Schedule)
+    cavity: bool = False
+    vc: float = 0.0
+    kc: float = 0.0
+    delta_c: float = 0.0
+    kappa: float = 0.0
+    eta: float = 0.0
+    alpha0: complex = 0j
+
+    def xs(self) -> np.ndarray:
+        return -0.5 * self.lx + np.arange(self.nx) * (self.lx / self.nx)
+
+    def ys(self) -> np.ndarray:
+        return -0.5 * self.ly + np.arange(self.ny) * (self.ly / self.ny)
+
+    def with_(self, **kw) -> "Setup":
+        return replace(self, **kw)
+
+
+def to_c64(psi: np.ndarray) -> np.ndarray:
+    """Round an FP64 state to complex64: both sides start from these exact values."""
+    return np.ascontiguousarray(psi, dtype=np.complex64)
+
+
+def normalise(s: Setup, psi: np.ndarray) -> np.ndarray:
+    """Scale to unit norm, sum |psi|^2 dx dy = 1 (normalisation convention)."""
+    da = (s.lx / s.nx) * (s.ly / s.ny)
+    return psi / np.sqrt(np.sum(np.abs(psi) ** 2) * da)
+
+
+def gaussian(s: Setup, width: float = 1.0, cx: float = 0.0, cy: float = 0.0) -> np.ndarray:
+    x, y = np.meshgrid(s.xs(), s.ys())
+    return normalise(s, np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * width**2)).astype(np.complex128))
+
+
+def noisy_gaussian(s: Setup, seed: int, width: float = 1.5, amp: float = 0.05) -> np.ndarray:
+    """Gaussian of the given width times (1 + amp*xi), xi ~ U[-1, 1) i.i.d. in C order
+    from PCG64(seed), normalised in FP64 and rounded to complex64."""
+    x, y = np.meshgrid(s.xs(), s.ys())
+    xi = np.random.Generator(np.random.PCG64(seed)).uniform(-1.0, 1.0, size=(s.ny, s.nx))
+    psi = np.exp(-(x**2 + y**2) / (2 * width**2)) * (1.0 + amp * xi)
+    return to_c64(normalise(s, psi.astype(np.complex128)))
+
+
+def thomas_fermi_guess(s: Setup, mu: float) -> np.ndarray:
+    """sqrt(max(mu - V_trap, 0)/g) (trap only), smoothed by a small floor, normalised:
+    a synthetic start close to a strongly interacting ground state (Sec. 5.1)."""
+    x, y = np.meshgrid(s.xs(), s.ys())
+    v = 0.5 * (s.wx**2 * (x - s.x0) ** 2 + s.wy**2 * (y - s.y0) ** 2)
+    dens = np.maximum(mu - v, 0.0) / max(s.g, 1e-30)
+    psi = np.sqrt(dens) + 1e-3 * np.exp(-(x**2 + y**2) / (2 * (0.25 * s.lx) ** 2))
+    return normalise(s, psi.astype(np.complex128))
+
+
+def random_state(s: Setup, seed: int) -> np.ndarray:
+    """Smooth random complex field (band-limited noise) for pass-level checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((s.ny, s.nx)) + 1j * rng.standard_normal((s.ny, s.nx))
+    return to_c64(normalise(s, z))
+
+
+# ----------------------------------------------------------------- workloads
+
+def imag_ground_64(g: float) -> Setup:
+    """Imaginary-time ground state: 64x64 on [-8, 8)^2, harmonic trap w = 1,
+    dtau = 1e-3, 2000 steps, g in {0, 100}."""
+    return Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=1e-3, g=g)
+
+
+IMAG_64_STEPS = 2000
+
+
+def dipole_lattice_256() -> Setup:
+    """Real-time dynamics on 256x256, [-16, 16)^2, g = 500, trap centre moved to
+    (0, 0.5), lattice Vx(t) cos^2(2x) ramped 0 -> 10 over the first 5000 steps
+    (t = 2.5), dt = 5e-4, 10000 steps."""
+    return Setup(nx=256, ny=256, lx=32.0, ly=32.0, dt=5e-4, g=500.0, y0=0.5, kx_lat=2.0,
+                 sx=Schedule("ramp", 0.0, 10.0, 0.0, 2.5))
+
+
+DIPOLE_256_STEPS = 10000
+
+
+def cavity_1024(seed: int = 0) -> Setup:
+    """Self-consistent cavity run on 1024x1024, [-32, 32)^2, trap w = 0.05, g = 1000,
+    pump lattice Vp cos^2(y) with Vp = 3, cavity lattice Vc = 3, k = 1,
+    Delta_c = -20, kappa = 10, eta = 5 U[0,1) from PCG64(seed), dt = 2e-4,
+    20000 steps, alpha_0 = 0."""
+    eta = 5.0 * np.random.Generator(np.random.PCG64(seed)).uniform()
+    return Setup(nx=1024, ny=1024, lx=64.0, ly=64.0, dt=2e-4, g=1000.0, wx=0.05, wy=0.05,
+                 ky_lat=1.0, sy=Schedule("const", 3.0), cavity=True, vc=3.0, kc=1.0,
+                 delta_c=-20.0, kappa=10.0, eta=float(eta))
+
+
+CAVITY_1024_STEPS = 20000
+
+
+def cavity_scaled(n: int, seed: int = 0) -> Setup:
+    """The cavity workload's physics on an n x n grid with the same spacing
+    dx = 1/16 (box n/16), for parity at sizes the oracle finishes in seconds."""
+    s = cavity_1024(seed)
+    return s.with_(nx=n, ny=n, lx=n / 16.0, ly=n / 16.0)
+
+
+@dataclass
+class BatchMember:
+    setup: Setup
+    psi0: np.ndarray
+
+
+def sweep_208(seed: int = 0, counts=(128, 64, 16)) -> list[Setup]:
+    """Batched sweep: 128 at 128^2 on [-8,8)^2, 64 at 256^2 on [-16,16)^2, 16 at 512^2
+    on [-32,32)^2 (dx = 0.125), trap w = 1 plus the 2D lattice V0 (cos^2 2x + cos^2 2y),
+    (V0, g) ~ (U[0,20], U[50,1000]) from PCG64(seed) in instance order, dt = 5e-4."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for n, cnt in zip((128, 256, 512), counts):
+        for _ in range(cnt):
+            v0 = float(rng.uniform(0.0, 20.0))
+            g = float(rng.uniform(50.0, 1000.0))
+            out.append(Setup(nx=n, ny=n, lx=n * 0.125, ly=n * 0.125, dt=5e-4, g=g,
+                             kx_lat=2.0, ky_lat=2.0, sx=Schedule("const", v0), sy=Schedule("const", v0)))
+    return out
+
+
+SWEEP_STEPS = 5000
+
+
+def control_512(b: int, n: int = 512, nknots: int = 200, nsteps: int = 5000) -> Setup:
+    """Optimal-control member b: n x n on [-16, 16)^2, trap w = 1, g = 300, lattice
+    V0(t) cos^2(2x) piecewise-linear over `nknots` values ~ U[0, 15] from PCG64(b),
+    knots spread over [0, T], T = nsteps * dt, dt = 5e-4."""
+    knots = np.random.Generator(np.random.PCG64(b)).uniform(0.0, 15.0, size=nknots)
+    dt = 5e-4
+    return Setup(nx=n, ny=n, lx=32.0, ly=32.0, dt=dt, g=300.0, kx_lat=2.0,
+                 sx=Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots))
+
+
+CONTROL_STEPS = 5000
+CONTROL_BATCH = 16

@@ -1,0 +1,401 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: each checks a closed form, a
+library special case, an invariant or a brute-force definition, chosen so that a
+dropped term, a wrong sign or index or a transposed operand fails at least one.
+CPU only.
+"""
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, rel_l2, state
+
+RNG = np.random.Generator(np.random.PCG64(1234))
+
+
+def crandn(*shape):
+    return RNG.standard_normal(shape) + 1j * RNG.standard_normal(shape)
+
+
+# ------------------------------------------------------------------ FFT (p1)
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32, 64])
+def test_fft1d_matches_brute_force_dft(n):
+    a = crandn(n)
+    for inv in (False, True):
+        assert np.abs(O.fft1d(a, inv) - O.dft1d(a, inv)).max() <= 1e-12 * max(1.0, np.abs(a).sum())
+
+
+@pytest.mark.parametrize("ny,nx", [(2, 2), (4, 8), (8, 4), (16, 16), (2, 32), (16, 8)])
+def test_fft2d_matches_literal_double_sum(ny, nx):
+    a = crandn(ny, nx)
+    for inv in (False, True):
+        ref = O.dft2d(a, inv)
+        assert np.abs(O.fft2d(a, inv) - ref).max() <= 1e-12 * np.abs(a).sum()
+
+
+@pytest.mark.parametrize("ny,nx", [(64, 64), (32, 128), (256, 16)])
+def test_fft2d_matches_numpy_and_round_trips(ny, nx):
+    a = crandn(ny, nx)
+    f = O.fft2d(a)
+    assert np.abs(f - np.fft.fft2(a)).max() <= 1e-13 * np.abs(f).max() * np.log2(nx * ny)
+    assert np.abs(O.fft2d(f, True) - a).max() <= 1e-14 * np.abs(a).max() * np.log2(nx * ny) * 4
+    # Parseval: sum |a|^2 = sum |F a|^2 / N
+    assert np.isclose(np.sum(np.abs(a) ** 2), np.sum(np.abs(f) ** 2) / a.size, rtol=1e-13)
+
+
+def test_fft_sign_convention_single_mode():
+    # forward transform of exp(+2 pi i m x/N) peaks at bin m with value N
+    n, m = 32, 5
+    x = np.exp(2j * np.pi * m * np.arange(n) / n)
+    f = O.fft1d(x)
+    assert abs(f[m] - n) < 1e-11 and np.abs(np.delete(f, m)).max() < 1e-11
+
+
+# ------------------------------------------------------- kinetic exactness (p2)
+
+def test_free_propagation_is_exact_spectral_flow():
+    """V = g = 0: every split step is the exact kinetic flow, so n steps equal one
+    multiplication by exp(-i k^2 t / 2) in Fourier space (numpy FFT as the
+    independent route)."""
+    s = W.Setup(nx=32, ny=16, lx=12.0, ly=6.0, dt=0.01, g=0.0, wx=0.0, wy=0.0)
+    psi0 = W.gaussian(s, 0.7, 0.5, -0.3) * np.exp(1j * 1.3 * s.xs()[None, :])
+    n = 37
+    out, _ = O.step_real(problem(s), state(s), psi0, n)
+    kx = 2 * np.pi * np.fft.fftfreq(s.nx, s.lx / s.nx)
+    ky = 2 * np.pi * np.fft.fftfreq(s.ny, s.ly / s.ny)
+    k2 = kx[None, :] ** 2 + ky[:, None] ** 2
+    ref = np.fft.ifft2(np.fft.fft2(psi0) * np.exp(-0.5j * k2 * n * s.dt))
+    assert rel_l2(out, ref) < 1e-13
+
+
+def test_free_gaussian_packet_closed_form():
+    """Free 2D Gaussian packet: |psi|^2 width sigma(t)^2 = sigma0^2 + (t/sigma0)^2 /... use the
+    analytic 1D solution per axis while the packet does not wrap."""
+    s = W.Setup(nx=128, ny=128, lx=40.0, ly=40.0, dt=0.02, g=0.0, wx=0.0, wy=0.0)
+    sig = 1.0
+    x, y = np.meshgrid(s.xs(), s.ys())
+    psi0 = np.exp(-(x**2 + y**2) / (2 * sig**2)).astype(complex)
+    psi0 /= np.sqrt(np.sum(np.abs(psi0) ** 2) * s.lx * s.ly / s.nx / s.ny)
+    n = 100
+    t = n * s.dt
+    out, _ = O.step_real(problem(s), state(s), psi0, n)
+    # psi(x,t) = (sig^2 / (sig^2 + i t))^(d/2) exp(-r^2 / (2 (sig^2 + i t))) * const
+    z = sig**2 + 1j * t
+    ref = (sig**2 / z) * np.exp(-(x**2 + y**2) / (2 * z))
+    ref /= np.sqrt(np.sum(np.abs(ref) ** 2) * s.lx * s.ly / s.nx / s.ny)
+    ref *= psi0[s.ny // 2, s.nx // 2] / abs(psi0[s.ny // 2, s.nx // 2])
+    assert rel_l2(out, ref) < 1e-10
+
+
+# --------------------------------------------------------------- kick (p3)
+
+def test_uniform_state_takes_the_exact_potential_phase():
+    """A uniform state has only the k = 0 mode, so the kinetic factor is 1 and each
+    step multiplies by exp(-i (V + g|psi|^2) dt) exactly.  A lattice with k = 0 is a
+    constant offset V0 cos^2(0) = V0 on both axes."""
+    s = W.Setup(nx=16, ny=8, lx=4.0, ly=2.0, dt=0.003, g=7.0, wx=0.0, wy=0.0,
+                kx_lat=0.0, ky_lat=0.0, sx=W.Schedule("const", 2.5), sy=W.Schedule("const", 0.75))
+    amp = 1.0 / np.sqrt(s.lx * s.ly)
+    psi0 = np.full((s.ny, s.nx), amp, dtype=complex)
+    n = 200
+    out, _ = O.step_real(problem(s), state(s), psi0, n)
+    phase = (2.5 + 0.75 + s.g * amp**2) * n * s.dt
+    assert np.abs(out - amp * np.exp(-1j * phase)).max() < 1e-13
+    # imaginary time keeps it uniform and normalised; the second half kick sees the
+    # density left by the first one (the most recent psi), so the pre-normalisation
+    # amplitude is amp e^{-(V + g amp^2) h} e^{-(V + g amp1^2) h}
+    out_i, obs = O.step_imag(problem(s), state(s), psi0, 3, want_obs=True)
+    assert np.abs(out_i - amp).max() < 1e-13
+    h, v = s.dt / 2, 2.5 + 0.75
+    amp1 = amp * np.exp(-(v + s.g * amp**2) * h)
+    amp2 = amp1 * np.exp(-(v + s.g * amp1**2) * h)
+    assert np.allclose(obs[:, 0], (amp2 / amp) ** 2, rtol=1e-13)
+
+
+def test_real_time_kick_keeps_modulus_under_strong_potential():
+    """With the kinetic factor trivial (uniform in x, k=0 in y), |psi| stays fixed."""
+    s = W.Setup(nx=32, ny=32, lx=8.0, ly=8.0, dt=0.01, g=3.0, wx=0.0, wy=0.0)
+    psi0 = W.random_state(s, 3).astype(complex)
+    out, obs = O.step_real(problem(s), state(s), psi0, 50, want_obs=True)
+    assert np.allclose(obs[:, 0], 1.0, atol=1e-12)
+
+
+# ----------------------------------------- harmonic ground state, g = 0 (p4)
+
+@pytest.mark.parametrize("dtau", [0.1, 0.05])
+def test_imaginary_time_fixed_point_is_the_discrete_gaussian(dtau):
+    """For V = r^2/2, g = 0, the V/2-T-V/2 map's fixed point is exactly
+    exp(-a r^2/2) with a = sqrt(1 + dtau^2/4) (derived from the Gaussian map
+    b -> b/(1 + b dtau) between half kicks); its energy is (a + 1/a)/2.  The
+    T/2-V/2-T/2 ordering would give a = 1/sqrt(1 + dtau^2/4) instead."""
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dtau, g=0.0)
+    out, _ = O.step_imag(problem(s), state(s), W.gaussian(s, 1.3, 0.2, -0.1), int(40 / dtau))
+    a = np.sqrt(1 + dtau**2 / 4)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    ref = W.normalise(s, np.exp(-a * (x**2 + y**2) / 2).astype(complex))
+    assert rel_l2(out, ref) < 1e-9
+    e = O.energy(problem(s), out)
+    assert abs(e["e"] - (a + 1 / a) / 2) < 1e-9
+    # other ordering would differ by about dtau^2 / 4 in a
+    assert abs(a - 1 / np.sqrt(1 + dtau**2 / 4)) > 1e-4
+
+
+def test_ground_state_energy_is_hbar_omega():
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=0.01, g=0.0, wx=1.0, wy=2.0)
+    out, _ = O.step_imag(problem(s), state(s), W.gaussian(s, 1.0), 3000)
+    e = O.energy(problem(s), out)
+    # anisotropic trap: E = (wx + wy)/2 up to O(dt^2)
+    assert abs(e["e"] - 1.5) < 1e-4
+
+
+# ------------------------------------------------ lattice term vs Mathieu
+
+def test_lattice_ground_energy_matches_mathieu():
+    """Ground state of -1/2 d2/dx2 + V0 cos^2(k x) on a periodic box (no x trap) is
+    E = V0/2 + k^2 a_0(q)/2, q = V0/(2 k^2) (Mathieu characteristic value); the y
+    axis carries a harmonic trap with energy 1/2."""
+    v0, k = 4.0, 2.0
+    s = W.Setup(nx=64, ny=64, lx=np.pi * 2, ly=12.0, dt=0.002, g=0.0, wx=0.0, wy=1.0,
+                kx_lat=k, sx=W.Schedule("const", v0))
+    out, _ = O.step_imag(problem(s), state(s), W.gaussian(s, 2.0), 8000)
+    e = O.energy(problem(s), out)
+    q = v0 / (2 * k * k)
+    ex = v0 / 2 + k * k * special.mathieu_a(0, q) / 2
+    assert abs(e["e"] - (ex + 0.5)) < 2e-5
+
+
+# ----------------------------------------------------- real time, g = 0 (p5)
+
+def test_stationary_discrete_gaussian_in_real_time():
+    """exp(-a r^2/2) with a = sqrt(1 - dt^2/4) is an eigenstate of the real-time map
+    (the same Gaussian algebra with i dt), so |psi| never changes."""
+    dt = 0.05
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dt, g=0.0)
+    a = np.sqrt(1 - dt**2 / 4)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    psi0 = W.normalise(s, np.exp(-a * (x**2 + y**2) / 2).astype(complex))
+    out, _ = O.step_real(problem(s), state(s), psi0, 400)
+    assert np.abs(np.abs(out) - np.abs(psi0)).max() < 1e-10
+    # the global phase advances by exactly the discrete eigenvalue
+    assert rel_l2(np.abs(out), np.abs(psi0)) < 1e-10
+
+
+@pytest.mark.parametrize("g", [0.0, 50.0])
+def test_kohn_dipole_follows_discrete_leapfrog(g):
+    """Displacing the trap centre by d: <y>_n = d (1 - cos(w_d t_n)) with
+    cos(w_d dt) = 1 - w^2 dt^2 / 2 (Strang on a quadratic Hamiltonian = velocity
+    Verlet for the centre of mass).  Exact at g = 0; to spectral accuracy for g > 0
+    (interactions exert no net force), also with an x-only lattice."""
+    s0 = W.Setup(nx=64, ny=64, lx=20.0, ly=20.0, dt=0.01, g=g, kx_lat=1.5, sx=W.Schedule("const", 1.0))
+    gs, _ = O.step_imag(problem(s0), state(s0), W.gaussian(s0, 1.2), 3000)
+    d, dt = 0.5, 0.02
+    s = s0.with_(y0=d, dt=dt)
+    out, obs = O.step_real(problem(s), state(s), gs, 500, want_obs=True)
+    n = np.arange(1, 501)
+    wd = np.arccos(1 - dt**2 / 2) / dt
+    y0 = W.Setup.ys  # noqa: F841 (documentation: <y> at t=0 is 0 by symmetry)
+    ref = d * (1 - np.cos(wd * n * dt))
+    tol = 1e-10 if g == 0 else 1e-6
+    assert np.abs(obs[:, 5] - ref).max() < tol
+
+
+# ------------------------------------------------ conservation laws (p6, p7)
+
+def test_norm_and_energy_conserved_in_real_time():
+    s0 = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=1e-3, g=100.0)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.gaussian(s0, 1.5), 3000)
+    s = s0.with_(x0=0.3, kx_lat=2.0, sx=W.Schedule("const", 3.0))
+    e0 = O.energy(problem(s), gs)["e"]
+    psi, obs = O.step_real(problem(s), state(s), gs, 2000, want_obs=True)
+    assert np.abs(obs[:, 0] - 1.0).max() < 1e-12
+    e1 = O.energy(problem(s), psi)["e"]
+    assert abs(e1 - e0) / abs(e0) < 1e-5
+
+
+# ---------------------------------------------------- second order (p8)
+
+def test_global_error_is_second_order_in_dt():
+    s0 = W.Setup(nx=32, ny=32, lx=12.0, ly=12.0, dt=0.1, g=40.0, x0=0.4, kx_lat=1.0,
+                 sx=W.Schedule("ramp", 0.0, 2.0, 0.0, 1.0))
+    psi0 = W.gaussian(s0, 1.0)
+    T = 0.8
+
+    def run(dt):
+        s = s0.with_(dt=dt)
+        out, _ = O.step_real(problem(s), state(s), psi0, int(round(T / dt)))
+        return out
+
+    ref = run(T / 512)
+    errs = [rel_l2(run(T / m), ref) for m in (16, 32, 64)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.8 < r2 < 4.2
+
+
+# ------------------------------------ imaginary time: monotone, virial, TF, mu
+
+def test_imaginary_time_energy_decreases_monotonically():
+    s = W.imag_ground_64(100.0)
+    psi = W.noisy_gaussian(s, 0)
+    es = []
+    st = state(s)
+    for _ in range(20):
+        psi, _ = O.step_imag(problem(s), st, psi, 25)
+        es.append(O.energy(problem(s), psi)["e"])
+    assert np.all(np.diff(es) < 0)
+
+
+@pytest.fixture(scope="module")
+def converged_g100():
+    out = {}
+    for dtau in (0.005, 0.0025):
+        s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dtau, g=100.0)
+        psi, _ = O.step_imag(problem(s), state(s), W.noisy_gaussian(s, 1), int(30 / dtau))
+        out[dtau] = (s, psi)
+    return out
+
+
+def test_virial_theorem_at_convergence(converged_g100):
+    """Scaling psi -> l psi(l r) makes E_kin, E_int ~ l^2 and E_pot ~ l^-2, so a 2D
+    stationary state has E_kin + E_int = E_pot (harmonic trap).  The normalised
+    imaginary-time fixed point carries an O(dtau) bias (the second half kick sees the
+    density before renormalisation), so the residual must halve with dtau and its
+    Richardson extrapolation must vanish."""
+    r = {}
+    for dtau, (s, psi) in converged_g100.items():
+        e = O.energy(problem(s), psi)
+        r[dtau] = (e["ekin"] + e["eint"] - e["epot"]) / e["e"]
+    assert 1.9 < r[0.005] / r[0.0025] < 2.1
+    assert abs(2 * r[0.0025] - r[0.005]) < 2e-5
+
+
+def test_mu_from_norm_decay_matches_functional(converged_g100):
+    """In imaginary time the pre-normalisation norm of a converged state is
+    exp(-2 mu dtau); the second half kick acting on the already decayed density
+    biases this by O(dtau), so the gap must halve with dtau and extrapolate to 0."""
+    gap = {}
+    for dtau, (s, psi) in converged_g100.items():
+        _, obs = O.step_imag(problem(s), state(s), psi, 1, want_obs=True)
+        mu_decay = -np.log(obs[0, 0]) / (2 * s.dt)
+        mu_fun = O.energy(problem(s), psi)["mu"]
+        gap[dtau] = (mu_decay - mu_fun) / mu_fun
+    assert 1.9 < gap[0.005] / gap[0.0025] < 2.1
+    assert abs(2 * gap[0.0025] - gap[0.005]) < 1e-4  # O(dtau^2) remainder, (mu dtau)^2 ~ 8e-4
+
+
+def test_thomas_fermi_limit_trend():
+    """mu -> w sqrt(g/pi) at large g (2D TF with unit norm); the exact mu lies above
+    TF and approaches it as g grows; the bulk density follows (mu - V)/g."""
+    gaps = []
+    for g in (100.0, 1000.0):
+        s = W.Setup(nx=64, ny=64, lx=24.0, ly=24.0, dt=0.005, g=g)
+        mu_tf = np.sqrt(g / np.pi)
+        psi, _ = O.step_imag(problem(s), state(s), W.thomas_fermi_guess(s, mu_tf), 4000)
+        e = O.energy(problem(s), psi)
+        gaps.append((e["mu"] - mu_tf) / mu_tf)
+        if g == 1000.0:
+            x, y = np.meshgrid(s.xs(), s.ys())
+            r2 = x**2 + y**2
+            bulk = r2 < 0.25 * 2 * mu_tf
+            n_tf = (e["mu"] - 0.5 * r2) / g
+            assert np.abs(np.abs(psi[bulk]) ** 2 - n_tf[bulk]).max() / n_tf.max() < 0.02
+            assert abs(e["e"] - 2 / 3 * e["mu"]) / e["mu"] < 0.02
+    assert 0 < gaps[1] < gaps[0] < 0.1
+
+
+# ------------------------------------------------------------- cavity (p13)
+
+def test_cavity_with_zero_coupling_reduces_to_plain_solver():
+    """eta = 0 and alpha_0 = 0: the cavity terms vanish and alpha stays 0, so psi is
+    identical to the cavity-free run; with alpha_0 != 0, alpha = alpha_0 e^{lambda t}."""
+    s = W.cavity_scaled(64, 0).with_(eta=0.0)
+    psi0 = W.gaussian(s, 1.2)
+    plain = s.with_(cavity=False)
+    a, _ = O.step_real(problem(s), state(s), psi0, 50)
+    b, _ = O.step_real(problem(plain), state(plain), psi0, 50)
+    assert np.array_equal(a, b)
+    s2 = s.with_(alpha0=0.3 - 0.2j)
+    st = state(s2)
+    _, obs = O.step_real(problem(s2), st, psi0, 50, want_obs=True)
+    lam = 1j * s.delta_c - s.kappa
+    t = s.dt * np.arange(1, 51)
+    ref = (0.3 - 0.2j) * np.exp(lam * t)
+    assert np.abs(obs[:, 2] + 1j * obs[:, 3] - ref).max() < 1e-13
+
+
+def test_cavity_field_with_frozen_overlap_has_closed_form():
+    """With Vc = 0 and no pump the potential ignores alpha; the real-time discrete
+    Gaussian is stationary in |psi|, so Theta is constant and alpha must follow
+    alpha(t) = e^{lambda t} alpha_0 + (e^{lambda t} - 1)/lambda (-i eta Theta),
+    tending to the adiabatic value eta Theta / (Delta_c + i kappa) (Sec. 5.3, Eq. 17)."""
+    dt = 0.01
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dt, g=0.0, cavity=True, vc=0.0, kc=0.7,
+                delta_c=-3.0, kappa=1.5, eta=2.0, alpha0=0.1 + 0.05j)
+    a = np.sqrt(1 - dt**2 / 4)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    psi0 = W.normalise(s, np.exp(-a * (x**2 + y**2) / 2).astype(complex))
+    th = O.theta(problem(s), psi0)
+    # closed form of Theta for the Gaussian: (1/(pi/a)) * (int cos(kx) e^{-a x^2})^2 -> exp(-k^2/(2a))
+    assert abs(th - np.exp(-0.7**2 / (2 * a))) < 1e-10
+    st = state(s)
+    _, obs = O.step_real(problem(s), st, psi0, 400, want_obs=True)
+    lam = 1j * s.delta_c - s.kappa
+    t = dt * np.arange(1, 401)
+    ref = np.exp(lam * t) * s.alpha0 + (np.exp(lam * t) - 1) / lam * (-1j * s.eta * th)
+    assert np.abs(obs[:, 2] + 1j * obs[:, 3] - ref).max() < 1e-10
+    assert abs(ref[-1] - s.eta * th / (s.delta_c + 1j * s.kappa)) < np.exp(-s.kappa * t[-1])
+
+
+# ------------------------------------------------------------ adjoint (p15)
+
+def _control_problem(nsteps=40, nknots=6, kx=2.0, n=32):
+    knots = np.random.Generator(np.random.PCG64(5)).uniform(0.0, 6.0, size=nknots)
+    dt = 0.01
+    s = W.Setup(nx=n, ny=n, lx=12.0, ly=12.0, dt=dt, g=20.0, kx_lat=kx,
+                sx=W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots))
+    return s
+
+
+@pytest.mark.parametrize("loss", ["fidelity", "energy"])
+def test_adjoint_matches_central_differences(loss):
+    nsteps = 40
+    s = _control_problem(nsteps)
+    psi0 = W.gaussian(s, 1.0, 0.3, 0.0)
+    target = W.gaussian(s, 0.9, -0.2, 0.1)
+    val, grad, _ = O.adjoint(problem(s), 0.0, psi0, target, nsteps, 0, loss)
+    h = 1e-4
+    fd = np.zeros_like(grad)
+    for m in range(grad.size):
+        for sgn in (1, -1):
+            k2 = s.sx.knots.copy()
+            k2[m] += sgn * h
+            s2 = s.with_(sx=W.Schedule("knots", t0=0.0, t1=s.sx.t1, knots=k2))
+            v2, _, _ = O.adjoint(problem(s2), 0.0, psi0, target, nsteps, 0, loss)
+            fd[m] += sgn * v2 / (2 * h)
+    assert np.abs(grad - fd).max() / np.abs(fd).max() < 1e-6
+
+
+def test_adjoint_is_independent_of_checkpoint_spacing_and_returns_forward_state():
+    nsteps = 30
+    s = _control_problem(nsteps)
+    psi0 = W.gaussian(s, 1.0, 0.3, 0.0)
+    target = W.gaussian(s, 0.9, -0.2, 0.1)
+    outs = [O.adjoint(problem(s), 0.0, psi0, target, nsteps, c) for c in (1, 5, 7, 30)]
+    for v, g, f in outs[1:]:
+        assert abs(v - outs[0][0]) < 1e-14 and np.abs(g - outs[0][1]).max() < 1e-12
+    fwd, _ = O.step_real(problem(s), state(s), psi0, nsteps)
+    assert np.array_equal(outs[0][2], fwd)
+
+
+def test_lattice_without_wavenumber_is_a_global_phase():
+    """k = 0 turns the lattice into V0(t) everywhere: a global phase, which the
+    fidelity cannot see, so every knot gradient vanishes."""
+    nsteps = 30
+    s = _control_problem(nsteps, kx=0.0)
+    psi0 = W.gaussian(s, 1.0, 0.3, 0.0)
+    target = W.gaussian(s, 0.9, -0.2, 0.1)
+    _, grad, _ = O.adjoint(problem(s), 0.0, psi0, target, nsteps)
+    assert np.abs(grad).max() < 1e-12
