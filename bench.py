@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the split-step GPE hot path on one MI355X.
+
+Workload: the self-consistent cavity run -- 1024x1024 grid on [-32, 32)^2, complex64
+state in HBM, harmonic trap w = 0.05, g = 1000, pump lattice Vp cos^2(y) with Vp = 3,
+cavity lattice Vc = 3, k = 1, Delta_c = -20, kappa = 10, eta from seed 0, dt = 2e-4.
+One step = one full symmetric split step (half kick, FFT2, kinetic factor, IFFT2,
+half kick; Sec. 3.1) with the fused overlap reduction Theta and the cavity-field update.
+The state is synthetic (a Thomas-Fermi-shaped start), already resident on the GPU.
+
+Prints ONE JSON line: grid-point-steps/s, the roofline of the dominant kernel (HIP
+events around sampled launches inside the timed region), and the FP64 oracle timed on
+a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+METRIC = "grid-point-steps/s (1024^2 c64) & %HBM roofline; batched + adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+B_PASS = 16  # algorithmic bytes per point per pass: one complex64 read + one write
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_engine.h", "physics.h", "gpe_internal.h"):
+        with open(os.path.join(HERE, "paper_2404_14401_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(HERE, "profiles", "traffic_cavity_1024.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(setup, psi0, budget_s: float):
+    sys.path.insert(0, HERE)
+    from oracle import oracle as O
+    from tests.bridge import problem, state
+
+    cores = O.set_threads(0)
+    prob, st = problem(setup), state(setup)
+    t = time.perf_counter()
+    psi, _ = O.step_real(prob, st, psi0, 1)
+    one = time.perf_counter() - t
+    n = max(2, int(budget_s / max(one, 1e-6)))
+    t = time.perf_counter()
+    O.step_real(prob, st, psi, n)
+    dt = time.perf_counter() - t
+    return {
+        "value": setup.nx * setup.ny * n / dt,
+        "unit": "grid-point-steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{n} real-time cavity steps at {setup.nx}x{setup.ny}, FP64 C oracle "
+                  f"(own radix-2 FFT, OpenMP over rows/columns), after 1 untimed step",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--timing-every", type=int, default=16,
+                    help="bracket every k-th step's passes with HIP events (roofline)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0: skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    setup = W.cavity_1024(seed=0)
+    npts = setup.nx * setup.ny
+    psi0 = W.to_c64(W.thomas_fermi_guess(setup, float(np.sqrt(setup.g / np.pi) * setup.wx)))
+    psi = torch.from_numpy(psi0).to("cuda")
+    plan = gpe.Plan.from_setup(setup)
+
+    plan.step_real(psi, args.warmup, 0.0)
+    plan.sync()
+    torch.cuda.synchronize()
+
+    plan.set_timing(args.timing_every)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    plan.step_real(psi, args.steps, args.warmup * setup.dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    plan.sync()
+    tim = plan.timing()
+    plan.set_timing(0)
+
+    value = npts * args.steps / (ms / 1e3)
+    passes = {"column_pass": tim["col_ms"], "row_pass_mid": tim["row_ms"]}
+    dom = max(passes, key=passes.get)
+    dom_ms = passes[dom]
+    achieved = B_PASS * npts / (dom_ms / 1e3) / 1e9
+    traffic = load_traffic(dom)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cavity-QED self-consistent real-time split step, 1024x1024 on [-32,32)^2, "
+                        "complex64 state, g=1000, trap w=0.05, Vp=Vc=3, k=1, Delta_c=-20, kappa=10, "
+                        "eta=5*U(seed 0), dt=2e-4",
+            "grid": [setup.ny, setup.nx],
+            "storage": "c64",
+            "arithmetic": "f64 registers",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": B_PASS * npts,
+            "launch_ms": dom_ms,
+            "launches_timed": tim["col_n"] if dom == "column_pass" else tim["row_n"],
+        },
+        "passes_ms": passes,
+        "step_roofline": {"b_alg_per_point_step": 2 * B_PASS,
+                          "frac": 2 * B_PASS * value / (HBM_PEAK_GBS * 1e9)},
+        "wall_s": wall,
+    }
+    if args.cpu_budget > 0:
+        log(f"timing the oracle for ~{args.cpu_budget:.0f} s ...")
+        out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

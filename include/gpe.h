@@ -1,0 +1,197 @@
+/*
+ * gpe.h -- C ABI of the MI355X (gfx950) split-step Gross-Pitaevskii library.
+ *
+ * The library advances a 2D condensate wave function psi(x, y) under
+ *   i d psi/dt = [ -1/2 laplacian + V(x, y, t; alpha) + g |psi|^2 ] psi
+ * (the GPE of arXiv:2404.14401, Sec. 2, Eq. 1, in the dimensionless oscillator
+ * units of Sec. 3.2: hbar = m = 1) with the symmetric split-step Fourier method
+ * (Sec. 3.1, Eqs. 3-4) in real time and in imaginary time (Sec. 3.3).  Each step is
+ *   psi' = psi  exp(-i [V(t_n) + g|psi|^2] dt/2)            half potential kick
+ *   psi* = IFFT2( exp(-i k^2 dt/2) FFT2(psi') )             kinetic propagation
+ *   psi_{n+1} = psi* exp(-i [V(t_{n+1}) + g|psi*|^2] dt/2)  half kick, newest density
+ * (imaginary time: the same with -i dt -> -dt and psi renormalised to unit norm after
+ * every step).  The potential is
+ *   V = 1/2 wx^2 (x-x0)^2 + 1/2 wy^2 (y-y0)^2                     trap (Sec. 5.1)
+ *     + Vx(t) cos^2(kx_lat x) + Vy(t) cos^2(ky_lat y)              lattices (Sec. 5.2, Eq. 12)
+ *     + Vc |alpha|^2 cos^2(kc x)
+ *     + 2 sqrt(Vy(t) Vc) Re(alpha) cos(kc x) cos(kc y)             cavity (Sec. 5.3, Eqs. 13-16)
+ *     + V_user(x, y)                                              optional static array
+ * and, with the cavity on, the field alpha obeys
+ *   d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta,  Theta = <psi| cos kc x cos kc y |psi>
+ * (the driven-damped form whose fixed point is Sec. 5.3, Eq. 17), advanced once per
+ * step by an exponential integrator with the forcing extrapolated to second order.
+ *
+ * Grid: x_i = -lx/2 + i lx/nx (i < nx), likewise y; psi is stored row-major
+ * [ny][nx] (x fastest) as interleaved (re, im) floats; periodic boundaries (the FFT
+ * imposes them, Sec. 3.1).  Norm: sum |psi|^2 dx dy.
+ *
+ * Conventions of every entry point:
+ *   - return 0 (GPE_OK) or a negative GPE_ERR_* code; no exception crosses the ABI;
+ *     gpe_last_error() gives a thread-local message for the last failure.
+ *   - argument errors are reported immediately; device-side failures (non-finite
+ *     values found by the fused reductions) are reported by the next synchronising
+ *     call (gpe_sync, gpe_energy, gpe_norm, gpe_get_cavity).
+ *   - device pointers are caller-owned and must stay valid until the work queued on
+ *     the plan's stream has finished; all work is queued on that stream.
+ *   - a plan or batch must not be used from two threads at once.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPE_OK 0
+#define GPE_ERR_INVALID (-1)     /* bad argument or plan state */
+#define GPE_ERR_NOMEM (-2)       /* device allocation failed or exceeds max_bytes */
+#define GPE_ERR_DEVICE (-3)      /* HIP runtime error */
+#define GPE_ERR_NONFINITE (-4)   /* NaN/Inf detected in psi by a fused reduction */
+#define GPE_ERR_UNSUPPORTED (-5) /* valid request this build does not implement */
+
+typedef struct gpe_plan gpe_plan;
+typedef struct gpe_batch gpe_batch;
+
+/* One complex64 grid value, interleaved (re, im). */
+typedef struct {
+    float re, im;
+} gpe_c64;
+
+/* Plan description.  nx, ny: powers of two in [16, 4096]; lx, ly > 0: box lengths;
+ * dt > 0: time step (imaginary time: dtau); g >= 0: interaction strength (already the
+ * effective 2D, norm-absorbing value, Sec. 3.2); stream: a hipStream_t, NULL for the
+ * null stream; max_bytes: cap on the plan's own device memory (0: none). */
+typedef struct {
+    int32_t nx, ny;
+    double lx, ly;
+    double dt;
+    double g;
+    void *stream;
+    size_t max_bytes;
+} gpe_plan_desc;
+
+/* Lattice depth versus time.  CONST: v0.  RAMP: v0 at t0 to v1 at t1, linear,
+ * clamped outside.  KNOTS: nknots >= 2 values spread evenly on [t0, t1], linear in
+ * between, clamped outside; the host array is copied when the descriptor is set. */
+#define GPE_SCHED_CONST 0
+#define GPE_SCHED_RAMP 1
+#define GPE_SCHED_KNOTS 2
+typedef struct {
+    int32_t kind;
+    int32_t nknots;
+    double v0, v1, t0, t1;
+    const double *knots;
+} gpe_schedule;
+
+/* Potential description (Sec. 5.1-5.3).  The pump lattice of the cavity model is the
+ * y lattice (depth Vy(t)); its interference term uses kc.  v_user: optional device
+ * float array [ny][nx], borrowed for as long as the plan uses it.  Setting a
+ * potential resets the cavity field to alpha0 and forgets the overlap history. */
+typedef struct {
+    double wx, wy, x0, y0;
+    double kx_lat, ky_lat;
+    gpe_schedule sx, sy;
+    int32_t cavity;
+    double vc, kc, delta_c, kappa, eta;
+    double alpha0_re, alpha0_im;
+    const float *v_user;
+} gpe_potential_desc;
+
+/* Per-step observables written by gpe_step_real / gpe_step_imag into a device array
+ * of nsteps records of GPE_NOBS doubles each, for the state after every step:
+ *   [0] norm (imaginary time: the norm before renormalisation, so that
+ *       -ln(norm) / (2 dtau) estimates mu), [1] Theta, [2] Re alpha, [3] Im alpha,
+ *   [4] integral x|psi|^2, [5] integral y|psi|^2. */
+#define GPE_NOBS 6
+
+/* Create a plan: allocates its tables and scratch once (the kernels allocate nothing
+ * per step).  The potential starts as a unit isotropic trap with no lattice. */
+int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *desc);
+int gpe_plan_destroy(gpe_plan *plan);
+
+/* Replace the potential (callable between steps, e.g. to displace the trap). */
+int gpe_set_potential(gpe_plan *plan, const gpe_potential_desc *pot);
+
+/* nsteps real-time split steps (Sec. 3.1) of psi in place, starting at time t0 (the
+ * lattice schedules are evaluated at t0 + n dt).  psi: device [ny][nx] gpe_c64.
+ * obs: device, nsteps * GPE_NOBS doubles, or NULL.  With the cavity on, the field
+ * and the overlap history carry over from the previous call on this plan. */
+int gpe_step_real(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t0, double *obs);
+
+/* nsteps imaginary-time steps (Sec. 3.3) with the potential frozen at time t and the
+ * cavity field held fixed; psi ends with unit norm.  obs as for gpe_step_real. */
+int gpe_step_imag(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t, double *obs);
+
+/* Energy functional of psi at time t with the plan's current cavity field
+ * (synchronous): out = {E_kin, E_pot, E_int, E, mu, norm}, each per unit norm,
+ * E_kin = sum_k |k|^2/2 |psi_k|^2 from the spectrum, E_int = g/2 int |psi|^4,
+ * mu = E_kin + E_pot + 2 E_int. */
+int gpe_energy(gpe_plan *plan, const gpe_c64 *psi, double t, double out[6]);
+
+/* sum |psi|^2 dx dy (synchronous). */
+int gpe_norm(gpe_plan *plan, const gpe_c64 *psi, double *out);
+
+/* Cavity state (synchronous): {Re alpha, Im alpha, Theta_n, Theta_{n-1}}; and its
+ * restore, for checkpoint/resume.  have_history = 0 makes the next real-time call
+ * start its overlap history from the current psi. */
+int gpe_get_cavity(gpe_plan *plan, double out[4]);
+int gpe_set_cavity(gpe_plan *plan, const double state[4], int have_history);
+
+/* Wait for the plan's stream; reports deferred device errors. */
+int gpe_sync(gpe_plan *plan);
+
+/* Instrumentation for roofline measurements.  gpe_set_timing(plan, every): when
+ * every > 0, gpe_step_real brackets the column pass and the middle row pass of every
+ * `every`-th step with HIP events on the plan's stream (every = 0 turns it off and
+ * clears the record).  gpe_get_timing (synchronous) returns
+ * {mean column-pass ms, column launches timed, mean row-pass ms, row launches timed}. */
+int gpe_set_timing(gpe_plan *plan, int every);
+int gpe_get_timing(gpe_plan *plan, double out[4]);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *gpe_last_error(void);
+
+/* ------------------------------------------------------------------ batched
+ * n independent condensates, each with its own plan description (sizes may differ;
+ * dt must be equal) and potential, advanced together: every step is one launch per
+ * FFT pass over all members (instances small enough to fit a work-group's LDS run
+ * their whole step in one work-group).  psis: host array of n device pointers.
+ * All members share the stream of desc[0]. */
+int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const gpe_potential_desc *pots);
+int gpe_batch_destroy(gpe_batch *b);
+int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double t0);
+
+/* ------------------------------------------------------------------ adjoint
+ * Gradient of a loss of psi(T), T = t0 + nsteps dt, with respect to the knot values
+ * of the x-lattice depth schedule (GPE_SCHED_KNOTS) of every member of a batch of
+ * real-time problems of one grid size (no cavity).  Losses:
+ *   GPE_LOSS_FIDELITY: L = 1 - |<target|psi(T)>|^2, <a|b> = sum conj(a) b dx dy;
+ *   GPE_LOSS_ENERGY:   L = E_kin + E_pot + E_int of psi(T) at time T.
+ * The reverse sweep rebuilds the forward states by running each step backwards
+ * (exact in real time) -- GPE_ADJ_RECONSTRUCT -- or from stored states every
+ * ~sqrt(nsteps) steps -- GPE_ADJ_CHECKPOINT; GPE_ADJ_AUTO reconstructs and falls
+ * back to checkpoints if the rebuilt psi(0) drifts from the input by more than
+ * drift_tol (relative L2).
+ * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each, target
+ * ignored for the energy loss); knots: host, nb * nknots values (they replace the
+ * members' x-lattice knots); loss: host, nb values; grad: host, nb * nknots values;
+ * psi_final (nullable): host array of nb device pointers receiving psi(T).
+ * info (nullable): host, 4 doubles {mode used (1 reconstruct, 2 checkpoint),
+ * reconstruction drift, peak scratch bytes, number of forward steps run}. */
+#define GPE_LOSS_FIDELITY 0
+#define GPE_LOSS_ENERGY 1
+#define GPE_ADJ_AUTO 0
+#define GPE_ADJ_RECONSTRUCT 1
+#define GPE_ADJ_CHECKPOINT 2
+int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *target, int64_t nsteps,
+                double t0, const double *knots, int nknots, int loss_kind, int mode, double drift_tol,
+                double *loss, double *grad, gpe_c64 *const *psi_final, double *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPE_H */

@@ -254,12 +254,14 @@ def energy(prob: Problem, psi, t: float = 0.0, alpha: complex = 0j) -> dict:
 
 def norm(prob: Problem, psi) -> float:
     p, keep = prob.cstruct()
-    return lib().orc_norm(C.byref(p), _c128(psi).ctypes.data)
+    a = _c128(psi)  # keep the (possibly converted) array alive across the call
+    return lib().orc_norm(C.byref(p), a.ctypes.data)
 
 
 def theta(prob: Problem, psi) -> float:
     p, keep = prob.cstruct()
-    return lib().orc_theta(C.byref(p), _c128(psi).ctypes.data)
+    a = _c128(psi)
+    return lib().orc_theta(C.byref(p), a.ctypes.data)
 
 
 def potential(prob: Problem, t: float = 0.0, alpha: complex = 0j) -> np.ndarray:

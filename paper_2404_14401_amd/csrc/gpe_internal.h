@@ -1,0 +1,114 @@
+// gpe_internal.h -- structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpe {
+
+// Lattice-depth schedule (device copy; knots in device memory).
+struct Sched {
+    int kind;  // 0 const, 1 ramp, 2 knots
+    int nknots;
+    double v0, v1, t0, t1;
+    const double *knots;
+};
+
+// Everything a kernel needs to evaluate V(x, y, t; alpha) (Sec. 5.1-5.3).
+// Per-axis tables hold {1/2 w^2 (x - x0)^2, cos^2(k_lat x), cos(kc x), x}.
+struct PotDev {
+    const float4 *tx;  // [nx]
+    const float4 *ty;  // [ny]
+    const float *vuser;  // [ny][nx] or null
+    Sched sx, sy;
+    int cavity;
+    double vc;
+    // cavity field step: alpha_{n+1} = ecav alpha_n + phi1 (-i eta Theta_bar)
+    double ecav_re, ecav_im, phi1_re, phi1_im, eta;
+};
+
+// Mutable device-side state of a plan (one per plan, in device memory).
+struct DevState {
+    double alpha_re, alpha_im;  // cavity field used by the next kick
+    double theta, theta_prev;   // Theta_n, Theta_{n-1}
+    double scale;               // imaginary time: pending 1/sqrt(norm)
+    double norm;                // last reduced norm
+    double t0;                  // time of the first step of the current call
+    int have_theta;
+    int nonfinite;
+};
+
+// Per-plan geometry and constant tables.
+struct GridDev {
+    int nx, ny;
+    double lx, ly, dx, dy, dA, dt, g;
+    const double2 *kin_x, *kin_y;    // real time: e^{-i kx^2 dt/2}, e^{-i ky^2 dt/2} / (nx ny)
+    const double *kim_x, *kim_y;     // imaginary time: e^{-kx^2 dt/2}, e^{-ky^2 dt/2} / (nx ny)
+    const double2 *tw_x, *tw_y;      // W_N^m, m < N, for the x and y transforms
+};
+
+constexpr int NPART = 4;  // norm, Theta, x moment, y moment (per work-group partials)
+constexpr int NOBS = 6;
+
+// Row-pass modes.
+enum RowMode : int {
+    ROW_ENTRY = 0,  // real-space psi -> (scale) -> half kick at t_n -> FFT_x
+    ROW_MID = 1,    // IFFT_x -> merged kick at t_{n+1} -> FFT_x (real time)
+    ROW_EXIT = 2,   // IFFT_x -> half kick at t_{n+1} -> real-space psi
+    ROW_FWD = 3,    // real-space psi -> FFT_x, energy partials (E_pot, E_int, norm)
+};
+
+// Column-pass modes.
+enum ColMode : int {
+    COL_KIN_REAL = 0,  // FFT_y -> e^{-i k^2 dt/2}/(nx ny) -> IFFT_y
+    COL_KIN_IMAG = 1,  // FFT_y -> e^{-k^2 dt/2}/(nx ny) -> IFFT_y
+    COL_EKIN = 2,      // FFT_y -> partials of sum k^2/2 |psi_k|^2 (no store)
+};
+
+struct RowArgs {
+    const float2 *src;
+    float2 *dst;
+    GridDev grid;
+    PotDev pot;
+    DevState *st;
+    double *partials;  // [gridDim.x][NPART]
+    int n;             // step index within the call; kick time = st->t0 + (n or n+1) dt
+    int reduce;        // write partials
+    int lines_per_wg;
+};
+
+// Work done by work-group 0 of a column pass before its own columns: reduce the
+// previous row pass's partials, record observables, advance the cavity field.
+struct TailArgs {
+    const double *partials;
+    int npartials;     // 0: nothing to reduce
+    int first_theta;   // the reduced Theta starts the overlap history
+    double *obs;       // record slot (NOBS doubles) or null
+    int imag;          // imaginary-time bookkeeping (scale, pre-normalisation norm)
+    int advance_alpha; // compute alpha_{n+1} after the reduction
+};
+
+struct ColArgs {
+    const float2 *src;
+    float2 *dst;
+    GridDev grid;
+    DevState *st;
+    double *partials;
+    int cols_per_wg;
+    int reduce;
+    PotDev pot;
+    TailArgs tail;
+    int do_tail;
+};
+
+// Whole grid resident in one work-group's LDS (small grids).
+struct LdsArgs {
+    float2 *psi;  // in/out real space, [ny][nx]
+    GridDev grid;
+    PotDev pot;
+    DevState *st;
+    double *obs;  // [nsteps][NOBS] or null
+    int nsteps;
+    int imag;
+};
+
+}  // namespace gpe

@@ -1,0 +1,564 @@
+// kernels.hip -- gfx950 kernels of the split-step GPE path and their launchers.
+//
+// Multi-pass path (any size): a step is a row pass and a column pass over the caller's
+// complex64 array, updated in place.  Between passes the array holds the x-transformed
+// field; only the first and last pass of a call see real space.
+//   row entry : psi -> half kick at t_n -> FFT_x                         (Sec. 3.1, Eq. 4)
+//   column    : FFT_y -> kinetic factor e^{-i k^2 dt/2}/(NxNy) -> IFFT_y  (Sec. 3.1)
+//   row mid   : IFFT_x -> the two half kicks of t_{n+1} merged -> FFT_x  (real time: a
+//               phase kick leaves |psi| unchanged, so the second half kick of step n and
+//               the first of step n+1 see the same density; Sec. 3.1 "most recent psi")
+//   row exit  : IFFT_x -> half kick at t_{n+1} -> psi
+// Imaginary time (Sec. 3.3) cannot merge the kicks (the renormalisation sits between
+// them), so each step is entry, column, exit, plus a one-work-group reduction.
+// Reductions (norm, cavity overlap Theta, moments) are fused into the row passes as
+// per-work-group partials, reduced in a fixed order by work-group 0 of the next column
+// pass (or by the tail kernel), which also advances the cavity field.
+//
+// LDS path (nx ny <= 16384): the whole grid stays in one work-group's LDS for all steps.
+#include "fft_engine.h"
+#include "physics.h"
+
+namespace gpe {
+
+constexpr int kRadix = 8;
+constexpr int kLgR = 3;
+
+// --------------------------------------------------------------------- row pass
+template <int N, int MODE, bool IMAG>
+__global__ void __launch_bounds__(512) row_pass(RowArgs a)
+{
+    using C = double2;
+    constexpr int R = kRadix;
+    constexpr int T = N / R;
+    using View = LinePad<double2, kLgR>;
+    extern __shared__ double2 smem[];
+    __shared__ double red[8 * NPART];
+
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int row = blockIdx.x * a.lines_per_wg + line;
+    const GridDev &gd = a.grid;
+    View lds{smem + line * View::words(N)};
+    const float2 *src = a.src + (size_t)row * N;
+    float2 *dst = a.dst + (size_t)row * N;
+
+    C v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        float2 f = src[t + m * T];
+        v[m] = {(double)f.x, (double)f.y};
+    }
+
+    // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes V
+    double tk = a.st->t0;
+    if (!IMAG) tk += (MODE == ROW_ENTRY ? a.n : a.n + 1) * gd.dt;
+    const double are = a.st->alpha_re, aim = a.st->alpha_im;
+    const VLine vl = vline_cav(a.pot, row, tk, are, aim);
+    const float4 ty = a.pot.ty[row];
+    const double cy = ty.z, yv = ty.w;
+    const float *vu = a.pot.vuser ? a.pot.vuser + (size_t)row * N : nullptr;
+
+    if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, gd.tw_x);
+
+    double part[NPART] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (MODE == ROW_ENTRY && IMAG) {
+        const double sc = a.st->scale;
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = {v[m].x * sc, v[m].y * sc};
+    }
+    const double hk = (MODE == ROW_MID) ? gd.dt : 0.5 * gd.dt;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int i = t + m * T;
+        const float4 tx = a.pot.tx[i];
+        double V = vpoint(vl, tx);
+        if (vu) V += (double)vu[i];
+        const double d = v[m].x * v[m].x + v[m].y * v[m].y;
+        if constexpr (MODE == ROW_FWD) {
+            part[0] += d;
+            part[1] += V * d;
+            part[2] += d * d;
+        } else {
+            const double th = (V + gd.g * d) * hk;
+            if constexpr (IMAG) {
+                v[m] = kick_imag(v[m], th);
+                if (MODE == ROW_EXIT) {
+                    const double d2 = v[m].x * v[m].x + v[m].y * v[m].y;
+                    part[0] += d2;
+                    part[1] += (double)tx.z * cy * d2;
+                    part[2] += (double)tx.w * d2;
+                    part[3] += yv * d2;
+                }
+            } else {
+                // |psi| is the same before and after a phase kick
+                part[0] += d;
+                part[1] += (double)tx.z * cy * d;
+                part[2] += (double)tx.w * d;
+                part[3] += yv * d;
+                v[m] = kick_real(v[m], th);
+            }
+        }
+    }
+    if (a.reduce) {
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) a.partials[blockIdx.x * NPART + k] = part[k];
+    }
+
+    if constexpr (MODE != ROW_EXIT) fft_line<N, R, false>(v, lds, t, gd.tw_x);
+
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[t + m * T] = make_float2((float)v[m].x, (float)v[m].y);
+}
+
+// ------------------------------------------------------------------ column pass
+template <int N, int MODE>
+__global__ void __launch_bounds__(1024) col_pass(ColArgs a)
+{
+    using C = double2;
+    constexpr int R = kRadix;
+    constexpr int T = N / R;
+    using View = LineTile<double2, kLgR>;
+    extern __shared__ double2 smem[];
+    __shared__ double red[16 * NPART];
+
+    const GridDev &gd = a.grid;
+    if (a.do_tail && blockIdx.x == 0) run_tail(a.tail, gd, a.pot, a.st, red);
+
+    const int w = a.cols_per_wg;
+    const int c = threadIdx.x % w, t = threadIdx.x / w;
+    const int col = blockIdx.x * w + c;
+    const int nx = gd.nx;
+    View lds{smem + c, w};
+
+    C v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        float2 f = a.src[(size_t)(t + m * T) * nx + col];
+        v[m] = {(double)f.x, (double)f.y};
+    }
+    fft_line<N, R, false>(v, lds, t, gd.tw_y);
+    if constexpr (MODE == COL_EKIN) {
+        const int ix = col >= nx / 2 ? col - nx : col;
+        const double kx = 2.0 * M_PI * ix / gd.lx;
+        double part[NPART] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int j = t + m * T;
+            const int iy = j >= N / 2 ? j - N : j;
+            const double ky = 2.0 * M_PI * iy / gd.ly;
+            part[0] += 0.5 * (kx * kx + ky * ky) * (v[m].x * v[m].x + v[m].y * v[m].y);
+        }
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0) a.partials[blockIdx.x * NPART] = part[0];
+        return;
+    } else {
+        if constexpr (MODE == COL_KIN_REAL) {
+            const C kx = gd.kin_x[col];
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kin_y[t + m * T]));
+        } else {
+            const double kx = gd.kim_x[col];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const double f = kx * gd.kim_y[t + m * T];
+                v[m] = {v[m].x * f, v[m].y * f};
+            }
+        }
+        fft_line<N, R, true>(v, lds, t, gd.tw_y);
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            a.dst[(size_t)(t + m * T) * nx + col] = make_float2((float)v[m].x, (float)v[m].y);
+    }
+}
+
+// --------------------------------------------------------------- small kernels
+__global__ void __launch_bounds__(256) tail_kernel(TailArgs ta, GridDev gd, PotDev pot, DevState *st)
+{
+    __shared__ double red[4 * NPART];
+    run_tail(ta, gd, pot, st, red);
+}
+
+// psi <- psi * st->scale (final renormalisation in imaginary time)
+__global__ void __launch_bounds__(256) scale_kernel(float2 *psi, size_t n, const DevState *st)
+{
+    const double sc = st->scale;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float2 p = psi[i];
+        psi[i] = make_float2((float)(p.x * sc), (float)(p.y * sc));
+    }
+}
+
+// Start of a call: record its first time; imaginary time starts unscaled.
+__global__ void set_call_kernel(DevState *st, double t0, int reset_scale, int clear_history)
+{
+    if (threadIdx.x == 0) {
+        st->t0 = t0;
+        if (reset_scale) st->scale = 1.0;
+        if (clear_history) st->have_theta = 0;
+    }
+}
+
+// sum |psi|^2 per work-group (norm)
+__global__ void __launch_bounds__(256) norm_kernel(const float2 *psi, size_t n, double *partials)
+{
+    __shared__ double red[4 * 1];
+    double s[1] = {0.0};
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float2 p = psi[i];
+        s[0] += (double)p.x * p.x + (double)p.y * p.y;
+    }
+    block_sum<1>(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// ------------------------------------------------------------- whole grid in LDS
+// One work-group owns one grid for all steps; psi stays in LDS as complex64 (row pitch
+// NX + 1), each transform line is lifted to double registers.  Steps follow the
+// definition literally: half kick, FFT2, kinetic factor, IFFT2, half kick, then the
+// reductions (imaginary time: renormalise; cavity: overlap and field update).  The
+// launch uses exactly NX*NY/8 threads (at most 1024), so every thread owns a slice of
+// a line in both the row and the column sweeps.
+template <int NX, int NY>
+__global__ void __launch_bounds__((NX * NY / kRadix) < 1024 ? NX * NY / kRadix : 1024) lds_grid(LdsArgs a)
+{
+    using C = double2;
+    constexpr int R = kRadix;
+    constexpr int TX = NX / R, TY = NY / R;
+    constexpr int P = NX + 1;
+    constexpr int NTH = (NX * NY / R) < 1024 ? NX * NY / R : 1024;
+    constexpr int LR = NTH / TX, LC = NTH / TY;  // lines per sweep
+    static_assert(LR <= NY && LC <= NX && NY % LR == 0 && NX % LC == 0, "sweep shape");
+    extern __shared__ float2 g[];
+    __shared__ double red[16 * NPART];
+    __shared__ double bc[NPART];
+    __shared__ double s_scale, s_are, s_aim, s_th, s_thp;
+
+    const GridDev &gd = a.grid;
+    const PotDev &pot = a.pot;
+    DevState *st = a.st;
+    const int rl = threadIdx.x % LR, rt = threadIdx.x / LR;
+    const int cl = threadIdx.x % LC, ct = threadIdx.x / LC;
+    const bool cav = pot.cavity && !a.imag;
+    const bool want = cav || a.obs != nullptr || a.imag;
+    const double t0 = st->t0;
+
+    for (int i = threadIdx.x; i < NX * NY; i += NTH) g[(i / NX) * P + (i % NX)] = a.psi[i];
+    if (threadIdx.x == 0) {
+        s_scale = 1.0;
+        s_are = st->alpha_re;
+        s_aim = st->alpha_im;
+        s_th = st->theta;
+        s_thp = st->theta_prev;
+    }
+    __syncthreads();
+
+    // sum NPART per-thread values over the work-group, times dA, broadcast to all
+    auto reduce_all = [&](double (&part)[NPART]) {
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < NPART; ++k) bc[k] = part[k] * gd.dA;
+        __syncthreads();
+        for (int k = 0; k < NPART; ++k) part[k] = bc[k];
+        __syncthreads();
+    };
+    // one half kick over the grid (optionally scaling first and reducing after)
+    auto kick_rows = [&](double tk, double are, double aim, double sc, bool reduce, double (&part)[NPART]) {
+        for (int r0 = 0; r0 < NY; r0 += LR) {
+            const int row = r0 + rl;
+            const VLine vl = vline_cav(pot, row, tk, are, aim);
+            const float4 ty = pot.ty[row];
+            for (int m = 0; m < R; ++m) {
+                const int i = rt + m * TX;
+                const float4 tx = pot.tx[i];
+                float2 f = g[row * P + i];
+                C p = {(double)f.x * sc, (double)f.y * sc};
+                double V = vpoint(vl, tx);
+                if (pot.vuser) V += (double)pot.vuser[row * NX + i];
+                const double th = (V + gd.g * (p.x * p.x + p.y * p.y)) * (0.5 * gd.dt);
+                p = a.imag ? kick_imag(p, th) : kick_real(p, th);
+                if (reduce) {
+                    const double d2 = p.x * p.x + p.y * p.y;
+                    part[0] += d2;
+                    part[1] += (double)tx.z * (double)ty.z * d2;
+                    part[2] += (double)tx.w * d2;
+                    part[3] += (double)ty.w * d2;
+                }
+                g[row * P + i] = make_float2((float)p.x, (float)p.y);
+            }
+        }
+    };
+    auto rows_fft = [&](auto inv_tag) {
+        constexpr bool INV = decltype(inv_tag)::value;
+        for (int r0 = 0; r0 < NY; r0 += LR) {
+            LineStride<float2> view{g + (r0 + rl) * P, 1};
+            C v[R];
+            for (int m = 0; m < R; ++m) v[m] = view.template ld<C>(rt + m * TX);
+            fft_line<NX, R, INV>(v, view, rt, gd.tw_x);
+            __syncthreads();
+            for (int m = 0; m < R; ++m) view.st(rt + m * TX, v[m]);
+            __syncthreads();
+        }
+    };
+    auto cols_kin = [&]() {
+        for (int c0 = 0; c0 < NX; c0 += LC) {
+            const int col = c0 + cl;
+            LineStride<float2> view{g + col, P};
+            C v[R];
+            for (int m = 0; m < R; ++m) v[m] = view.template ld<C>(ct + m * TY);
+            fft_line<NY, R, false>(v, view, ct, gd.tw_y);
+            if (!a.imag) {
+                const C kx = gd.kin_x[col];
+                for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kin_y[ct + m * TY]));
+            } else {
+                const double kx = gd.kim_x[col];
+                for (int m = 0; m < R; ++m) {
+                    const double f = kx * gd.kim_y[ct + m * TY];
+                    v[m] = {v[m].x * f, v[m].y * f};
+                }
+            }
+            fft_line<NY, R, true>(v, view, ct, gd.tw_y);
+            __syncthreads();
+            for (int m = 0; m < R; ++m) view.st(ct + m * TY, v[m]);
+            __syncthreads();
+        }
+    };
+
+    if (cav && !st->have_theta) {
+        // Theta_0 starts the overlap history
+        double part[NPART] = {0, 0, 0, 0};
+        for (int r0 = 0; r0 < NY; r0 += LR) {
+            const int row = r0 + rl;
+            const double cy = pot.ty[row].z;
+            for (int m = 0; m < R; ++m) {
+                const int i = rt + m * TX;
+                float2 f = g[row * P + i];
+                part[1] += (double)pot.tx[i].z * cy * ((double)f.x * f.x + (double)f.y * f.y);
+            }
+        }
+        reduce_all(part);
+        if (threadIdx.x == 0) {
+            s_th = part[1];
+            s_thp = part[1];
+        }
+        __syncthreads();
+    }
+
+    for (int n = 0; n < a.nsteps; ++n) {
+        const double tn = a.imag ? t0 : t0 + n * gd.dt;
+        const double tn1 = a.imag ? t0 : t0 + (n + 1) * gd.dt;
+        const double are0 = s_are, aim0 = s_aim, sc = s_scale;
+        __syncthreads();
+        if (cav && threadIdx.x == 0) {
+            // alpha_{n+1} = e^{lambda dt} alpha_n + phi1 (-i eta (3 Theta_n - Theta_{n-1}) / 2)
+            const double tb = 0.5 * (3.0 * s_th - s_thp);
+            const double fi = -pot.eta * tb;
+            const double nr = pot.ecav_re * are0 - pot.ecav_im * aim0 - pot.phi1_im * fi;
+            const double ni = pot.ecav_re * aim0 + pot.ecav_im * are0 + pot.phi1_re * fi;
+            s_are = nr;
+            s_aim = ni;
+        }
+        double part[NPART] = {0, 0, 0, 0};
+        kick_rows(tn, are0, aim0, sc, false, part);
+        __syncthreads();
+        rows_fft(std::integral_constant<bool, false>{});
+        cols_kin();
+        rows_fft(std::integral_constant<bool, true>{});
+        kick_rows(tn1, s_are, s_aim, 1.0, want, part);
+        __syncthreads();
+        if (want) {
+            reduce_all(part);
+            if (threadIdx.x == 0) {
+                const double norm = part[0];
+                if (!isfinite(norm)) st->nonfinite = 1;
+                double *o = a.obs ? a.obs + (size_t)n * NOBS : nullptr;
+                const double inv = a.imag ? 1.0 / norm : 1.0;
+                if (a.imag) s_scale = sqrt(inv);
+                if (cav) {
+                    s_thp = s_th;
+                    s_th = part[1];
+                }
+                if (o) {
+                    o[0] = norm;
+                    o[1] = part[1] * inv;
+                    o[2] = s_are;
+                    o[3] = s_aim;
+                    o[4] = part[2] * inv;
+                    o[5] = part[3] * inv;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const double sc = s_scale;
+    for (int i = threadIdx.x; i < NX * NY; i += NTH) {
+        float2 f = g[(i / NX) * P + (i % NX)];
+        a.psi[i] = make_float2((float)(f.x * sc), (float)(f.y * sc));
+    }
+    if (threadIdx.x == 0) {
+        st->alpha_re = s_are;
+        st->alpha_im = s_aim;
+        if (cav) {
+            st->theta = s_th;
+            st->theta_prev = s_thp;
+            st->have_theta = 1;
+        }
+        st->scale = 1.0;
+    }
+}
+
+// ------------------------------------------------------------------- launchers
+template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowArgs &a, int blocks, int threads,
+                                                size_t shmem, hipStream_t s)
+{
+#define GPE_ROW(M, I)                                                                              \
+    do {                                                                                           \
+        static bool attr_ = false;                                                                 \
+        if (!attr_) {                                                                              \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass<N, M, I>,                   \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
+            if (e_ != hipSuccess) return e_;                                                       \
+            attr_ = true;                                                                          \
+        }                                                                                          \
+        hipLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), shmem, s, a);         \
+    } while (0)
+    if (imag) {
+        if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, true);
+        else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, true);
+        else return hipErrorInvalidValue;
+    } else {
+        if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, false);
+        else if (mode == ROW_MID) GPE_ROW(ROW_MID, false);
+        else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, false);
+        else if (mode == ROW_FWD) GPE_ROW(ROW_FWD, false);
+        else return hipErrorInvalidValue;
+    }
+#undef GPE_ROW
+    return hipGetLastError();
+}
+
+hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
+                      hipStream_t s)
+{
+    switch (n) {
+    case 16: return row_dispatch<16>(mode, imag, a, blocks, threads, shmem, s);
+    case 32: return row_dispatch<32>(mode, imag, a, blocks, threads, shmem, s);
+    case 64: return row_dispatch<64>(mode, imag, a, blocks, threads, shmem, s);
+    case 128: return row_dispatch<128>(mode, imag, a, blocks, threads, shmem, s);
+    case 256: return row_dispatch<256>(mode, imag, a, blocks, threads, shmem, s);
+    case 512: return row_dispatch<512>(mode, imag, a, blocks, threads, shmem, s);
+    case 1024: return row_dispatch<1024>(mode, imag, a, blocks, threads, shmem, s);
+    case 2048: return row_dispatch<2048>(mode, imag, a, blocks, threads, shmem, s);
+    case 4096: return row_dispatch<4096>(mode, imag, a, blocks, threads, shmem, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int blocks, int threads, size_t shmem,
+                                                hipStream_t s)
+{
+#define GPE_COL(M)                                                                                 \
+    do {                                                                                           \
+        static bool attr_ = false;                                                                 \
+        if (!attr_) {                                                                              \
+            hipError_t e_ = hipFuncSetAttribute((const void *)col_pass<N, M>,                      \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
+            if (e_ != hipSuccess) return e_;                                                       \
+            attr_ = true;                                                                          \
+        }                                                                                          \
+        hipLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), shmem, s, a);            \
+    } while (0)
+    if (mode == COL_KIN_REAL) GPE_COL(COL_KIN_REAL);
+    else if (mode == COL_KIN_IMAG) GPE_COL(COL_KIN_IMAG);
+    else if (mode == COL_EKIN) GPE_COL(COL_EKIN);
+    else return hipErrorInvalidValue;
+#undef GPE_COL
+    return hipGetLastError();
+}
+
+hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
+{
+    switch (n) {
+    case 16: return col_dispatch<16>(mode, a, blocks, threads, shmem, s);
+    case 32: return col_dispatch<32>(mode, a, blocks, threads, shmem, s);
+    case 64: return col_dispatch<64>(mode, a, blocks, threads, shmem, s);
+    case 128: return col_dispatch<128>(mode, a, blocks, threads, shmem, s);
+    case 256: return col_dispatch<256>(mode, a, blocks, threads, shmem, s);
+    case 512: return col_dispatch<512>(mode, a, blocks, threads, shmem, s);
+    case 1024: return col_dispatch<1024>(mode, a, blocks, threads, shmem, s);
+    case 2048: return col_dispatch<2048>(mode, a, blocks, threads, shmem, s);
+    case 4096: return col_dispatch<4096>(mode, a, blocks, threads, shmem, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(256), 0, s, ta, gd, pot, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(256), 0, s, psi, n, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_call_kernel, dim3(1), dim3(64), 0, s, st, t0, reset_scale, clear_history);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(norm_kernel, dim3(blocks), dim3(256), 0, s, psi, n, partials);
+    return hipGetLastError();
+}
+
+template <int NX, int NY> static hipError_t lds_launch(const LdsArgs &a, int threads, hipStream_t s)
+{
+    const size_t shmem = (size_t)(NX + 1) * NY * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void *)lds_grid<NX, NY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lds_grid<NX, NY>), dim3(1), dim3(threads), shmem, s, a);
+    return hipGetLastError();
+}
+
+bool lds_supported(int nx, int ny)
+{
+    return nx >= 16 && ny >= 16 && nx <= 128 && ny <= 128 && (size_t)(nx + 1) * ny * 8 <= 160 * 1024;
+}
+
+int lds_threads(int nx, int ny)
+{
+    const int n = nx * ny / kRadix;
+    return n < 1024 ? n : 1024;
+}
+
+hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s)
+{
+    const int nx = a.grid.nx, ny = a.grid.ny, th = lds_threads(nx, ny);
+#define GPE_LDS_Y(X)                                              \
+    switch (ny) {                                                 \
+    case 16: return lds_launch<X, 16>(a, th, s);                  \
+    case 32: return lds_launch<X, 32>(a, th, s);                  \
+    case 64: return lds_launch<X, 64>(a, th, s);                  \
+    case 128: return lds_launch<X, 128>(a, th, s);                \
+    default: return hipErrorInvalidValue;                         \
+    }
+    switch (nx) {
+    case 16: GPE_LDS_Y(16)
+    case 32: GPE_LDS_Y(32)
+    case 64: GPE_LDS_Y(64)
+    case 128: GPE_LDS_Y(128)
+    default: return hipErrorInvalidValue;
+    }
+#undef GPE_LDS_Y
+}
+
+}  // namespace gpe

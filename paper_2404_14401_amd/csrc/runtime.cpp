@@ -1,0 +1,588 @@
+// runtime.cpp -- host side of the C ABI declared in include/gpe.h: plans, tables,
+// launch sequences, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gpe.h"
+#include "gpe_internal.h"
+
+namespace gpe {
+hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
+                      hipStream_t s);
+hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
+hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
+hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
+hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s);
+hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s);
+bool lds_supported(int nx, int ny);
+int lds_threads(int nx, int ny);
+}  // namespace gpe
+
+using namespace gpe;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// Launch shape of the multi-pass path.
+struct Shape {
+    int row_lines, row_threads, row_blocks;
+    size_t row_shmem;
+    int col_cols, col_threads, col_blocks;
+    size_t col_shmem;
+};
+
+struct gpe_plan {
+    int nx = 0, ny = 0;
+    double lx = 0, ly = 0, dt = 0, g = 0;
+    hipStream_t stream = nullptr;
+    size_t max_bytes = 0, bytes = 0;
+    int path = 0;  // 0 auto, 1 multi-pass, 2 LDS
+    std::vector<void *> allocs;
+    DevState *st = nullptr;
+    float4 *tx = nullptr, *ty = nullptr;
+    double2 *kin_x = nullptr, *kin_y = nullptr, *tw_x = nullptr, *tw_y = nullptr;
+    double *kim_x = nullptr, *kim_y = nullptr;
+    double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
+    int npart_max = 0;
+    float2 *scratch = nullptr;
+    double *knots_x = nullptr, *knots_y = nullptr;
+    int knots_cap_x = 0, knots_cap_y = 0;
+    GridDev grid{};
+    PotDev pot{};
+    Shape shape{};
+    bool have_theta = false;
+    // pass timing (instrumentation)
+    int timing_every = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pairs;  // (kind 0 col / 1 row, index of start event)
+};
+
+static hipEvent_t *timing_pair(gpe_plan *p, int kind)
+{
+    if (p->ev_used + 2 > p->ev_pool.size()) return nullptr;
+    p->ev_pairs.push_back({kind, p->ev_used});
+    hipEvent_t *e = &p->ev_pool[p->ev_used];
+    p->ev_used += 2;
+    return e;
+}
+
+static int dalloc(gpe_plan *p, void **ptr, size_t bytes)
+{
+    if (p->max_bytes && p->bytes + bytes > p->max_bytes)
+        return fail(GPE_ERR_NOMEM, "plan memory cap exceeded");
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->allocs.push_back(*ptr);
+    p->bytes += bytes;
+    return GPE_OK;
+}
+
+template <typename T> static int upload(gpe_plan *p, T **dst, const std::vector<T> &src)
+{
+    int rc = dalloc(p, (void **)dst, src.size() * sizeof(T));
+    if (rc) return rc;
+    HIP_OK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return GPE_OK;
+}
+
+static double kval(int j, int n, double len) { return 2.0 * M_PI * (j >= n / 2 ? j - n : j) / len; }
+
+static Shape make_shape(int nx, int ny)
+{
+    Shape s{};
+    const int R = 8;
+    const int tr = nx / R;
+    s.row_lines = std::max(1, 256 / tr);
+    if (s.row_lines > ny) s.row_lines = ny;
+    s.row_threads = s.row_lines * tr;
+    s.row_blocks = ny / s.row_lines;
+    s.row_shmem = (size_t)s.row_lines * (nx + nx / 8) * sizeof(double2);
+    const int tc = ny / R;
+    s.col_cols = std::max(1, std::min(nx, 512 / tc));
+    s.col_threads = s.col_cols * tc;
+    s.col_blocks = nx / s.col_cols;
+    s.col_shmem = ((size_t)ny * s.col_cols + ny / 8 + s.col_cols) * sizeof(double2);
+    return s;
+}
+
+static Sched to_sched(const gpe_schedule &s, const double *dev_knots)
+{
+    Sched d{};
+    d.kind = s.kind;
+    d.nknots = s.nknots;
+    d.v0 = s.v0;
+    d.v1 = s.v1;
+    d.t0 = s.t0;
+    d.t1 = s.t1;
+    d.knots = dev_knots;
+    return d;
+}
+
+static int check_sched(const gpe_schedule &s, const char *name)
+{
+    if (s.kind < 0 || s.kind > 2) return fail(GPE_ERR_INVALID, std::string(name) + ": unknown schedule kind");
+    if (s.kind == GPE_SCHED_RAMP && !(s.t1 > s.t0)) return fail(GPE_ERR_INVALID, std::string(name) + ": ramp needs t1 > t0");
+    if (s.kind == GPE_SCHED_KNOTS && (s.nknots < 2 || !s.knots || !(s.t1 > s.t0)))
+        return fail(GPE_ERR_INVALID, std::string(name) + ": knots need nknots >= 2, a host array and t1 > t0");
+    return GPE_OK;
+}
+
+static int upload_knots(gpe_plan *p, const gpe_schedule &s, double **dev, int *cap)
+{
+    if (s.kind != GPE_SCHED_KNOTS) return GPE_OK;
+    if (s.nknots > *cap) {
+        int rc = dalloc(p, (void **)dev, sizeof(double) * (size_t)s.nknots);
+        if (rc) return rc;
+        *cap = s.nknots;
+    }
+    HIP_OK(hipMemcpy(*dev, s.knots, sizeof(double) * (size_t)s.nknots, hipMemcpyHostToDevice));
+    return GPE_OK;
+}
+
+extern "C" {
+
+const char *gpe_last_error(void) { return g_err.c_str(); }
+
+int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
+{
+    if (!p || !v) return fail(GPE_ERR_INVALID, "null plan or potential");
+    int rc = check_sched(v->sx, "sx");
+    if (rc) return rc;
+    if ((rc = check_sched(v->sy, "sy"))) return rc;
+    if (v->cavity && v->vc < 0) return fail(GPE_ERR_INVALID, "cavity: vc must be >= 0");
+    HIP_OK(hipStreamSynchronize(p->stream));
+    const int nx = p->nx, ny = p->ny;
+    std::vector<float4> tx(nx), ty(ny);
+    for (int i = 0; i < nx; ++i) {
+        const double x = -0.5 * p->lx + i * (p->lx / nx);
+        const double c = std::cos(v->kx_lat * x);
+        tx[i] = make_float4((float)(0.5 * v->wx * v->wx * (x - v->x0) * (x - v->x0)), (float)(c * c),
+                            (float)std::cos(v->kc * x), (float)x);
+    }
+    for (int j = 0; j < ny; ++j) {
+        const double y = -0.5 * p->ly + j * (p->ly / ny);
+        const double c = std::cos(v->ky_lat * y);
+        ty[j] = make_float4((float)(0.5 * v->wy * v->wy * (y - v->y0) * (y - v->y0)), (float)(c * c),
+                            (float)std::cos(v->kc * y), (float)y);
+    }
+    HIP_OK(hipMemcpy(p->tx, tx.data(), sizeof(float4) * nx, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->ty, ty.data(), sizeof(float4) * ny, hipMemcpyHostToDevice));
+    if ((rc = upload_knots(p, v->sx, &p->knots_x, &p->knots_cap_x))) return rc;
+    if ((rc = upload_knots(p, v->sy, &p->knots_y, &p->knots_cap_y))) return rc;
+    PotDev &d = p->pot;
+    d.tx = p->tx;
+    d.ty = p->ty;
+    d.vuser = v->v_user;
+    d.sx = to_sched(v->sx, p->knots_x);
+    d.sy = to_sched(v->sy, p->knots_y);
+    d.cavity = v->cavity ? 1 : 0;
+    d.vc = v->vc;
+    d.eta = v->eta;
+    const std::complex<double> lam(-v->kappa, v->delta_c);
+    const std::complex<double> e = std::exp(lam * p->dt);
+    const std::complex<double> phi1 = std::abs(lam) > 0 ? (e - 1.0) / lam : std::complex<double>(p->dt, 0.0);
+    d.ecav_re = e.real();
+    d.ecav_im = e.imag();
+    d.phi1_re = phi1.real();
+    d.phi1_im = phi1.imag();
+    DevState st{};
+    st.alpha_re = v->alpha0_re;
+    st.alpha_im = v->alpha0_im;
+    st.scale = 1.0;
+    HIP_OK(hipMemcpy(p->st, &st, sizeof(st), hipMemcpyHostToDevice));
+    p->have_theta = false;
+    return GPE_OK;
+}
+
+int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
+{
+    if (!out || !d) return fail(GPE_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (!pow2_in(d->nx, 16, 4096) || !pow2_in(d->ny, 16, 4096))
+        return fail(GPE_ERR_INVALID, "nx, ny must be powers of two in [16, 4096]");
+    if (!(d->lx > 0) || !(d->ly > 0) || !(d->dt > 0) || !(d->g >= 0) || !std::isfinite(d->dt) ||
+        !std::isfinite(d->g))
+        return fail(GPE_ERR_INVALID, "need lx, ly, dt > 0 and g >= 0, all finite");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GPE_ERR_DEVICE, "no HIP device");
+    gpe_plan *p = new gpe_plan();
+    p->nx = d->nx;
+    p->ny = d->ny;
+    p->lx = d->lx;
+    p->ly = d->ly;
+    p->dt = d->dt;
+    p->g = d->g;
+    p->stream = (hipStream_t)d->stream;
+    p->max_bytes = d->max_bytes;
+    const char *force = getenv("GPE_PATH");
+    if (force && !strcmp(force, "multipass")) p->path = 1;
+    if (force && !strcmp(force, "lds")) p->path = 2;
+    const int nx = d->nx, ny = d->ny;
+    p->shape = make_shape(nx, ny);
+    int rc = 0;
+    auto cleanup = [&](int code) {
+        gpe_plan_destroy(p);
+        return code;
+    };
+    if ((rc = dalloc(p, (void **)&p->st, sizeof(DevState)))) return cleanup(rc);
+    if ((rc = dalloc(p, (void **)&p->tx, sizeof(float4) * nx))) return cleanup(rc);
+    if ((rc = dalloc(p, (void **)&p->ty, sizeof(float4) * ny))) return cleanup(rc);
+    std::vector<double2> kx(nx), ky(ny), twx(nx), twy(ny);
+    std::vector<double> kmx(nx), kmy(ny);
+    const double inv = 1.0 / ((double)nx * ny);
+    for (int i = 0; i < nx; ++i) {
+        const double k = kval(i, nx, d->lx), ph = 0.5 * k * k * d->dt;
+        kx[i] = make_double2(std::cos(ph), -std::sin(ph));
+        kmx[i] = std::exp(-ph);
+        const double a = -2.0 * M_PI * i / nx;
+        twx[i] = make_double2(std::cos(a), std::sin(a));
+    }
+    for (int j = 0; j < ny; ++j) {
+        const double k = kval(j, ny, d->ly), ph = 0.5 * k * k * d->dt;
+        ky[j] = make_double2(std::cos(ph) * inv, -std::sin(ph) * inv);
+        kmy[j] = std::exp(-ph) * inv;
+        const double a = -2.0 * M_PI * j / ny;
+        twy[j] = make_double2(std::cos(a), std::sin(a));
+    }
+    if ((rc = upload(p, &p->kin_x, kx)) || (rc = upload(p, &p->kin_y, ky)) || (rc = upload(p, &p->kim_x, kmx)) ||
+        (rc = upload(p, &p->kim_y, kmy)) || (rc = upload(p, &p->tw_x, twx)) || (rc = upload(p, &p->tw_y, twy)))
+        return cleanup(rc);
+    p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 4096);
+    if ((rc = dalloc(p, (void **)&p->partials, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
+    if ((rc = dalloc(p, (void **)&p->partials2, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
+    if ((rc = dalloc(p, (void **)&p->scratch, sizeof(float2) * (size_t)nx * ny))) return cleanup(rc);
+    if (hipHostMalloc((void **)&p->hpart, sizeof(double) * NPART * p->npart_max) != hipSuccess)
+        return cleanup(fail(GPE_ERR_NOMEM, "hipHostMalloc"));
+    GridDev &gd = p->grid;
+    gd.nx = nx;
+    gd.ny = ny;
+    gd.lx = d->lx;
+    gd.ly = d->ly;
+    gd.dx = d->lx / nx;
+    gd.dy = d->ly / ny;
+    gd.dA = gd.dx * gd.dy;
+    gd.dt = d->dt;
+    gd.g = d->g;
+    gd.kin_x = p->kin_x;
+    gd.kin_y = p->kin_y;
+    gd.kim_x = p->kim_x;
+    gd.kim_y = p->kim_y;
+    gd.tw_x = p->tw_x;
+    gd.tw_y = p->tw_y;
+    gpe_potential_desc pot{};
+    pot.wx = pot.wy = 1.0;
+    if ((rc = gpe_set_potential(p, &pot))) return cleanup(rc);
+    *out = p;
+    return GPE_OK;
+}
+
+int gpe_plan_destroy(gpe_plan *p)
+{
+    if (!p) return GPE_OK;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *a : p->allocs) (void)hipFree(a);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->hpart) (void)hipHostFree(p->hpart);
+    delete p;
+    return GPE_OK;
+}
+
+static bool use_lds(const gpe_plan *p)
+{
+    if (p->path == 1) return false;
+    return lds_supported(p->nx, p->ny);
+}
+
+static RowArgs row_args(gpe_plan *p, float2 *psi)
+{
+    RowArgs a{};
+    a.src = psi;
+    a.dst = psi;
+    a.grid = p->grid;
+    a.pot = p->pot;
+    a.st = p->st;
+    a.partials = p->partials;
+    a.lines_per_wg = p->shape.row_lines;
+    return a;
+}
+
+static ColArgs col_args(gpe_plan *p, float2 *psi, int mode_tail_unused = 0)
+{
+    (void)mode_tail_unused;
+    ColArgs c{};
+    c.src = psi;
+    c.dst = psi;
+    c.grid = p->grid;
+    c.st = p->st;
+    c.partials = p->partials2;
+    c.cols_per_wg = p->shape.col_cols;
+    c.pot = p->pot;
+    return c;
+}
+
+#define LAUNCH_OK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static int run_lds(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *obs, bool imag)
+{
+    LdsArgs a{};
+    a.psi = (float2 *)psi;
+    a.grid = p->grid;
+    a.pot = p->pot;
+    a.st = p->st;
+    a.obs = obs;
+    a.imag = imag ? 1 : 0;
+    LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
+    // the kernel runs all steps; split very long runs so one launch stays short
+    const int64_t chunk = 1 << 20;
+    for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
+        a.nsteps = (int)std::min<int64_t>(chunk, nsteps - s0);
+        a.obs = obs ? obs + s0 * NOBS : nullptr;
+        if (s0 > 0 && !imag) LAUNCH_OK(launch_set_call(p->st, t + s0 * p->dt, 1, 0, p->stream));
+        LAUNCH_OK(launch_lds_grid(a, p->stream));
+    }
+    if (p->pot.cavity && !imag) p->have_theta = true;
+    return GPE_OK;
+}
+
+int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *obs)
+{
+    if (!p || !psi || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
+    if (!std::isfinite(t0)) return fail(GPE_ERR_INVALID, "t0 must be finite");
+    if (nsteps == 0) return GPE_OK;
+    if (use_lds(p)) return run_lds(p, psi, nsteps, t0, obs, false);
+    const Shape &sh = p->shape;
+    float2 *f = (float2 *)psi;
+    const bool cav = p->pot.cavity != 0;
+    const bool first_theta = cav && !p->have_theta;
+    const bool red = cav || obs != nullptr;
+    LAUNCH_OK(launch_set_call(p->st, t0, 0, 0, p->stream));
+    RowArgs ra = row_args(p, f);
+    ra.n = 0;
+    ra.reduce = first_theta ? 1 : 0;
+    LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+    for (int64_t n = 0; n < nsteps; ++n) {
+        ColArgs ca = col_args(p, f);
+        TailArgs &ta = ca.tail;
+        ta.partials = p->partials;
+        ta.npartials = (n == 0) ? (first_theta ? sh.row_blocks : 0) : (red ? sh.row_blocks : 0);
+        ta.first_theta = (n == 0 && first_theta) ? 1 : 0;
+        ta.obs = (n >= 1 && obs) ? obs + (n - 1) * NOBS : nullptr;
+        ta.imag = 0;
+        ta.advance_alpha = cav ? 1 : 0;
+        ca.do_tail = (ta.npartials > 0 || ta.advance_alpha) ? 1 : 0;
+        const bool timed = p->timing_every > 0 && n % p->timing_every == 0 && n + 1 < nsteps;
+        hipEvent_t *ec = timed ? timing_pair(p, 0) : nullptr;
+        if (ec) HIP_OK(hipEventRecord(ec[0], p->stream));
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        if (ec) HIP_OK(hipEventRecord(ec[1], p->stream));
+        ra.n = (int)n;
+        ra.reduce = red ? 1 : 0;
+        hipEvent_t *er = timed ? timing_pair(p, 1) : nullptr;
+        if (er) HIP_OK(hipEventRecord(er[0], p->stream));
+        LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, ra, sh.row_blocks, sh.row_threads,
+                             sh.row_shmem, p->stream));
+        if (er) HIP_OK(hipEventRecord(er[1], p->stream));
+    }
+    if (red) {
+        TailArgs ta{};
+        ta.partials = p->partials;
+        ta.npartials = sh.row_blocks;
+        ta.obs = obs ? obs + (nsteps - 1) * NOBS : nullptr;
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+    }
+    if (cav) p->have_theta = true;
+    return GPE_OK;
+}
+
+int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *obs)
+{
+    if (!p || !psi || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
+    if (!std::isfinite(t)) return fail(GPE_ERR_INVALID, "t must be finite");
+    if (nsteps == 0) return GPE_OK;
+    if (use_lds(p)) return run_lds(p, psi, nsteps, t, obs, true);
+    const Shape &sh = p->shape;
+    float2 *f = (float2 *)psi;
+    LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
+    RowArgs ra = row_args(p, f);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        ra.n = (int)n;
+        ra.reduce = 0;
+        LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        ColArgs ca = col_args(p, f);
+        ca.do_tail = 0;
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        ra.reduce = 1;
+        LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        TailArgs ta{};
+        ta.partials = p->partials;
+        ta.npartials = sh.row_blocks;
+        ta.imag = 1;
+        ta.obs = obs ? obs + n * NOBS : nullptr;
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+    }
+    LAUNCH_OK(launch_scale(f, (size_t)p->nx * p->ny, p->st, p->stream));
+    LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
+    return GPE_OK;
+}
+
+static int read_state(gpe_plan *p, DevState *out)
+{
+    HIP_OK(hipMemcpyAsync(out, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    return GPE_OK;
+}
+
+int gpe_sync(gpe_plan *p)
+{
+    if (!p) return fail(GPE_ERR_INVALID, "null plan");
+    DevState st;
+    int rc = read_state(p, &st);
+    if (rc) return rc;
+    if (st.nonfinite) return fail(GPE_ERR_NONFINITE, "non-finite values in psi");
+    return GPE_OK;
+}
+
+int gpe_norm(gpe_plan *p, const gpe_c64 *psi, double *out)
+{
+    if (!p || !psi || !out) return fail(GPE_ERR_INVALID, "null argument");
+    const int blocks = 256;
+    LAUNCH_OK(launch_norm((const float2 *)psi, (size_t)p->nx * p->ny, p->partials, blocks, p->stream));
+    HIP_OK(hipMemcpyAsync(p->hpart, p->partials, sizeof(double) * blocks, hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    double s = 0;
+    for (int i = 0; i < blocks; ++i) s += p->hpart[i];
+    *out = s * p->grid.dA;
+    return GPE_OK;
+}
+
+int gpe_energy(gpe_plan *p, const gpe_c64 *psi, double t, double out[6])
+{
+    if (!p || !psi || !out) return fail(GPE_ERR_INVALID, "null argument");
+    if (!std::isfinite(t)) return fail(GPE_ERR_INVALID, "t must be finite");
+    const Shape &sh = p->shape;
+    LAUNCH_OK(launch_set_call(p->st, t, 0, 0, p->stream));
+    RowArgs ra = row_args(p, p->scratch);
+    ra.src = (const float2 *)psi;
+    ra.dst = p->scratch;
+    ra.reduce = 1;
+    LAUNCH_OK(launch_row(p->nx, ROW_FWD, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+    ColArgs ca = col_args(p, p->scratch);
+    ca.do_tail = 0;
+    LAUNCH_OK(launch_col(p->ny, COL_EKIN, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+    std::vector<double> rp((size_t)sh.row_blocks * NPART), cp((size_t)sh.col_blocks * NPART);
+    HIP_OK(hipMemcpyAsync(rp.data(), p->partials, rp.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipMemcpyAsync(cp.data(), p->partials2, cp.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    double nrm = 0, ep = 0, ei = 0, ek = 0;
+    for (int b = 0; b < sh.row_blocks; ++b) {
+        nrm += rp[b * NPART + 0];
+        ep += rp[b * NPART + 1];
+        ei += rp[b * NPART + 2];
+    }
+    for (int b = 0; b < sh.col_blocks; ++b) ek += cp[b * NPART + 0];
+    const double dA = p->grid.dA;
+    nrm *= dA;
+    ep *= dA;
+    ei *= 0.5 * p->g * dA;
+    ek *= dA / ((double)p->nx * p->ny);
+    out[0] = ek / nrm;
+    out[1] = ep / nrm;
+    out[2] = ei / nrm;
+    out[3] = (ek + ep + ei) / nrm;
+    out[4] = (ek + ep + 2 * ei) / nrm;
+    out[5] = nrm;
+    return GPE_OK;
+}
+
+int gpe_set_timing(gpe_plan *p, int every)
+{
+    if (!p || every < 0) return fail(GPE_ERR_INVALID, "null plan or negative interval");
+    HIP_OK(hipStreamSynchronize(p->stream));
+    p->ev_pairs.clear();
+    p->ev_used = 0;
+    p->timing_every = every;
+    if (every > 0 && p->ev_pool.empty()) {
+        p->ev_pool.resize(8192);
+        for (auto &e : p->ev_pool) HIP_OK(hipEventCreate(&e));
+    }
+    return GPE_OK;
+}
+
+int gpe_get_timing(gpe_plan *p, double out[4])
+{
+    if (!p || !out) return fail(GPE_ERR_INVALID, "null argument");
+    HIP_OK(hipStreamSynchronize(p->stream));
+    double sum[2] = {0, 0};
+    int cnt[2] = {0, 0};
+    for (auto &pr : p->ev_pairs) {
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, p->ev_pool[pr.second], p->ev_pool[pr.second + 1]));
+        sum[pr.first] += ms;
+        cnt[pr.first] += 1;
+    }
+    out[0] = cnt[0] ? sum[0] / cnt[0] : 0.0;
+    out[1] = cnt[0];
+    out[2] = cnt[1] ? sum[1] / cnt[1] : 0.0;
+    out[3] = cnt[1];
+    return GPE_OK;
+}
+
+int gpe_get_cavity(gpe_plan *p, double out[4])
+{
+    if (!p || !out) return fail(GPE_ERR_INVALID, "null argument");
+    DevState st;
+    int rc = read_state(p, &st);
+    if (rc) return rc;
+    out[0] = st.alpha_re;
+    out[1] = st.alpha_im;
+    out[2] = st.theta;
+    out[3] = st.theta_prev;
+    if (st.nonfinite) return fail(GPE_ERR_NONFINITE, "non-finite values in psi");
+    return GPE_OK;
+}
+
+int gpe_set_cavity(gpe_plan *p, const double s[4], int have_history)
+{
+    if (!p || !s) return fail(GPE_ERR_INVALID, "null argument");
+    DevState st;
+    int rc = read_state(p, &st);
+    if (rc) return rc;
+    st.alpha_re = s[0];
+    st.alpha_im = s[1];
+    st.theta = s[2];
+    st.theta_prev = s[3];
+    st.have_theta = have_history ? 1 : 0;
+    HIP_OK(hipMemcpyAsync(p->st, &st, sizeof(st), hipMemcpyHostToDevice, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    p->have_theta = have_history != 0;
+    return GPE_OK;
+}
+
+}  // extern "C"

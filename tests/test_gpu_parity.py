@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (per workload, after its step count): relative L2 error of psi <= 1e-4 and
+relative energy error <= 1e-5; pass-level checks are tighter.  Both the LDS-resident
+path (small grids) and the multi-pass path (any grid; forced with GPE_PATH) are run.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, state
+from tests.gpu_util import rel_l2, rel_l2_phase_aligned, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL_L2 = 1e-4
+TOL_E = 1e-5
+
+
+def make_plan(setup, path, monkeypatch):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    monkeypatch.setenv("GPE_PATH", path)
+    return gpe.Plan.from_setup(setup)
+
+
+def rel_e(a, b):
+    return abs(a - b) / abs(b)
+
+
+# ------------------------------------------------------------ pass level
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+@pytest.mark.parametrize("shape", [(64, 64), (128, 32), (32, 128), (16, 16)])
+def test_free_flow_single_steps_match_spectral_propagation(path, shape, monkeypatch):
+    """V = g = 0: a step is exactly the kinetic factor; checks FFT signs, k ordering,
+    scaling and the transposed axes on non-square grids."""
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=nx * 0.2, ly=ny * 0.15, dt=0.01, g=0.0, wx=0.0, wy=0.0)
+    psi0 = W.to_c64(W.gaussian(s, 0.8, 0.3, -0.2) * np.exp(1j * 0.7 * s.xs()[None, :]))
+    ref, _ = O.step_real(problem(s), state(s), psi0, 3)
+    plan = make_plan(s, path, monkeypatch)
+    d = to_dev(psi0)
+    plan.step_real(d, 3, 0.0)
+    assert rel_l2(to_host(d), ref) < 2e-6
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_one_step_with_every_potential_term(path, monkeypatch):
+    """Trap (displaced, anisotropic), both lattices (ramp and const), cavity terms
+    with a non-zero field: one real and one imaginary step."""
+    s = W.Setup(nx=64, ny=32, lx=12.0, ly=8.0, dt=0.02, g=30.0, wx=1.1, wy=0.8, x0=0.3, y0=-0.2,
+                kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("ramp", 1.0, 3.0, 0.0, 0.1),
+                sy=W.Schedule("const", 2.0), cavity=True, vc=1.5, kc=1.7, delta_c=-4.0, kappa=2.0,
+                eta=3.0, alpha0=0.4 - 0.3j)
+    psi0 = W.random_state(s, 11)
+    for mode in ("real", "imag"):
+        st = state(s, 0.05)
+        if mode == "real":
+            ref, _ = O.step_real(problem(s), st, psi0, 2)
+        else:
+            ref, _ = O.step_imag(problem(s), st, psi0, 2)
+        plan = make_plan(s, path, monkeypatch)
+        d = to_dev(psi0)
+        (plan.step_real if mode == "real" else plan.step_imag)(d, 2, 0.05)
+        assert rel_l2(to_host(d), ref) < 2e-6, mode
+        if mode == "real":
+            assert abs(plan.cavity()["alpha"] - st.alpha) < 1e-9
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_energy_and_norm_functionals(path, monkeypatch):
+    s = W.Setup(nx=128, ny=64, lx=16.0, ly=10.0, dt=0.01, g=50.0, kx_lat=1.0, sx=W.Schedule("const", 2.0))
+    psi0 = W.random_state(s, 5)
+    plan = make_plan(s, path, monkeypatch)
+    d = to_dev(psi0)
+    e = plan.energy(d, 0.0)
+    ref = O.energy(problem(s), psi0)
+    for k in ("ekin", "epot", "eint", "e", "mu", "norm"):
+        assert rel_e(e[k], ref[k]) < 1e-9, k
+    assert rel_e(plan.norm(d), O.norm(problem(s), psi0)) < 1e-12
+
+
+# ----------------------------------------------- imaginary-time ground state
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+@pytest.mark.parametrize("g", [0.0, 100.0])
+def test_imag_ground_state_64(path, g, monkeypatch):
+    """64x64 on [-8,8)^2, dtau = 1e-3, 2000 steps, seed-perturbed Gaussian."""
+    s = W.imag_ground_64(g)
+    psi0 = W.noisy_gaussian(s, 0)
+    ref, robs = O.step_imag(problem(s), state(s), psi0, W.IMAG_64_STEPS, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((W.IMAG_64_STEPS, 6), dtype=torch.float64, device="cuda")
+    plan.step_imag(d, W.IMAG_64_STEPS, 0.0, obs)
+    out = to_host(d)
+    assert rel_l2(out, ref) < TOL_L2
+    assert rel_e(plan.energy(d)["e"], O.energy(problem(s), ref)["e"]) < TOL_E
+    o = obs.cpu().numpy()
+    assert np.abs(o[:, 0] - robs[:, 0]).max() < 3e-7  # pre-normalisation norms (c64 state)
+    assert abs(plan.norm(d) - 1.0) < 1e-6
+
+
+# --------------------------------------------------------------- real time
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_real_time_ramp_and_displaced_trap(path, monkeypatch):
+    s0 = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=0.01, g=100.0)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.gaussian(s0, 1.5), 1500)
+    psi0 = W.to_c64(gs)
+    s = s0.with_(dt=1e-3, y0=0.5, kx_lat=2.0, sx=W.Schedule("ramp", 0.0, 5.0, 0.0, 1.0))
+    nsteps = 2000
+    ref, robs = O.step_real(problem(s), state(s), psi0, nsteps, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((nsteps, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, nsteps, 0.0, obs)
+    out = to_host(d)
+    assert rel_l2(out, ref) < TOL_L2
+    t = nsteps * s.dt
+    assert rel_e(plan.energy(d, t)["e"], O.energy(problem(s), ref, t)["e"]) < TOL_E
+    o = obs.cpu().numpy()
+    assert np.abs(o[:, 0] - robs[:, 0]).max() < 1e-5       # norm
+    assert np.abs(o[:, 5] - robs[:, 5]).max() < 1e-5       # <y> dipole
+    assert np.abs(o[:, 4] - robs[:, 4]).max() < 1e-5       # <x>
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_calls_compose(path, monkeypatch):
+    """Two calls of n steps equal one call of 2n steps (time and cavity history carried)."""
+    s = W.cavity_scaled(64, 1)
+    psi0 = W.to_c64(W.gaussian(s, 1.0))
+    plan = make_plan(s, path, monkeypatch)
+    a = to_dev(psi0)
+    plan.step_real(a, 300, 0.0)
+    plan.step_real(a, 300, 300 * s.dt)
+    al1 = plan.cavity()["alpha"]
+    plan2 = make_plan(s, path, monkeypatch)
+    b = to_dev(psi0)
+    plan2.step_real(b, 600, 0.0)
+    al2 = plan2.cavity()["alpha"]
+    # the split call adds one real-space round trip (one more complex64 rounding)
+    assert rel_l2(to_host(a), to_host(b)) < 1e-5
+    assert abs(al1 - al2) < 1e-6 * max(1.0, abs(al2))
+
+
+# ----------------------------------------------------------------- cavity
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+@pytest.mark.parametrize("seed", [0, 3])
+def test_cavity_self_consistent_128(path, seed, monkeypatch):
+    """Cavity workload physics (dx = 1/16, Vp = Vc = 3, k = 1, Delta_c = -20,
+    kappa = 10, eta from the seed) on a 128^2 box: psi and the field alpha."""
+    s = W.cavity_scaled(128, seed)
+    psi0 = W.to_c64(W.thomas_fermi_guess(s.with_(wx=0.4, wy=0.4), np.sqrt(s.g / np.pi) * 0.4))
+    nsteps = 2000
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, nsteps, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((nsteps, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, nsteps, 0.0, obs)
+    out = to_host(d)
+    assert rel_l2(out, ref) < TOL_L2
+    o = obs.cpu().numpy()
+    aref = robs[:, 2] + 1j * robs[:, 3]
+    agpu = o[:, 2] + 1j * o[:, 3]
+    assert np.abs(agpu - aref).max() <= 1e-4 * max(np.abs(aref).max(), 1e-3)
+    assert np.abs(o[:, 1] - robs[:, 1]).max() < 1e-6  # Theta
+    t = nsteps * s.dt
+    assert rel_e(plan.energy(d, t)["e"], O.energy(problem(s), ref, t, st.alpha)["e"]) < TOL_E
