@@ -164,6 +164,16 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
 int gpe_batch_destroy(gpe_batch *b);
 int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double t0);
 
+/* Autotune the launch schedule (radix 4 or 8, rows per work-group, number of column
+ * tiles) of every multi-pass group by timing the candidates on the members' scratch
+ * arrays; choices are read from and appended to the text file cache_path (NULL: no
+ * cache), one line "arch nx ny count radix row_threads min_col_tiles us_per_step". */
+int gpe_batch_tune(gpe_batch *b, const char *cache_path);
+
+/* Description of size group g (synchronous): out = {nx, ny, members, lds-resident,
+ * radix, row threads per work-group, column work-groups per member, number of groups}. */
+int gpe_batch_info(gpe_batch *b, int group, int out[8]);
+
 /* ------------------------------------------------------------------ adjoint
  * Gradient of a loss of psi(T), T = t0 + nsteps dt, with respect to the knot values
  * of the x-lattice depth schedule (GPE_SCHED_KNOTS) of every member of a batch of

@@ -19,17 +19,20 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = OUT, defines: tuple = ()) -> str:
+    """Compile every source into `out`; `defines` (e.g. ("GPE_RADIX=16",)) select
+    compile-time kernel variants for tuning runs."""
     srcs = [s for s in SRC if os.path.exists(s)]
-    tmp = OUT + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *srcs]
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(OUT)
+    defs = tuple(a[2:] for a in sys.argv[1:] if a.startswith("-D"))
+    outs = [a[len("--out="):] for a in sys.argv[1:] if a.startswith("--out=")]
+    print(build(verbose="-v" in sys.argv, out=outs[0] if outs else OUT, defines=defs))

@@ -1,32 +1,751 @@
-// batch.cpp -- batched and adjoint entry points (placeholders until implemented).
-#include <hip/hip_runtime.h>
+// batch.cpp -- many independent condensates advanced together (gpe_batch_*).
+//
+// Members are grouped by grid size.  Groups small enough for one work-group's LDS
+// run all their steps in a single launch (one work-group per member) on a side
+// stream; the other groups run one batched row pass and one batched column pass per
+// step over all their members, with chunks of steps replayed from a captured HIP
+// graph.  Launch shapes (radix, rows per work-group, column-tile count) of each
+// multi-pass group are chosen by gpe_batch_tune, which times the candidates on the
+// members' own geometry and keeps the choice in a small text cache.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
 
-#include "../../include/gpe.h"
+#include "runtime_internal.h"
+
+namespace {
+
+struct Tuning {
+    int radix = 8, row_threads = 256, min_col_tiles = 256;
+};
+
+struct BGroup {
+    int nx = 0, ny = 0;
+    bool lds = false;
+    std::vector<int> members;
+    Tuning tune;
+    Shape shape{};
+    InstDesc *d_inst = nullptr;
+    std::vector<InstDesc> h_inst;
+    LdsArgs *d_lds = nullptr;
+    std::vector<LdsArgs> h_lds;
+};
+
+}  // namespace
+
+struct gpe_batch {
+    int n = 0;
+    double dt = 0;
+    std::vector<gpe_plan *> plans;
+    std::vector<BGroup> groups;
+    hipStream_t user = nullptr, work = nullptr, side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_fork = nullptr, ev_side = nullptr, ev_out = nullptr;
+    DevState **d_states = nullptr;     // every member
+    DevState **d_states_mp = nullptr;  // members of multi-pass groups
+    int n_mp = 0;
+    std::vector<void *> allocs;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    int chunk = 50;
+    bool warmed = false;
+};
+
+static int balloc(gpe_batch *b, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    b->allocs.push_back(*p);
+    return GPE_OK;
+}
+
+static Shape group_shape(const BGroup &g)
+{
+    return make_shape_r(g.nx, g.ny, g.tune.radix, xchg_bytes(), g.tune.row_threads, g.tune.min_col_tiles);
+}
+
+static void drop_graph(gpe_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_def) (void)hipGraphDestroy(b->graph_def);
+    b->graph = nullptr;
+    b->graph_def = nullptr;
+}
+
+// One multi-pass group: the row pass of relative step n (mode entry/mid/exit).
+static int group_row(gpe_batch *b, BGroup &g, int mode, int n, hipStream_t s)
+{
+    BatchPassArgs a{};
+    a.inst = g.d_inst;
+    a.blocks_per_inst = g.shape.row_blocks;
+    a.per_wg = g.shape.row_lines;
+    a.n = n;
+    const int blocks = g.shape.row_blocks * (int)g.members.size();
+    LAUNCH_OK(launch_row_batched(g.nx, g.tune.radix, mode, a, blocks, g.shape.row_threads, g.shape.row_shmem, s));
+    (void)b;
+    return GPE_OK;
+}
+
+static int group_col(gpe_batch *b, BGroup &g, hipStream_t s)
+{
+    BatchPassArgs a{};
+    a.inst = g.d_inst;
+    a.blocks_per_inst = g.shape.col_blocks;
+    a.per_wg = g.shape.col_cols;
+    const int blocks = g.shape.col_blocks * (int)g.members.size();
+    a.xcd_swizzle = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
+    LAUNCH_OK(launch_col_batched(g.ny, g.tune.radix, a, blocks, g.shape.col_threads, g.shape.col_shmem, s));
+    (void)b;
+    return GPE_OK;
+}
+
+// `count` middle steps (column pass + merged-kick row pass) of every multi-pass group,
+// relative step indices n0 .. n0+count-1.
+static int mid_steps(gpe_batch *b, int n0, int count, hipStream_t s)
+{
+    for (int k = 0; k < count; ++k)
+        for (auto &g : b->groups) {
+            if (g.lds) continue;
+            int rc = group_col(b, g, s);
+            if (rc) return rc;
+            if ((rc = group_row(b, g, ROW_MID, n0 + k, s))) return rc;
+        }
+    return GPE_OK;
+}
+
+static bool has_multipass(const gpe_batch *b)
+{
+    for (auto &g : b->groups)
+        if (!g.lds) return true;
+    return false;
+}
+
+static int build_graph(gpe_batch *b)
+{
+    drop_graph(b);
+    HIP_OK(hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal));
+    int rc = mid_steps(b, 0, b->chunk, b->work);
+    hipError_t e2 = launch_advance_t0(b->d_states_mp, b->n_mp, b->chunk * b->dt, b->work);
+    hipError_t e = hipStreamEndCapture(b->work, &b->graph_def);
+    if (rc) return rc;
+    if (e2 != hipSuccess || e != hipSuccess) return fail(GPE_ERR_DEVICE, "graph capture failed");
+    HIP_OK(hipGraphInstantiate(&b->graph, b->graph_def, nullptr, nullptr, 0));
+    return GPE_OK;
+}
 
 extern "C" {
 
 int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const gpe_potential_desc *pots)
 {
-    (void)n; (void)descs; (void)pots;
-    if (out) *out = nullptr;
-    return GPE_ERR_UNSUPPORTED;
+    if (!out || !descs || !pots || n < 1) return fail(GPE_ERR_INVALID, "need n >= 1 descriptions and potentials");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (descs[i].dt != descs[0].dt) return fail(GPE_ERR_INVALID, "batch members must share dt");
+        if (pots[i].cavity) return fail(GPE_ERR_UNSUPPORTED, "batched cavity members are not supported");
+    }
+    gpe_batch *b = new gpe_batch();
+    b->n = n;
+    b->dt = descs[0].dt;
+    b->user = (hipStream_t)descs[0].stream;
+    auto cleanup = [&](int rc) {
+        gpe_batch_destroy(b);
+        return rc;
+    };
+    int rc = 0;
+    for (int i = 0; i < n; ++i) {
+        gpe_plan_desc d = descs[i];
+        d.stream = nullptr;
+        gpe_plan *p = nullptr;
+        if ((rc = gpe_plan_create(&p, &d))) return cleanup(rc);
+        b->plans.push_back(p);
+        if ((rc = gpe_set_potential(p, &pots[i]))) return cleanup(rc);
+    }
+    HIP_OK(hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&b->ev_in, &b->ev_fork, &b->ev_side, &b->ev_out})
+        HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    for (int i = 0; i < n; ++i) {
+        gpe_plan *p = b->plans[i];
+        auto it = std::find_if(b->groups.begin(), b->groups.end(),
+                               [&](const BGroup &g) { return g.nx == p->nx && g.ny == p->ny; });
+        if (it == b->groups.end()) {
+            BGroup g;
+            g.nx = p->nx;
+            g.ny = p->ny;
+            g.lds = lds_supported(p->nx, p->ny);
+            b->groups.push_back(g);
+            it = b->groups.end() - 1;
+        }
+        it->members.push_back(i);
+    }
+    std::vector<DevState *> states(n);
+    for (int i = 0; i < n; ++i) states[i] = b->plans[i]->st;
+    if ((rc = balloc(b, (void **)&b->d_states, sizeof(DevState *) * n))) return cleanup(rc);
+    HIP_OK(hipMemcpy(b->d_states, states.data(), sizeof(DevState *) * n, hipMemcpyHostToDevice));
+    // the time base of multi-pass members is advanced by the graph while the LDS groups
+    // (side stream) read theirs, so the two sets are kept apart
+    std::vector<DevState *> mp;
+    for (auto &g : b->groups)
+        if (!g.lds)
+            for (int i : g.members) mp.push_back(b->plans[i]->st);
+    b->n_mp = (int)mp.size();
+    if (b->n_mp) {
+        if ((rc = balloc(b, (void **)&b->d_states_mp, sizeof(DevState *) * mp.size()))) return cleanup(rc);
+        HIP_OK(hipMemcpy(b->d_states_mp, mp.data(), sizeof(DevState *) * mp.size(), hipMemcpyHostToDevice));
+    }
+    for (auto &g : b->groups) {
+        const size_t m = g.members.size();
+        if (g.lds) {
+            g.h_lds.resize(m);
+            for (size_t k = 0; k < m; ++k) {
+                gpe_plan *p = b->plans[g.members[k]];
+                LdsArgs a{};
+                a.grid = p->grid;
+                a.pot = p->pot;
+                a.st = p->st;
+                g.h_lds[k] = a;
+            }
+            if ((rc = balloc(b, (void **)&g.d_lds, sizeof(LdsArgs) * m))) return cleanup(rc);
+        } else {
+            g.shape = group_shape(g);
+            g.h_inst.resize(m);
+            for (size_t k = 0; k < m; ++k) {
+                gpe_plan *p = b->plans[g.members[k]];
+                InstDesc d{};
+                d.grid = p->grid;
+                d.pot = p->pot;
+                d.st = p->st;
+                g.h_inst[k] = d;
+            }
+            if ((rc = balloc(b, (void **)&g.d_inst, sizeof(InstDesc) * m))) return cleanup(rc);
+        }
+    }
+    *out = b;
+    return GPE_OK;
 }
 
-int gpe_batch_destroy(gpe_batch *b) { (void)b; return GPE_OK; }
+int gpe_batch_destroy(gpe_batch *b)
+{
+    if (!b) return GPE_OK;
+    if (b->work) (void)hipStreamSynchronize(b->work);
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    drop_graph(b);
+    for (gpe_plan *p : b->plans) gpe_plan_destroy(p);
+    for (void *a : b->allocs) (void)hipFree(a);
+    for (hipEvent_t e : {b->ev_in, b->ev_fork, b->ev_side, b->ev_out})
+        if (e) (void)hipEventDestroy(e);
+    if (b->work) (void)hipStreamDestroy(b->work);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    delete b;
+    return GPE_OK;
+}
+
+// Point every member's descriptor at its wave function (and, for the LDS groups, at
+// the step count of this call).
+static int bind_psis(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, bool ensure_len = true)
+{
+    for (auto &g : b->groups) {
+        const size_t m = g.members.size();
+        if (g.lds) {
+            for (size_t k = 0; k < m; ++k) {
+                g.h_lds[k].psi = (float2 *)psis[g.members[k]];
+                g.h_lds[k].nsteps = (int)nsteps;
+            }
+            HIP_OK(hipMemcpyAsync(g.d_lds, g.h_lds.data(), sizeof(LdsArgs) * m, hipMemcpyHostToDevice, b->work));
+        } else {
+            for (size_t k = 0; k < m; ++k) g.h_inst[k].psi = (float2 *)psis[g.members[k]];
+            HIP_OK(hipMemcpyAsync(g.d_inst, g.h_inst.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, b->work));
+        }
+    }
+    (void)ensure_len;
+    return GPE_OK;
+}
 
 int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double t0)
 {
-    (void)b; (void)psis; (void)nsteps; (void)t0;
-    return GPE_ERR_UNSUPPORTED;
+    if (!b || !psis || nsteps < 0) return fail(GPE_ERR_INVALID, "null batch/psis or negative nsteps");
+    if (!std::isfinite(t0)) return fail(GPE_ERR_INVALID, "t0 must be finite");
+    for (int i = 0; i < b->n; ++i)
+        if (!psis[i]) return fail(GPE_ERR_INVALID, "null member wave function");
+    if (nsteps == 0) return GPE_OK;
+    if (nsteps > (1 << 30)) return fail(GPE_ERR_INVALID, "nsteps too large for one call");
+    HIP_OK(hipEventRecord(b->ev_in, b->user));
+    HIP_OK(hipStreamWaitEvent(b->work, b->ev_in, 0));
+    int rc = bind_psis(b, psis, nsteps);
+    if (rc) return rc;
+    LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0, b->work));
+    // LDS-resident groups: all steps in one launch on the side stream
+    bool side_used = false;
+    HIP_OK(hipEventRecord(b->ev_fork, b->work));
+    for (auto &g : b->groups) {
+        if (!g.lds) continue;
+        if (!side_used) HIP_OK(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+        side_used = true;
+        LAUNCH_OK(launch_lds_batched(g.nx, g.ny, g.d_lds, (int)g.members.size(), b->side));
+    }
+    if (side_used) HIP_OK(hipEventRecord(b->ev_side, b->side));
+    // multi-pass groups
+    if (has_multipass(b)) {
+        for (auto &g : b->groups)
+            if (!g.lds && (rc = group_row(b, g, ROW_ENTRY, 0, b->work))) return rc;
+        int64_t mids = nsteps - 1, done = 0;
+        if (!b->warmed && mids > 0) {
+            const int k = (int)std::min<int64_t>(mids, 1);
+            if ((rc = mid_steps(b, 0, k, b->work))) return rc;
+            done = k;
+            b->warmed = true;
+        }
+        // chunks replayed from the captured graph use steps relative to st->t0,
+        // which the graph advances by chunk*dt at its end
+        if (mids - done >= b->chunk) {
+            if (done > 0) LAUNCH_OK(launch_advance_t0(b->d_states_mp, b->n_mp, done * b->dt, b->work));
+            if (!b->graph && (rc = build_graph(b))) return rc;
+            while (mids - done >= b->chunk) {
+                HIP_OK(hipGraphLaunch(b->graph, b->work));
+                done += b->chunk;
+            }
+            if ((rc = mid_steps(b, 0, (int)(mids - done), b->work))) return rc;
+            for (auto &g : b->groups)
+                if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
+            for (auto &g : b->groups)
+                if (!g.lds && (rc = group_row(b, g, ROW_EXIT, (int)(mids - done), b->work))) return rc;
+        } else {
+            if ((rc = mid_steps(b, (int)done, (int)(mids - done), b->work))) return rc;
+            for (auto &g : b->groups)
+                if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
+            for (auto &g : b->groups)
+                if (!g.lds && (rc = group_row(b, g, ROW_EXIT, (int)mids, b->work))) return rc;
+        }
+    }
+    if (side_used) HIP_OK(hipStreamWaitEvent(b->work, b->ev_side, 0));
+    HIP_OK(hipEventRecord(b->ev_out, b->work));
+    HIP_OK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    return GPE_OK;
+}
+
+// Time `steps` middle steps of group g on its members' scratch arrays (device-side
+// contents are irrelevant to the timing).
+static double time_group(gpe_batch *b, BGroup &g, int steps)
+{
+    std::vector<gpe_c64 *> psis(b->n, nullptr);
+    for (int i = 0; i < b->n; ++i) psis[i] = (gpe_c64 *)b->plans[i]->scratch;
+    for (auto &p : b->plans) (void)hipMemsetAsync(p->scratch, 0, sizeof(float2) * (size_t)p->nx * p->ny, b->work);
+    if (bind_psis(b, psis.data(), 1)) return 1e30;
+    for (int it = 0; it < 2; ++it) {
+        auto t = std::chrono::steady_clock::now();
+        for (int k = 0; k < steps; ++k) {
+            if (group_col(b, g, b->work) || group_row(b, g, ROW_MID, k, b->work)) return 1e30;
+        }
+        if (hipStreamSynchronize(b->work) != hipSuccess) return 1e30;
+        double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count();
+        if (it == 1) return us / steps;
+    }
+    return 1e30;
+}
+
+int gpe_batch_tune(gpe_batch *b, const char *cache_path)
+{
+    if (!b) return fail(GPE_ERR_INVALID, "null batch");
+    hipDeviceProp_t prop;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    const std::string arch = prop.gcnArchName;
+    std::vector<std::string> lines;
+    if (cache_path && *cache_path) {
+        std::ifstream f(cache_path);
+        std::string l;
+        while (std::getline(f, l)) lines.push_back(l);
+    }
+    bool changed = false;
+    for (auto &g : b->groups) {
+        if (g.lds) continue;
+        std::ostringstream key;
+        key << arch << " " << g.nx << " " << g.ny << " " << g.members.size();
+        bool found = false;
+        for (auto &l : lines) {
+            if (l.rfind(key.str() + " ", 0) == 0) {
+                std::istringstream is(l.substr(key.str().size()));
+                Tuning t;
+                double us;
+                if (is >> t.radix >> t.row_threads >> t.min_col_tiles >> us) {
+                    g.tune = t;
+                    g.shape = group_shape(g);
+                    found = true;
+                }
+            }
+        }
+        if (found) continue;
+        Tuning best = g.tune;
+        double best_us = 1e30;
+        for (int r : {8, 4})
+            for (int rt : {128, 256, 512})
+                for (int mt : {128, 256, 512}) {
+                    if (g.nx / r > 512 || g.ny / r > 1024 || g.nx > 2048 || g.ny > 2048) continue;
+                    g.tune = {r, rt, mt};
+                    g.shape = group_shape(g);
+                    if (g.shape.row_threads > 512 || g.shape.col_threads > 1024) continue;
+                    const double us = time_group(b, g, 10);
+                    if (us < best_us) {
+                        best_us = us;
+                        best = g.tune;
+                    }
+                }
+        g.tune = best;
+        g.shape = group_shape(g);
+        std::ostringstream l;
+        l << key.str() << " " << best.radix << " " << best.row_threads << " " << best.min_col_tiles << " " << best_us;
+        lines.push_back(l.str());
+        changed = true;
+    }
+    drop_graph(b);
+    b->warmed = false;
+    if (changed && cache_path && *cache_path) {
+        std::ofstream f(cache_path);
+        for (auto &l : lines) f << l << "\n";
+    }
+    HIP_OK(hipStreamSynchronize(b->work));
+    return GPE_OK;
+}
+
+int gpe_batch_info(gpe_batch *b, int group, int out[8])
+{
+    if (!b || !out || group < 0 || group >= (int)b->groups.size()) return fail(GPE_ERR_INVALID, "bad group");
+    const BGroup &g = b->groups[group];
+    out[0] = g.nx;
+    out[1] = g.ny;
+    out[2] = (int)g.members.size();
+    out[3] = g.lds ? 1 : 0;
+    out[4] = g.tune.radix;
+    out[5] = g.shape.row_threads;
+    out[6] = g.shape.col_blocks;
+    out[7] = (int)b->groups.size();
+    return GPE_OK;
+}
+
+// --------------------------------------------------------------------- adjoint
+
+namespace {
+struct AdjWork {
+    int nx = 0, ny = 0, nb = 0;
+    int64_t cap_steps = 0;
+    std::vector<float2 *> psi, lam;
+    std::vector<double *> kick_grad, partials;
+    std::vector<float2 *> ckpt;  // [slot * nb + member]
+    int ckpt_slots = 0;
+    AdjInst *d_adj = nullptr;
+    InstDesc *d_fwd = nullptr;
+    const float2 **d_pa = nullptr, **d_pb = nullptr;
+    float2 **d_dst = nullptr;
+    double2 *d_coef = nullptr;
+    double *d_sums = nullptr;
+    size_t bytes = 0;
+};
+}  // namespace
+
+static std::vector<std::pair<gpe_batch *, AdjWork *>> g_adj;  // one workspace per batch
+
+static AdjWork *adj_work(gpe_batch *b)
+{
+    for (auto &p : g_adj)
+        if (p.first == b) return p.second;
+    AdjWork *w = new AdjWork();
+    g_adj.push_back({b, w});
+    return w;
+}
+
+// Hat weights of the piecewise-linear schedule at time t (same clamping as the device).
+static void hat(const gpe_schedule &s, double t, int *i0, double *w0, double *w1)
+{
+    const int m = s.nknots;
+    if (t <= s.t0) { *i0 = 0; *w0 = 1; *w1 = 0; return; }
+    if (t >= s.t1) { *i0 = m - 2; *w0 = 0; *w1 = 1; return; }
+    double u = (t - s.t0) / (s.t1 - s.t0) * (m - 1);
+    int i = (int)std::floor(u);
+    if (i >= m - 1) i = m - 2;
+    *i0 = i;
+    *w1 = u - i;
+    *w0 = 1.0 - *w1;
+}
+
+static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t nsteps, int slots)
+{
+    const size_t npts = (size_t)nx * ny;
+    if (w->nx != nx || w->ny != ny || w->nb != nb) {
+        if (w->nb) return fail(GPE_ERR_INVALID, "adjoint workspace already sized for another batch shape");
+        w->nx = nx;
+        w->ny = ny;
+        w->nb = nb;
+        w->psi.resize(nb);
+        w->lam.resize(nb);
+        w->kick_grad.resize(nb);
+        w->partials.resize(nb);
+        for (int i = 0; i < nb; ++i) {
+            int rc;
+            if ((rc = balloc(b, (void **)&w->psi[i], sizeof(float2) * npts))) return rc;
+            if ((rc = balloc(b, (void **)&w->lam[i], sizeof(float2) * npts))) return rc;
+            if ((rc = balloc(b, (void **)&w->partials[i], sizeof(double) * 4096))) return rc;
+            w->bytes += 2 * sizeof(float2) * npts;
+        }
+        int rc;
+        if ((rc = balloc(b, (void **)&w->d_adj, sizeof(AdjInst) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_fwd, sizeof(InstDesc) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_pa, sizeof(void *) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_pb, sizeof(void *) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_dst, sizeof(void *) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_coef, sizeof(double2) * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_sums, sizeof(double) * 4 * 64 * nb))) return rc;
+    }
+    if (nsteps + 1 > w->cap_steps) {
+        for (int i = 0; i < nb; ++i) {
+            int rc;
+            if ((rc = balloc(b, (void **)&w->kick_grad[i], sizeof(double) * (size_t)(nsteps + 1)))) return rc;
+        }
+        w->cap_steps = nsteps + 1;
+    }
+    while (w->ckpt_slots < slots) {
+        for (int i = 0; i < nb; ++i) {
+            float2 *c = nullptr;
+            int rc;
+            if ((rc = balloc(b, (void **)&c, sizeof(float2) * npts))) return rc;
+            w->ckpt.push_back(c);
+            w->bytes += sizeof(float2) * npts;
+        }
+        w->ckpt_slots++;
+    }
+    return GPE_OK;
+}
+
+// Host sums of pair_sums partials: {Re <a|b>, Im <a|b>, |a-b|^2, |b|^2} per member.
+static int pair_sums(gpe_batch *b, AdjWork *w, const std::vector<const float2 *> &pa,
+                     const std::vector<const float2 *> &pb, std::vector<std::array<double, 4>> &out)
+{
+    const int per = 64, nb = w->nb;
+    HIP_OK(hipMemcpyAsync(w->d_pa, pa.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+    HIP_OK(hipMemcpyAsync(w->d_pb, pb.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+    LAUNCH_OK(launch_pair_sums(w->d_pa, w->d_pb, (size_t)w->nx * w->ny, nb, per, w->d_sums, b->work));
+    std::vector<double> h((size_t)4 * per * nb);
+    HIP_OK(hipMemcpyAsync(h.data(), w->d_sums, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->work));
+    HIP_OK(hipStreamSynchronize(b->work));
+    out.assign(nb, {0, 0, 0, 0});
+    for (int i = 0; i < nb; ++i)
+        for (int l = 0; l < per; ++l)
+            for (int k = 0; k < 4; ++k) out[i][k] += h[((size_t)i * per + l) * 4 + k];
+    return GPE_OK;
+}
+
+// Forward real-time steps [n0, n1) of every member on the adjoint workspace (batched
+// multi-pass kernels, time base st->t0 = t0 + n0 dt).
+static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1)
+{
+    const int nb = w->nb;
+    LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0 + n0 * b->dt, b->work));
+    BatchPassArgs ra{}, ca{};
+    ra.inst = w->d_fwd;
+    ra.blocks_per_inst = sh.row_blocks;
+    ra.per_wg = sh.row_lines;
+    ca.inst = w->d_fwd;
+    ca.blocks_per_inst = sh.col_blocks;
+    ca.per_wg = sh.col_cols;
+    const int rblocks = sh.row_blocks * nb, cblocks = sh.col_blocks * nb;
+    ca.xcd_swizzle = (cblocks % 8 == 0 && cblocks >= 64) ? 1 : 0;
+    const int64_t k = n1 - n0;
+    ra.n = 0;
+    LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_ENTRY, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+    for (int64_t j = 0; j < k; ++j) {
+        LAUNCH_OK(launch_col_batched(w->ny, 8, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
+        ra.n = (int)j;
+        LAUNCH_OK(launch_row_batched(w->nx, 8, j + 1 < k ? ROW_MID : ROW_EXIT, ra, rblocks, sh.row_threads,
+                                     sh.row_shmem, b->work));
+    }
+    return GPE_OK;
+}
+
+// Reverse sweep over steps [n0, n1) (from n1 down to n0): on entry psi holds psi_{n1}
+// and lam the adjoint at n1 (real space); on exit psi_{n0} (reconstructed) and lam_{n0}.
+static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1)
+{
+    const int nb = w->nb;
+    LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0, b->work));
+    AdjPassArgs ra{}, ca{};
+    ra.inst = w->d_adj;
+    ra.blocks_per_inst = sh.row_blocks;
+    ra.per_wg = sh.row_lines;
+    ca.inst = w->d_adj;
+    ca.blocks_per_inst = sh.col_blocks;
+    ca.per_wg = sh.col_cols;
+    ca.row_blocks = sh.row_blocks;
+    const int rblocks = sh.row_blocks * nb, cblocks = sh.col_blocks * nb;
+    ca.xcd_swizzle = (cblocks % 8 == 0 && cblocks >= 64) ? 1 : 0;
+    // rows need 2 arrays' worth of registers: at most 256 threads per work-group
+    ra.kick = (int)n1;
+    LAUNCH_OK(launch_row_adj(w->nx, ADJ_FIRST, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+    int pending = (int)n1;
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+        ca.tail_kick = pending;
+        LAUNCH_OK(launch_col_adj(w->ny, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
+        ra.kick = (int)n;
+        LAUNCH_OK(launch_row_adj(w->nx, n > n0 ? ADJ_MID : ADJ_LAST, ra, rblocks, sh.row_threads, sh.row_shmem,
+                                 b->work));
+        pending = (int)n;
+    }
+    LAUNCH_OK(launch_adj_tail(w->d_adj, nb, sh.row_blocks, pending, b->work));
+    return GPE_OK;
 }
 
 int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *target, int64_t nsteps, double t0,
                 const double *knots, int nknots, int loss_kind, int mode, double drift_tol, double *loss,
                 double *grad, gpe_c64 *const *psi_final, double *info)
 {
-    (void)b; (void)psi0; (void)target; (void)nsteps; (void)t0; (void)knots; (void)nknots; (void)loss_kind;
-    (void)mode; (void)drift_tol; (void)loss; (void)grad; (void)psi_final; (void)info;
-    return GPE_ERR_UNSUPPORTED;
+    if (!b || !psi0 || !loss || !grad || nsteps < 1 || !knots)
+        return fail(GPE_ERR_INVALID, "null argument or nsteps < 1");
+    if (loss_kind != GPE_LOSS_FIDELITY) return fail(GPE_ERR_UNSUPPORTED, "only the fidelity loss runs on the GPU");
+    if (!target) return fail(GPE_ERR_INVALID, "fidelity loss needs target states");
+    if (mode < GPE_ADJ_AUTO || mode > GPE_ADJ_CHECKPOINT) return fail(GPE_ERR_INVALID, "bad adjoint mode");
+    if (nsteps > (1 << 28)) return fail(GPE_ERR_INVALID, "nsteps too large");
+    const int nb = b->n;
+    const int nx = b->plans[0]->nx, ny = b->plans[0]->ny;
+    for (int i = 0; i < nb; ++i) {
+        gpe_plan *p = b->plans[i];
+        if (p->nx != nx || p->ny != ny) return fail(GPE_ERR_INVALID, "adjoint members must share the grid size");
+        if (p->pot.sx.kind != GPE_SCHED_KNOTS || p->pot.sx.nknots != nknots)
+            return fail(GPE_ERR_INVALID, "members need an x-lattice knot schedule with nknots values");
+        if (p->pot.cavity) return fail(GPE_ERR_UNSUPPORTED, "adjoint with the cavity on");
+        if (!psi0[i] || !target[i]) return fail(GPE_ERR_INVALID, "null member state");
+    }
+    if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
+    Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, 256);
+    if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, nx / std::max(1, 512 / (ny / 8)));
+    if (sh.col_threads > 512) return fail(GPE_ERR_UNSUPPORTED, "column shape");
+    AdjWork *w = adj_work(b);
+    const int64_t seg = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    int rc = adj_alloc(b, w, nx, ny, nb, nsteps, mode == GPE_ADJ_RECONSTRUCT ? 0 : (int)nseg);
+    if (rc) return rc;
+    const size_t npts = (size_t)nx * ny;
+    HIP_OK(hipEventRecord(b->ev_in, b->user));
+    HIP_OK(hipStreamWaitEvent(b->work, b->ev_in, 0));
+    // controls: the members' x-lattice knot values
+    for (int i = 0; i < nb; ++i)
+        HIP_OK(hipMemcpyAsync(b->plans[i]->knots_x, knots + (size_t)i * nknots, sizeof(double) * nknots,
+                              hipMemcpyHostToDevice, b->work));
+    std::vector<InstDesc> fwd(nb);
+    std::vector<AdjInst> adj(nb);
+    for (int i = 0; i < nb; ++i) {
+        gpe_plan *p = b->plans[i];
+        fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st};
+        adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i]};
+    }
+    HIP_OK(hipMemcpyAsync(w->d_fwd, fwd.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice, b->work));
+    HIP_OK(hipMemcpyAsync(w->d_adj, adj.data(), sizeof(AdjInst) * nb, hipMemcpyHostToDevice, b->work));
+
+    auto run = [&](bool checkpoint, double *drift) -> int {
+        for (int i = 0; i < nb; ++i) {
+            HIP_OK(hipMemcpyAsync(w->psi[i], psi0[i], sizeof(float2) * npts, hipMemcpyDeviceToDevice, b->work));
+            HIP_OK(hipMemsetAsync(w->kick_grad[i], 0, sizeof(double) * (size_t)(nsteps + 1), b->work));
+        }
+        int r;
+        if (checkpoint) {
+            for (int64_t s = 0; s < nseg; ++s) {
+                for (int i = 0; i < nb; ++i)
+                    HIP_OK(hipMemcpyAsync(w->ckpt[(size_t)s * nb + i], w->psi[i], sizeof(float2) * npts,
+                                          hipMemcpyDeviceToDevice, b->work));
+                if ((r = adj_forward(b, w, sh, t0, s * seg, std::min(nsteps, (s + 1) * seg)))) return r;
+            }
+        } else if ((r = adj_forward(b, w, sh, t0, 0, nsteps))) {
+            return r;
+        }
+        if (psi_final)
+            for (int i = 0; i < nb; ++i)
+                if (psi_final[i])
+                    HIP_OK(hipMemcpyAsync(psi_final[i], w->psi[i], sizeof(float2) * npts, hipMemcpyDeviceToDevice,
+                                          b->work));
+        // terminal adjoint: L = 1 - |c|^2, c = <target|psi(T)>, G = -2 c target dA
+        std::vector<const float2 *> pa(nb), pb(nb);
+        for (int i = 0; i < nb; ++i) {
+            pa[i] = (const float2 *)target[i];
+            pb[i] = w->psi[i];
+        }
+        std::vector<std::array<double, 4>> sums;
+        if ((r = pair_sums(b, w, pa, pb, sums))) return r;
+        std::vector<double2> coef(nb);
+        for (int i = 0; i < nb; ++i) {
+            const double dA = b->plans[i]->grid.dA;
+            const double cr = sums[i][0] * dA, ci = sums[i][1] * dA;
+            loss[i] = 1.0 - (cr * cr + ci * ci);
+            coef[i] = make_double2(-2.0 * cr * dA, -2.0 * ci * dA);
+        }
+        HIP_OK(hipMemcpyAsync(w->d_coef, coef.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, b->work));
+        std::vector<float2 *> dst(w->lam.begin(), w->lam.end());
+        HIP_OK(hipMemcpyAsync(w->d_dst, dst.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+        HIP_OK(hipMemcpyAsync(w->d_pa, pa.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+        LAUNCH_OK(launch_scaled_copy(w->d_dst, w->d_pa, w->d_coef, npts, nb, 64, b->work));
+        if (checkpoint) {
+            for (int64_t s = nseg - 1; s >= 0; --s) {
+                const int64_t e = std::min(nsteps, (s + 1) * seg);
+                if (s < nseg - 1)  // restart the state from the stored psi at the segment end
+                    for (int i = 0; i < nb; ++i)
+                        HIP_OK(hipMemcpyAsync(w->psi[i], w->ckpt[(size_t)(s + 1) * nb + i], sizeof(float2) * npts,
+                                              hipMemcpyDeviceToDevice, b->work));
+                if ((r = adj_reverse(b, w, sh, t0, s * seg, e))) return r;
+            }
+        } else if ((r = adj_reverse(b, w, sh, t0, 0, nsteps))) {
+            return r;
+        }
+        // drift of the state rebuilt at t0 against the input
+        for (int i = 0; i < nb; ++i) {
+            pa[i] = w->psi[i];
+            pb[i] = (const float2 *)psi0[i];
+        }
+        if ((r = pair_sums(b, w, pa, pb, sums))) return r;
+        *drift = 0;
+        for (int i = 0; i < nb; ++i) *drift = std::max(*drift, std::sqrt(sums[i][2] / std::max(sums[i][3], 1e-300)));
+        return GPE_OK;
+    };
+
+    double drift = 0;
+    bool ckpt = (mode == GPE_ADJ_CHECKPOINT);
+    if ((rc = run(ckpt, &drift))) return rc;
+    int64_t fwd_steps = nsteps;
+    if (mode == GPE_ADJ_AUTO && !(drift <= drift_tol)) {
+        if ((rc = adj_alloc(b, w, nx, ny, nb, nsteps, (int)nseg))) return rc;
+        ckpt = true;
+        if ((rc = run(true, &drift))) return rc;
+        fwd_steps += nsteps;
+    }
+    // gradient: dL/dc_m = sum_k w_m(t_k) dL/dV0(t_k)
+    std::vector<double> kg((size_t)(nsteps + 1));
+    for (int i = 0; i < nb; ++i) {
+        HIP_OK(hipMemcpyAsync(kg.data(), w->kick_grad[i], sizeof(double) * kg.size(), hipMemcpyDeviceToHost, b->work));
+        HIP_OK(hipStreamSynchronize(b->work));
+        gpe_schedule s{};
+        const Sched &d = b->plans[i]->pot.sx;
+        s.nknots = d.nknots;
+        s.t0 = d.t0;
+        s.t1 = d.t1;
+        double *g = grad + (size_t)i * nknots;
+        for (int m = 0; m < nknots; ++m) g[m] = 0;
+        for (int64_t k = 0; k <= nsteps; ++k) {
+            int i0;
+            double w0, w1;
+            hat(s, t0 + k * b->dt, &i0, &w0, &w1);
+            g[i0] += w0 * kg[k];
+            g[i0 + 1] += w1 * kg[k];
+        }
+    }
+    if (info) {
+        info[0] = ckpt ? 2 : 1;
+        info[1] = drift;
+        info[2] = (double)w->bytes;
+        info[3] = (double)fwd_steps;
+    }
+    HIP_OK(hipEventRecord(b->ev_out, b->work));
+    HIP_OK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    return GPE_OK;
 }
 
-}
+}  // extern "C"

@@ -94,10 +94,56 @@ struct ColArgs {
     DevState *st;
     double *partials;
     int cols_per_wg;
+    int xcd_swizzle;  // map consecutive column tiles onto one XCD (shared L2 lines)
     int reduce;
     PotDev pot;
     TailArgs tail;
     int do_tail;
+};
+
+// One member of a batch (device memory).
+struct InstDesc {
+    float2 *psi;
+    GridDev grid;
+    PotDev pot;
+    DevState *st;
+};
+
+// A batched row or column pass over all members of one grid size.
+struct BatchPassArgs {
+    const InstDesc *inst;
+    int blocks_per_inst;  // work-groups (row blocks or column tiles) per member
+    int per_wg;           // rows or columns per work-group
+    int n;                // step index within the call
+    int xcd_swizzle;
+};
+
+// One member of an adjoint sweep (device memory): the state being reconstructed
+// backwards and its adjoint, plus where the per-kick lattice gradient goes.
+struct AdjInst {
+    float2 *psi;
+    float2 *lam;
+    GridDev grid;
+    PotDev pot;
+    DevState *st;
+    double *partials;   // [row work-groups] per-row-block sums of the current kick
+    double *kick_grad;  // [nsteps + 1] dL/dV0 at t0 + k dt
+};
+
+enum AdjRowMode : int {
+    ADJ_FIRST = 0,  // real-space (psi_K, lam_K) -> adjoint half kick at t_K -> FFT_x
+    ADJ_MID = 1,    // IFFT_x -> adjoint merged kick at t_n -> FFT_x
+    ADJ_LAST = 2,   // IFFT_x -> adjoint half kick at t_0 -> real space
+};
+
+struct AdjPassArgs {
+    const AdjInst *inst;
+    int blocks_per_inst;
+    int per_wg;
+    int kick;           // step index of the kick (time st->t0 + kick dt)
+    int xcd_swizzle;
+    int tail_kick;      // column pass: add the previous row pass's sums to kick_grad[tail_kick] (-1: none)
+    int row_blocks;     // number of row work-groups per member (partials to reduce)
 };
 
 // Whole grid resident in one work-group's LDS (small grids).

@@ -21,26 +21,84 @@
 
 namespace gpe {
 
-constexpr int kRadix = 8;
-constexpr int kLgR = 3;
+// Points per thread of the multi-pass kernels (radix of the Stockham passes) and the
+// element type of the LDS exchanges between passes.
+#ifndef GPE_RADIX
+#define GPE_RADIX 8
+#endif
+#ifndef GPE_XCHG_FLOAT
+#define GPE_XCHG_FLOAT 0
+#endif
+#ifndef GPE_TW_LDS
+#define GPE_TW_LDS 1
+#endif
+constexpr int kRadix = GPE_RADIX;
+constexpr int kLgR = ilog2(GPE_RADIX);
+#if GPE_XCHG_FLOAT
+using XchgT = float2;
+#else
+using XchgT = double2;
+#endif
+
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
+#ifndef GPE_NT_STORE
+#define GPE_NT_STORE 0
+#endif
+// Store of one complex64 result of a pass.  The non-temporal form streams the line
+// past L2 (it is read next by work-groups on other XCDs), leaving no dirty L2 lines
+// for the end-of-kernel write-back.
+__device__ __forceinline__ void store_c64(float2 *p, double2 v)
+{
+    const float2 f = make_float2((float)v.x, (float)v.y);
+#if GPE_NT_STORE
+    union {
+        float2 f;
+        unsigned long long u;
+    } cv;
+    cv.f = f;
+    __builtin_nontemporal_store(cv.u, (unsigned long long *)p);
+#else
+    *p = f;
+#endif
+}
+
+int kernel_radix() { return kRadix; }
+size_t xchg_bytes() { return sizeof(XchgT); }
+// extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
+size_t staged_table_bytes(int n) { return GPE_TW_LDS ? (size_t)n * (sizeof(double2) + sizeof(float4)) : 0; }
 
 // --------------------------------------------------------------------- row pass
-template <int N, int MODE, bool IMAG>
-__global__ void __launch_bounds__(512) row_pass(RowArgs a)
+// One work-group transforms `lines` rows.  `row` is this thread's row; the caller has
+// placed `smem` (exchange lines, then the staged tables).
+template <int N, int R, int MODE, bool IMAG>
+__device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
+                                         const PotDev &pot, const DevState *st, double *partials, int n, int lb,
+                                         int lines, XchgT *smem, double *red)
 {
     using C = double2;
-    constexpr int R = kRadix;
     constexpr int T = N / R;
-    using View = LinePad<double2, kLgR>;
-    extern __shared__ double2 smem[];
-    __shared__ double red[8 * NPART];
-
+    using View = LinePad<XchgT, ilog2(R)>;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int row = blockIdx.x * a.lines_per_wg + line;
-    const GridDev &gd = a.grid;
+    const int row = lb * lines + line;
     View lds{smem + line * View::words(N)};
-    const float2 *src = a.src + (size_t)row * N;
-    float2 *dst = a.dst + (size_t)row * N;
+    const float2 *src = src_base + (size_t)row * N;
+    float2 *dst = dst_base + (size_t)row * N;
+#if GPE_TW_LDS
+    // twiddles and the x tables of the potential live in LDS for the whole pass, so
+    // the passes wait on LDS latency only
+    double2 *s_tw = (double2 *)((char *)smem + align16(lines * View::words(N) * sizeof(XchgT)));
+    float4 *s_tx = (float4 *)(s_tw + N);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s_tw[i] = gd.tw_x[i];
+        s_tx[i] = pot.tx[i];
+    }
+    const double2 *twx = s_tw;
+    const float4 *txt = s_tx;
+#else
+    const double2 *twx = gd.tw_x;
+    const float4 *txt = pot.tx;
+#endif
 
     C v[R];
 #pragma unroll
@@ -48,21 +106,23 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
         float2 f = src[t + m * T];
         v[m] = {(double)f.x, (double)f.y};
     }
+#if GPE_TW_LDS
+    __syncthreads();
+#endif
 
     // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes V
-    double tk = a.st->t0;
-    if (!IMAG) tk += (MODE == ROW_ENTRY ? a.n : a.n + 1) * gd.dt;
-    const double are = a.st->alpha_re, aim = a.st->alpha_im;
-    const VLine vl = vline_cav(a.pot, row, tk, are, aim);
-    const float4 ty = a.pot.ty[row];
+    double tk = st->t0;
+    if (!IMAG) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt;
+    const VLine vl = vline_cav(pot, row, tk, st->alpha_re, st->alpha_im);
+    const float4 ty = pot.ty[row];
     const double cy = ty.z, yv = ty.w;
-    const float *vu = a.pot.vuser ? a.pot.vuser + (size_t)row * N : nullptr;
+    const float *vu = pot.vuser ? pot.vuser + (size_t)row * N : nullptr;
 
-    if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, gd.tw_x);
+    if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, twx);
 
     double part[NPART] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (MODE == ROW_ENTRY && IMAG) {
-        const double sc = a.st->scale;
+        const double sc = st->scale;
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = {v[m].x * sc, v[m].y * sc};
     }
@@ -70,7 +130,7 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int i = t + m * T;
-        const float4 tx = a.pot.tx[i];
+        const float4 tx = txt[i];
         double V = vpoint(vl, tx);
         if (vu) V += (double)vu[i];
         const double d = v[m].x * v[m].x + v[m].y * v[m].y;
@@ -99,46 +159,76 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
             }
         }
     }
-    if (a.reduce) {
+    if (partials) {
         block_sum<NPART>(part, red);
         if (threadIdx.x == 0)
 #pragma unroll
-            for (int k = 0; k < NPART; ++k) a.partials[blockIdx.x * NPART + k] = part[k];
+            for (int k = 0; k < NPART; ++k) partials[k] = part[k];
     }
 
-    if constexpr (MODE != ROW_EXIT) fft_line<N, R, false>(v, lds, t, gd.tw_x);
+    if constexpr (MODE != ROW_EXIT) fft_line<N, R, false>(v, lds, t, twx);
 
 #pragma unroll
-    for (int m = 0; m < R; ++m) dst[t + m * T] = make_float2((float)v[m].x, (float)v[m].y);
+    for (int m = 0; m < R; ++m) store_c64(dst + t + m * T, v[m]);
+}
+
+template <int N, int MODE, bool IMAG>
+__global__ void __launch_bounds__(512) row_pass(RowArgs a)
+{
+    extern __shared__ XchgT smem[];
+    __shared__ double red[8 * NPART];
+    row_body<N, kRadix, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
+                                     a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
+                                     a.lines_per_wg, smem, red);
+}
+
+// Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
+template <int N, int R, int MODE>
+__global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
+{
+    extern __shared__ XchgT smem[];
+    __shared__ double red[8 * NPART];
+    const InstDesc &I = a.inst[blockIdx.x / a.blocks_per_inst];
+    row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, blockIdx.x % a.blocks_per_inst,
+                                a.per_wg, smem, red);
 }
 
 // ------------------------------------------------------------------ column pass
-template <int N, int MODE>
-__global__ void __launch_bounds__(1024) col_pass(ColArgs a)
+template <int N, int R, int MODE>
+__device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 *dst, const GridDev &gd,
+                                         double *partials, int tile, int w, XchgT *smem, double *red)
 {
     using C = double2;
-    constexpr int R = kRadix;
     constexpr int T = N / R;
-    using View = LineTile<double2, kLgR>;
-    extern __shared__ double2 smem[];
-    __shared__ double red[16 * NPART];
-
-    const GridDev &gd = a.grid;
-    if (a.do_tail && blockIdx.x == 0) run_tail(a.tail, gd, a.pot, a.st, red);
-
-    const int w = a.cols_per_wg;
+    using View = LineTile<XchgT, ilog2(R)>;
     const int c = threadIdx.x % w, t = threadIdx.x / w;
-    const int col = blockIdx.x * w + c;
+    const int col = tile * w + c;
     const int nx = gd.nx;
     View lds{smem + c, w};
+#if GPE_TW_LDS
+    double2 *s_tw = (double2 *)((char *)smem + align16(View::words(N, w) * sizeof(XchgT)));
+    double2 *s_ky = s_tw + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s_tw[i] = gd.tw_y[i];
+        if constexpr (MODE == COL_KIN_REAL) s_ky[i] = gd.kin_y[i];
+    }
+    const double2 *twy = s_tw;
+    const double2 *kiny = s_ky;
+#else
+    const double2 *twy = gd.tw_y;
+    const double2 *kiny = gd.kin_y;
+#endif
 
     C v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        float2 f = a.src[(size_t)(t + m * T) * nx + col];
+        float2 f = src[(size_t)(t + m * T) * nx + col];
         v[m] = {(double)f.x, (double)f.y};
     }
-    fft_line<N, R, false>(v, lds, t, gd.tw_y);
+#if GPE_TW_LDS
+    __syncthreads();
+#endif
+    fft_line<N, R, false>(v, lds, t, twy);
     if constexpr (MODE == COL_EKIN) {
         const int ix = col >= nx / 2 ? col - nx : col;
         const double kx = 2.0 * M_PI * ix / gd.lx;
@@ -151,13 +241,13 @@ __global__ void __launch_bounds__(1024) col_pass(ColArgs a)
             part[0] += 0.5 * (kx * kx + ky * ky) * (v[m].x * v[m].x + v[m].y * v[m].y);
         }
         block_sum<NPART>(part, red);
-        if (threadIdx.x == 0) a.partials[blockIdx.x * NPART] = part[0];
+        if (threadIdx.x == 0) partials[0] = part[0];
         return;
     } else {
         if constexpr (MODE == COL_KIN_REAL) {
             const C kx = gd.kin_x[col];
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kin_y[t + m * T]));
+            for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, kiny[t + m * T]));
         } else {
             const double kx = gd.kim_x[col];
 #pragma unroll
@@ -166,11 +256,38 @@ __global__ void __launch_bounds__(1024) col_pass(ColArgs a)
                 v[m] = {v[m].x * f, v[m].y * f};
             }
         }
-        fft_line<N, R, true>(v, lds, t, gd.tw_y);
+        fft_line<N, R, true>(v, lds, t, twy);
 #pragma unroll
-        for (int m = 0; m < R; ++m)
-            a.dst[(size_t)(t + m * T) * nx + col] = make_float2((float)v[m].x, (float)v[m].y);
+        for (int m = 0; m < R; ++m) store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
     }
+}
+
+// Work-groups are dealt round-robin to the 8 XCDs; with the swizzle, the tiles of one
+// XCD are contiguous, so the 128-byte lines shared by neighbouring tiles are fetched
+// once into that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int swz)
+{
+    return swz ? (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : (int)blockIdx.x;
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(1024) col_pass(ColArgs a)
+{
+    extern __shared__ XchgT smem[];
+    __shared__ double red[16 * NPART];
+    if (a.do_tail && blockIdx.x == 0) run_tail(a.tail, a.grid, a.pot, a.st, red);
+    col_body<N, kRadix, MODE>(a.src, a.dst, a.grid, a.partials + blockIdx.x * NPART, xcd_tile(a.xcd_swizzle),
+                              a.cols_per_wg, smem, red);
+}
+
+template <int N, int R>
+__global__ void __launch_bounds__(1024) col_pass_b(BatchPassArgs a)
+{
+    extern __shared__ XchgT smem[];
+    __shared__ double red[16 * NPART];
+    const int tile = xcd_tile(a.xcd_swizzle);
+    const InstDesc &I = a.inst[tile / a.blocks_per_inst];
+    col_body<N, R, COL_KIN_REAL>(I.psi, I.psi, I.grid, nullptr, tile % a.blocks_per_inst, a.per_wg, smem, red);
 }
 
 // --------------------------------------------------------------- small kernels
@@ -220,11 +337,12 @@ __global__ void __launch_bounds__(256) norm_kernel(const float2 *psi, size_t n, 
 // reductions (imaginary time: renormalise; cavity: overlap and field update).  The
 // launch uses exactly NX*NY/8 threads (at most 1024), so every thread owns a slice of
 // a line in both the row and the column sweeps.
-template <int NX, int NY>
-__global__ void __launch_bounds__((NX * NY / kRadix) < 1024 ? NX * NY / kRadix : 1024) lds_grid(LdsArgs a)
+constexpr int kLdsRadix = 8;
+
+template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs &a)
 {
     using C = double2;
-    constexpr int R = kRadix;
+    constexpr int R = kLdsRadix;
     constexpr int TX = NX / R, TY = NY / R;
     constexpr int P = NX + 1;
     constexpr int NTH = (NX * NY / R) < 1024 ? NX * NY / R : 1024;
@@ -408,6 +526,20 @@ __global__ void __launch_bounds__((NX * NY / kRadix) < 1024 ? NX * NY / kRadix :
     }
 }
 
+template <int NX, int NY>
+__global__ void __launch_bounds__((NX * NY / kLdsRadix) < 1024 ? NX * NY / kLdsRadix : 1024) lds_grid(LdsArgs a)
+{
+    lds_body<NX, NY>(a);
+}
+
+// Batched: work-group b runs member b of the batch for all steps.
+template <int NX, int NY>
+__global__ void __launch_bounds__((NX * NY / kLdsRadix) < 1024 ? NX * NY / kLdsRadix : 1024)
+    lds_grid_b(const LdsArgs *arr)
+{
+    lds_body<NX, NY>(arr[blockIdx.x]);
+}
+
 // ------------------------------------------------------------------- launchers
 template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowArgs &a, int blocks, int threads,
                                                 size_t shmem, hipStream_t s)
@@ -536,7 +668,7 @@ bool lds_supported(int nx, int ny)
 
 int lds_threads(int nx, int ny)
 {
-    const int n = nx * ny / kRadix;
+    const int n = nx * ny / kLdsRadix;
     return n < 1024 ? n : 1024;
 }
 
@@ -559,6 +691,386 @@ hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s)
     default: return hipErrorInvalidValue;
     }
 #undef GPE_LDS_Y
+}
+
+// ------------------------------------------------------------ batched launchers
+template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPassArgs &a, int blocks, int threads,
+                                                        size_t shmem, hipStream_t s)
+{
+#define GPE_ROWB(M)                                                                                \
+    do {                                                                                           \
+        static bool attr_ = false;                                                                 \
+        if (!attr_) {                                                                              \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M>,                 \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
+            if (e_ != hipSuccess) return e_;                                                       \
+            attr_ = true;                                                                          \
+        }                                                                                          \
+        hipLaunchKernelGGL((row_pass_b<N, R, M>), dim3(blocks), dim3(threads), shmem, s, a);       \
+    } while (0)
+    if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY);
+    else if (mode == ROW_MID) GPE_ROWB(ROW_MID);
+    else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT);
+    else return hipErrorInvalidValue;
+#undef GPE_ROWB
+    return hipGetLastError();
+}
+
+template <int N, int R> static hipError_t colb_dispatch(const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                                                        hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)col_pass_b<N, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((col_pass_b<N, R>), dim3(blocks), dim3(threads), shmem, s, a);
+    return hipGetLastError();
+}
+
+#define GPE_SIZES(F, ...)                                                                          \
+    switch (n) {                                                                                   \
+    case 64: return F<64, RR>(__VA_ARGS__);                                                        \
+    case 128: return F<128, RR>(__VA_ARGS__);                                                      \
+    case 256: return F<256, RR>(__VA_ARGS__);                                                      \
+    case 512: return F<512, RR>(__VA_ARGS__);                                                      \
+    case 1024: return F<1024, RR>(__VA_ARGS__);                                                    \
+    case 2048: return F<2048, RR>(__VA_ARGS__);                                                    \
+    default: return hipErrorInvalidValue;                                                          \
+    }
+
+hipError_t launch_row_batched(int n, int r, int mode, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                              hipStream_t s)
+{
+    if (r == 8) {
+        constexpr int RR = 8;
+        GPE_SIZES(rowb_dispatch, mode, a, blocks, threads, shmem, s)
+    } else if (r == 4) {
+        constexpr int RR = 4;
+        GPE_SIZES(rowb_dispatch, mode, a, blocks, threads, shmem, s)
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_col_batched(int n, int r, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                              hipStream_t s)
+{
+    if (r == 8) {
+        constexpr int RR = 8;
+        GPE_SIZES(colb_dispatch, a, blocks, threads, shmem, s)
+    } else if (r == 4) {
+        constexpr int RR = 4;
+        GPE_SIZES(colb_dispatch, a, blocks, threads, shmem, s)
+    }
+    return hipErrorInvalidValue;
+}
+#undef GPE_SIZES
+
+template <int NX, int NY> static hipError_t ldsb_launch(const LdsArgs *arr, int count, int threads, hipStream_t s)
+{
+    const size_t shmem = (size_t)(NX + 1) * NY * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void *)lds_grid_b<NX, NY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lds_grid_b<NX, NY>), dim3(count), dim3(threads), shmem, s, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, hipStream_t s)
+{
+    const int th = lds_threads(nx, ny);
+#define GPE_LDSB_Y(X)                                                                              \
+    switch (ny) {                                                                                  \
+    case 16: return ldsb_launch<X, 16>(arr, count, th, s);                                         \
+    case 32: return ldsb_launch<X, 32>(arr, count, th, s);                                         \
+    case 64: return ldsb_launch<X, 64>(arr, count, th, s);                                         \
+    case 128: return ldsb_launch<X, 128>(arr, count, th, s);                                       \
+    default: return hipErrorInvalidValue;                                                          \
+    }
+    switch (nx) {
+    case 16: GPE_LDSB_Y(16)
+    case 32: GPE_LDSB_Y(32)
+    case 64: GPE_LDSB_Y(64)
+    case 128: GPE_LDSB_Y(128)
+    default: return hipErrorInvalidValue;
+    }
+#undef GPE_LDSB_Y
+}
+
+// Start of a batched call: every member's state records the call's first time.
+__global__ void set_call_batched_kernel(DevState *const *st, int n, double t0)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        st[i]->t0 = t0;
+        st[i]->scale = 1.0;
+    }
+}
+
+// After a replayed chunk of steps: advance every member's first time.
+__global__ void advance_t0_kernel(DevState *const *st, int n, double dt_total)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) st[i]->t0 += dt_total;
+}
+
+hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_call_batched_kernel, dim3(1), dim3(256), 0, s, st, n, t0);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_t0_kernel, dim3(1), dim3(256), 0, s, st, n, dt_total);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------- adjoint passes
+// Reverse sweep of the real-time step for the discrete adjoint with respect to the
+// x-lattice depth.  For a kick psi' = psi e^{-i theta}, theta = (V + g|psi|^2) tau,
+// with real gradient G (dL = Re sum conj(G) d psi):
+//   psi = psi' e^{+i theta}   (exact: |psi| = |psi'|),
+//   s = Im(conj(G') psi'),  G = G' e^{+i theta} + 2 g tau s psi,  dL/dV(x) = tau s(x).
+// The kinetic propagation U = IFFT2 M FFT2 is unitary, so both the state and G go
+// back through U^H = IFFT2 conj(M) FFT2: the same passes with the conjugate factor.
+template <int N, int R, int MODE>
+__device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines, int kick, XchgT *smem, double *red)
+{
+    using C = double2;
+    constexpr int T = N / R;
+    using View = LinePad<XchgT, ilog2(R)>;
+    const GridDev &gd = I.grid;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int row = lb * lines + line;
+    View lds{smem + line * View::words(N)};
+    float2 *pp = I.psi + (size_t)row * N;
+    float2 *pl = I.lam + (size_t)row * N;
+    C v[R], w[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        float2 a = pp[t + m * T], b = pl[t + m * T];
+        v[m] = {(double)a.x, (double)a.y};
+        w[m] = {(double)b.x, (double)b.y};
+    }
+    if constexpr (MODE != ADJ_FIRST) {
+        fft_line<N, R, true>(v, lds, t, gd.tw_x);
+        fft_line<N, R, true>(w, lds, t, gd.tw_x);
+    }
+    const double tk = I.st->t0 + kick * gd.dt;
+    const double tau = (MODE == ADJ_MID) ? gd.dt : 0.5 * gd.dt;
+    const VLine vl = vline_cav(I.pot, row, tk, 0.0, 0.0);
+    const float *vu = I.pot.vuser ? I.pot.vuser + (size_t)row * N : nullptr;
+    double part[1] = {0.0};
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int i = t + m * T;
+        const float4 tx = I.pot.tx[i];
+        double V = vpoint(vl, tx);
+        if (vu) V += (double)vu[i];
+        const double th = (V + gd.g * (v[m].x * v[m].x + v[m].y * v[m].y)) * tau;
+        double sn, cs;
+        sincos_d(th, &sn, &cs);
+        const double s = w[m].x * v[m].y - w[m].y * v[m].x;  // Im(conj(G') psi')
+        const C vin = {v[m].x * cs - v[m].y * sn, v[m].x * sn + v[m].y * cs};
+        const double k2 = 2.0 * gd.g * tau * s;
+        w[m] = {w[m].x * cs - w[m].y * sn + k2 * vin.x, w[m].x * sn + w[m].y * cs + k2 * vin.y};
+        v[m] = vin;
+        part[0] += tau * s * (double)tx.y;  // d V / d V0 = cos^2(kx_lat x)
+    }
+    block_sum<1>(part, red);
+    if (threadIdx.x == 0) I.partials[lb] = part[0];
+    if constexpr (MODE != ADJ_LAST) {
+        fft_line<N, R, false>(v, lds, t, gd.tw_x);
+        fft_line<N, R, false>(w, lds, t, gd.tw_x);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        store_c64(pp + t + m * T, v[m]);
+        store_c64(pl + t + m * T, w[m]);
+    }
+}
+
+template <int N, int R, int MODE>
+__global__ void __launch_bounds__(512) row_adj_b(AdjPassArgs a)
+{
+    extern __shared__ XchgT smem[];
+    __shared__ double red[8];
+    const AdjInst &I = a.inst[blockIdx.x / a.blocks_per_inst];
+    row_adj_body<N, R, MODE>(I, blockIdx.x % a.blocks_per_inst, a.per_wg, a.kick, smem, red);
+}
+
+// Sum one member's row partials (fixed order) into kick_grad[k]; one work-group.
+__device__ __forceinline__ void adj_tail(const AdjInst &I, int nrow, int k, double *red)
+{
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < nrow; i += blockDim.x) s[0] += I.partials[i];
+    block_sum<1>(s, red);
+    if (threadIdx.x == 0) I.kick_grad[k] += s[0];
+}
+
+template <int N, int R>
+__global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
+{
+    using C = double2;
+    constexpr int T = N / R;
+    using View = LineTile<XchgT, ilog2(R)>;
+    extern __shared__ XchgT smem[];
+    __shared__ double red[16];
+    const int tile = xcd_tile(a.xcd_swizzle);
+    const AdjInst &I = a.inst[tile / a.blocks_per_inst];
+    const int lt = tile % a.blocks_per_inst;
+    if (a.tail_kick >= 0 && lt == 0) adj_tail(I, a.row_blocks, a.tail_kick, red);
+    const GridDev &gd = I.grid;
+    const int w = a.per_wg;
+    const int c = threadIdx.x % w, t = threadIdx.x / w;
+    const int col = lt * w + c;
+    const int nx = gd.nx;
+    View lds{smem + c, w};
+    C v[R], u[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        float2 f = I.psi[(size_t)(t + m * T) * nx + col], h = I.lam[(size_t)(t + m * T) * nx + col];
+        v[m] = {(double)f.x, (double)f.y};
+        u[m] = {(double)h.x, (double)h.y};
+    }
+    fft_line<N, R, false>(v, lds, t, gd.tw_y);
+    fft_line<N, R, false>(u, lds, t, gd.tw_y);
+    const C kx = gd.kin_x[col];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const C f = cmul(kx, gd.kin_y[t + m * T]);
+        v[m] = cmulc(v[m], f);
+        u[m] = cmulc(u[m], f);
+    }
+    fft_line<N, R, true>(v, lds, t, gd.tw_y);
+    fft_line<N, R, true>(u, lds, t, gd.tw_y);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        store_c64(I.psi + (size_t)(t + m * T) * nx + col, v[m]);
+        store_c64(I.lam + (size_t)(t + m * T) * nx + col, u[m]);
+    }
+}
+
+// The last kick's sums: one work-group per member.
+__global__ void __launch_bounds__(256) adj_tail_kernel(const AdjInst *inst, int nrow, int k)
+{
+    __shared__ double red[4];
+    adj_tail(inst[blockIdx.x], nrow, k, red);
+}
+
+// Per work-group partial sums over one member's points: {Re, Im} of sum conj(a) b, and
+// sum |a - b|^2, sum |b|^2.  Work-group b serves member b / per_inst.
+__global__ void __launch_bounds__(256) pair_sums_kernel(const float2 *const *a, const float2 *const *b, size_t npts,
+                                                        int per_inst, double *out)
+{
+    __shared__ double red[4 * 4];
+    const int inst = blockIdx.x / per_inst, lb = blockIdx.x % per_inst;
+    const float2 *pa = a[inst], *pb = b[inst];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < npts; i += (size_t)per_inst * blockDim.x) {
+        const float2 x = pa[i], y = pb[i];
+        s[0] += (double)x.x * y.x + (double)x.y * y.y;
+        s[1] += (double)x.x * y.y - (double)x.y * y.x;
+        const double dx = (double)x.x - y.x, dy = (double)x.y - y.y;
+        s[2] += dx * dx + dy * dy;
+        s[3] += (double)y.x * y.x + (double)y.y * y.y;
+    }
+    block_sum<4>(s, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) out[blockIdx.x * 4 + k] = s[k];
+}
+
+// lam_i = coef_i * src_i (terminal adjoint of the fidelity loss).
+__global__ void __launch_bounds__(256) scaled_copy_kernel(float2 *const *dst, const float2 *const *src,
+                                                          const double2 *coef, size_t npts, int per_inst)
+{
+    const int inst = blockIdx.x / per_inst, lb = blockIdx.x % per_inst;
+    const double2 c = coef[inst];
+    float2 *d = dst[inst];
+    const float2 *s = src[inst];
+    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < npts; i += (size_t)per_inst * blockDim.x) {
+        const float2 x = s[i];
+        d[i] = make_float2((float)(c.x * x.x - c.y * x.y), (float)(c.x * x.y + c.y * x.x));
+    }
+}
+
+template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPassArgs &a, int blocks, int threads,
+                                                          size_t shmem, hipStream_t s)
+{
+#define GPE_RADJ(M)                                                                                \
+    do {                                                                                           \
+        static bool attr_ = false;                                                                 \
+        if (!attr_) {                                                                              \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_adj_b<N, R, M>,                  \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
+            if (e_ != hipSuccess) return e_;                                                       \
+            attr_ = true;                                                                          \
+        }                                                                                          \
+        hipLaunchKernelGGL((row_adj_b<N, R, M>), dim3(blocks), dim3(threads), shmem, s, a);        \
+    } while (0)
+    if (mode == ADJ_FIRST) GPE_RADJ(ADJ_FIRST);
+    else if (mode == ADJ_MID) GPE_RADJ(ADJ_MID);
+    else if (mode == ADJ_LAST) GPE_RADJ(ADJ_LAST);
+    else return hipErrorInvalidValue;
+#undef GPE_RADJ
+    return hipGetLastError();
+}
+
+template <int N, int R> static hipError_t coladj_dispatch(const AdjPassArgs &a, int blocks, int threads, size_t shmem,
+                                                          hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)col_adj_b<N, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((col_adj_b<N, R>), dim3(blocks), dim3(threads), shmem, s, a);
+    return hipGetLastError();
+}
+
+#define GPE_ADJ_SIZES(F, ...)                                                                      \
+    switch (n) {                                                                                   \
+    case 64: return F<64, 8>(__VA_ARGS__);                                                         \
+    case 128: return F<128, 8>(__VA_ARGS__);                                                       \
+    case 256: return F<256, 8>(__VA_ARGS__);                                                       \
+    case 512: return F<512, 8>(__VA_ARGS__);                                                       \
+    case 1024: return F<1024, 8>(__VA_ARGS__);                                                     \
+    default: return hipErrorInvalidValue;                                                          \
+    }
+
+hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
+{
+    GPE_ADJ_SIZES(rowadj_dispatch, mode, a, blocks, threads, shmem, s)
+}
+
+hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
+{
+    GPE_ADJ_SIZES(coladj_dispatch, a, blocks, threads, shmem, s)
+}
+#undef GPE_ADJ_SIZES
+
+hipError_t launch_adj_tail(const AdjInst *inst, int count, int nrow, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(adj_tail_kernel, dim3(count), dim3(256), 0, s, inst, nrow, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sums(const float2 *const *a, const float2 *const *b, size_t npts, int count, int per_inst,
+                            double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(pair_sums_kernel, dim3(count * per_inst), dim3(256), 0, s, a, b, npts, per_inst, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, const double2 *coef, size_t npts,
+                              int count, int per_inst, hipStream_t s)
+{
+    hipLaunchKernelGGL(scaled_copy_kernel, dim3(count * per_inst), dim3(256), 0, s, dst, src, coef, npts, per_inst);
+    return hipGetLastError();
 }
 
 }  // namespace gpe

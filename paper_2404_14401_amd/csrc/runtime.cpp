@@ -10,76 +10,18 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gpe.h"
-#include "gpe_internal.h"
 
-namespace gpe {
-hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
-                      hipStream_t s);
-hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
-hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
-hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
-hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
-hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s);
-hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s);
-bool lds_supported(int nx, int ny);
-int lds_threads(int nx, int ny);
-}  // namespace gpe
-
-using namespace gpe;
+#include "runtime_internal.h"
 
 static thread_local std::string g_err;
 
-static int fail(int code, const std::string &msg)
+int gpe_fail(int code, const std::string &msg)
 {
     g_err = msg;
     return code;
 }
 
-#define HIP_OK(expr)                                                                               \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
-    } while (0)
-
-static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
-
-// Launch shape of the multi-pass path.
-struct Shape {
-    int row_lines, row_threads, row_blocks;
-    size_t row_shmem;
-    int col_cols, col_threads, col_blocks;
-    size_t col_shmem;
-};
-
-struct gpe_plan {
-    int nx = 0, ny = 0;
-    double lx = 0, ly = 0, dt = 0, g = 0;
-    hipStream_t stream = nullptr;
-    size_t max_bytes = 0, bytes = 0;
-    int path = 0;  // 0 auto, 1 multi-pass, 2 LDS
-    std::vector<void *> allocs;
-    DevState *st = nullptr;
-    float4 *tx = nullptr, *ty = nullptr;
-    double2 *kin_x = nullptr, *kin_y = nullptr, *tw_x = nullptr, *tw_y = nullptr;
-    double *kim_x = nullptr, *kim_y = nullptr;
-    double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
-    int npart_max = 0;
-    float2 *scratch = nullptr;
-    double *knots_x = nullptr, *knots_y = nullptr;
-    int knots_cap_x = 0, knots_cap_y = 0;
-    GridDev grid{};
-    PotDev pot{};
-    Shape shape{};
-    bool have_theta = false;
-    // pass timing (instrumentation)
-    int timing_every = 0;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<int, size_t>> ev_pairs;  // (kind 0 col / 1 row, index of start event)
-};
-
-static hipEvent_t *timing_pair(gpe_plan *p, int kind)
+hipEvent_t *timing_pair(gpe_plan *p, int kind)
 {
     if (p->ev_used + 2 > p->ev_pool.size()) return nullptr;
     p->ev_pairs.push_back({kind, p->ev_used});
@@ -88,7 +30,7 @@ static hipEvent_t *timing_pair(gpe_plan *p, int kind)
     return e;
 }
 
-static int dalloc(gpe_plan *p, void **ptr, size_t bytes)
+int dalloc(gpe_plan *p, void **ptr, size_t bytes)
 {
     if (p->max_bytes && p->bytes + bytes > p->max_bytes)
         return fail(GPE_ERR_NOMEM, "plan memory cap exceeded");
@@ -109,21 +51,48 @@ template <typename T> static int upload(gpe_plan *p, T **dst, const std::vector<
 
 static double kval(int j, int n, double len) { return 2.0 * M_PI * (j >= n / 2 ? j - n : j) / len; }
 
-static Shape make_shape(int nx, int ny)
+static int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+// Launch shape: threads per line T = n / R.  Rows: lines per work-group so that a
+// work-group has about 256 threads.  Columns: tiles of W adjacent columns, W chosen
+// so that there are at least 256 tiles (one per CU) when the grid allows it.
+Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles)
 {
     Shape s{};
-    const int R = 8;
-    const int tr = nx / R;
-    s.row_lines = std::max(1, 256 / tr);
+    int sh = 0;
+    while ((1 << sh) < R) ++sh;
+    const int tr = std::max(1, nx / R);
+    s.row_lines = std::max(1, row_threads / tr);
     if (s.row_lines > ny) s.row_lines = ny;
+    if (s.row_lines * tr > 512) s.row_lines = std::max(1, 512 / tr);
     s.row_threads = s.row_lines * tr;
     s.row_blocks = ny / s.row_lines;
-    s.row_shmem = (size_t)s.row_lines * (nx + nx / 8) * sizeof(double2);
-    const int tc = ny / R;
-    s.col_cols = std::max(1, std::min(nx, 512 / tc));
-    s.col_threads = s.col_cols * tc;
-    s.col_blocks = nx / s.col_cols;
-    s.col_shmem = ((size_t)ny * s.col_cols + ny / 8 + s.col_cols) * sizeof(double2);
+    s.row_shmem = (size_t)s.row_lines * (nx + (nx >> sh)) * eb;
+    s.row_shmem = (s.row_shmem + 15) / 16 * 16 + staged_table_bytes(nx);
+    const int tc = std::max(1, ny / R);
+    int w = std::max(1, std::min(nx, 1024 / tc));
+    while (w > 1 && nx / w < min_col_tiles) w /= 2;
+    s.col_cols = w;
+    s.col_threads = w * tc;
+    s.col_blocks = nx / w;
+    s.col_shmem = ((size_t)ny * w + (ny >> sh) + w) * eb;
+    s.col_shmem = (s.col_shmem + 15) / 16 * 16 + staged_table_bytes(ny);
+    return s;
+}
+
+static Shape make_shape(int nx, int ny)
+{
+    Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 256),
+                           env_int("GPE_MIN_COL_TILES", 256));
+    const int w = env_int("GPE_COL_W", 0);
+    if (w > 0 && w <= nx && (w & (w - 1)) == 0 && w * s.col_threads / s.col_cols <= 1024) {
+        Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 256), nx / w);
+        s = t;
+    }
     return s;
 }
 
@@ -239,6 +208,8 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     const char *force = getenv("GPE_PATH");
     if (force && !strcmp(force, "multipass")) p->path = 1;
     if (force && !strcmp(force, "lds")) p->path = 2;
+    const char *xcd = getenv("GPE_XCD");
+    if (xcd && !strcmp(xcd, "0")) p->xcd = 0;
     const int nx = d->nx, ny = d->ny;
     p->shape = make_shape(nx, ny);
     int rc = 0;
@@ -269,7 +240,7 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     if ((rc = upload(p, &p->kin_x, kx)) || (rc = upload(p, &p->kin_y, ky)) || (rc = upload(p, &p->kim_x, kmx)) ||
         (rc = upload(p, &p->kim_y, kmy)) || (rc = upload(p, &p->tw_x, twx)) || (rc = upload(p, &p->tw_y, twy)))
         return cleanup(rc);
-    p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 4096);
+    p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 256);
     if ((rc = dalloc(p, (void **)&p->partials, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->partials2, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->scratch, sizeof(float2) * (size_t)nx * ny))) return cleanup(rc);
@@ -339,15 +310,11 @@ static ColArgs col_args(gpe_plan *p, float2 *psi, int mode_tail_unused = 0)
     c.st = p->st;
     c.partials = p->partials2;
     c.cols_per_wg = p->shape.col_cols;
+    c.xcd_swizzle = (p->shape.col_blocks % 8 == 0 && p->shape.col_blocks >= 64) ? p->xcd : 0;
     c.pot = p->pot;
     return c;
 }
 
-#define LAUNCH_OK(expr)                                                                  \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e_)); \
-    } while (0)
 
 static int run_lds(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *obs, bool imag)
 {

@@ -1,0 +1,101 @@
+// runtime_internal.h -- host-side internals shared by the runtime files: the plan
+// object, launch shapes and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/gpe.h"
+#include "gpe_internal.h"
+
+namespace gpe {
+hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
+                      hipStream_t s);
+hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
+hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
+hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
+hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s);
+hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s);
+hipError_t launch_row_batched(int n, int r, int mode, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                              hipStream_t s);
+hipError_t launch_col_batched(int n, int r, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                              hipStream_t s);
+hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, hipStream_t s);
+hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStream_t s);
+hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s);
+hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+hipError_t launch_adj_tail(const AdjInst *inst, int count, int nrow, int k, hipStream_t s);
+hipError_t launch_pair_sums(const float2 *const *a, const float2 *const *b, size_t npts, int count, int per_inst,
+                            double *out, hipStream_t s);
+hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, const double2 *coef, size_t npts,
+                              int count, int per_inst, hipStream_t s);
+bool lds_supported(int nx, int ny);
+int lds_threads(int nx, int ny);
+int kernel_radix();
+size_t xchg_bytes();
+size_t staged_table_bytes(int n);
+}  // namespace gpe
+
+using namespace gpe;
+
+int gpe_fail(int code, const std::string &msg);
+#define fail gpe_fail
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_OK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// Launch shape of the multi-pass path.
+struct Shape {
+    int row_lines, row_threads, row_blocks;
+    size_t row_shmem;
+    int col_cols, col_threads, col_blocks;
+    size_t col_shmem;
+};
+
+struct gpe_plan {
+    int nx = 0, ny = 0;
+    double lx = 0, ly = 0, dt = 0, g = 0;
+    hipStream_t stream = nullptr;
+    size_t max_bytes = 0, bytes = 0;
+    int path = 0;  // 0 auto, 1 multi-pass, 2 LDS
+    int xcd = 1;   // XCD-aware column-tile order
+    std::vector<void *> allocs;
+    DevState *st = nullptr;
+    float4 *tx = nullptr, *ty = nullptr;
+    double2 *kin_x = nullptr, *kin_y = nullptr, *tw_x = nullptr, *tw_y = nullptr;
+    double *kim_x = nullptr, *kim_y = nullptr;
+    double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
+    int npart_max = 0;
+    float2 *scratch = nullptr;
+    double *knots_x = nullptr, *knots_y = nullptr;
+    int knots_cap_x = 0, knots_cap_y = 0;
+    GridDev grid{};
+    PotDev pot{};
+    Shape shape{};
+    bool have_theta = false;
+    // pass timing (instrumentation)
+    int timing_every = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pairs;  // (kind 0 col / 1 row, index of start event)
+};
+
+hipEvent_t *timing_pair(gpe_plan *p, int kind);
+int dalloc(gpe_plan *p, void **ptr, size_t bytes);
+Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles);
+

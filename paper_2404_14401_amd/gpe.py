@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgpe.so")
+# GPE_LIB_PATH selects another build of the same library (kernel-variant tuning runs).
+LIB_PATH = os.environ.get("GPE_LIB_PATH") or os.path.join(_HERE, "libgpe.so")
 
 OK = 0
 ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONFINITE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
@@ -29,7 +30,8 @@ EXPORTS = (
     "gpe_plan_create", "gpe_plan_destroy", "gpe_set_potential", "gpe_step_real", "gpe_step_imag",
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
-    "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_adjoint",
+    "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
+    "gpe_adjoint",
 )
 
 
@@ -90,6 +92,8 @@ def lib():
         L.gpe_batch_create.argtypes = [C.POINTER(P), I, P, P]
         L.gpe_batch_destroy.argtypes = [P]
         L.gpe_step_batched.argtypes = [P, P, I64, D]
+        L.gpe_batch_tune.argtypes = [P, C.c_char_p]
+        L.gpe_batch_info.argtypes = [P, I, P]
         L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, D, P, P, P, P]
         for name in EXPORTS:
             if name != "gpe_last_error":
@@ -220,3 +224,76 @@ class Plan:
         out = (C.c_double * 4)()
         check(lib().gpe_get_timing(self._h, out))
         return {"col_ms": out[0], "col_n": int(out[1]), "row_ms": out[2], "row_n": int(out[3])}
+
+
+class Batch:
+    """Many independent condensates (sizes may differ, dt shared) advanced together."""
+
+    def __init__(self, setups, stream=None):
+        n = len(setups)
+        descs = (PlanDesc * n)()
+        pots = (PotentialDesc * n)()
+        self._keep = []
+        sh = _stream_handle(stream)
+        for i, s in enumerate(setups):
+            descs[i] = PlanDesc(s.nx, s.ny, s.lx, s.ly, s.dt, s.g, sh, 0)
+            d, keep = potential_desc(s)
+            pots[i] = d
+            self._keep.append(keep)
+        h = C.c_void_p()
+        check(lib().gpe_batch_create(C.byref(h), n, descs, pots))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gpe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, psis):
+        if len(psis) != self.n:
+            raise ValueError(f"expected {self.n} wave functions")
+        return (C.c_void_p * self.n)(*[_ptr(p) for p in psis])
+
+    def step(self, psis, nsteps: int, t0: float = 0.0):
+        arr = self._ptrs(psis)
+        check(lib().gpe_step_batched(self._h, arr, int(nsteps), float(t0)))
+
+    def tune(self, cache_path: str | None = None):
+        check(lib().gpe_batch_tune(self._h, cache_path.encode() if cache_path else None))
+
+    def groups(self) -> list[dict]:
+        out = (C.c_int * 8)()
+        check(lib().gpe_batch_info(self._h, 0, out))
+        res = []
+        for g in range(out[7]):
+            check(lib().gpe_batch_info(self._h, g, out))
+            res.append(dict(nx=out[0], ny=out[1], members=out[2], lds=bool(out[3]), radix=out[4],
+                            row_threads=out[5], col_blocks=out[6]))
+        return res
+
+
+def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, mode: str = "auto",
+            drift_tol: float = 1e-4, psi_finals=None):
+    """Loss 1 - |<target|psi(T)>|^2 and its gradient w.r.t. the x-lattice knot values of
+    every batch member (discrete adjoint on the GPU).  knots: array (n, M).
+    Returns (loss[n], grad[n, M], info dict)."""
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    n, m = k.shape
+    if n != batch.n:
+        raise ValueError("one row of knots per batch member")
+    loss = np.zeros(n)
+    grad = np.zeros((n, m))
+    info = np.zeros(4)
+    fin = batch._ptrs(psi_finals) if psi_finals is not None else None
+    check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), batch._ptrs(targets), int(nsteps), float(t0),
+                            k.ctypes.data, m, LOSS["fidelity"], ADJ_MODE[mode], float(drift_tol),
+                            loss.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
+    return loss, grad, {"mode": {1: "reconstruct", 2: "checkpoint"}[int(info[0])], "drift": info[1],
+                        "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}

@@ -1,0 +1,94 @@
+"""GPU adjoint: gradient of the final-state infidelity w.r.t. lattice-depth knots,
+against the FP64 oracle adjoint and central finite differences of the GPU loss."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem
+from tests.gpu_util import to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def control_setup(b, n=64, nknots=8, nsteps=60, dt=0.005):
+    knots = np.random.Generator(np.random.PCG64(100 + b)).uniform(0.0, 15.0, size=nknots)
+    return W.Setup(nx=n, ny=n, lx=16.0, ly=16.0, dt=dt, g=300.0, kx_lat=2.0,
+                   sx=W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots))
+
+
+def states(s, b):
+    psi0 = W.to_c64(W.gaussian(s, 1.2, 0.2 * b, 0.0))
+    tgt = W.to_c64(W.gaussian(s, 0.9, -0.3, 0.1))
+    return psi0, tgt
+
+
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+def test_adjoint_matches_oracle(mode):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nsteps, nb = 60, 2
+    setups = [control_setup(b, nsteps=nsteps) for b in range(nb)]
+    batch = gpe.Batch(setups)
+    p0, tg = zip(*[states(s, b) for b, s in enumerate(setups)])
+    knots = np.stack([s.sx.knots for s in setups])
+    loss, grad, info = gpe.adjoint(batch, [to_dev(p) for p in p0], [to_dev(t) for t in tg], nsteps, knots,
+                                   mode=mode)
+    assert info["mode"] == mode
+    assert info["drift"] < 1e-4
+    for b, s in enumerate(setups):
+        l_ref, g_ref, _ = O.adjoint(problem(s), 0.0, p0[b], tg[b], nsteps)
+        assert abs(loss[b] - l_ref) < 1e-5
+        assert np.linalg.norm(grad[b] - g_ref) / np.linalg.norm(g_ref) < 1e-3
+
+
+def test_adjoint_matches_gpu_finite_differences_and_autograd():
+    torch = torch_cuda()
+    from paper_2404_14401_amd import autograd as A
+    from paper_2404_14401_amd import gpe
+
+    nsteps = 60
+    s = control_setup(0, nsteps=nsteps)
+    batch = gpe.Batch([s])
+    p0, tg = states(s, 0)
+    d0, dt_ = [to_dev(p0)], [to_dev(tg)]
+    knots = torch.tensor(s.sx.knots[None, :], dtype=torch.float64, requires_grad=True)
+    loss = A.control_loss(knots, batch, d0, dt_, nsteps)
+    loss.sum().backward()
+    g = knots.grad.numpy()[0]
+    h = 1e-3
+    for m in (0, 3, 7):
+        kp, km = s.sx.knots.copy(), s.sx.knots.copy()
+        kp[m] += h
+        km[m] -= h
+        lp, _, _ = gpe.adjoint(batch, d0, dt_, nsteps, kp[None, :])
+        lm, _, _ = gpe.adjoint(batch, d0, dt_, nsteps, km[None, :])
+        fd = (lp[0] - lm[0]) / (2 * h)
+        assert abs(g[m] - fd) <= 2e-3 * np.abs(g).max() + 1e-6, (m, g[m], fd)
+
+
+def test_lattice_without_wavenumber_gives_zero_gradient():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nsteps = 40
+    s = control_setup(0, nsteps=nsteps).with_(kx_lat=0.0)
+    batch = gpe.Batch([s])
+    p0, tg = states(s, 0)
+    loss, grad, _ = gpe.adjoint(batch, [to_dev(p0)], [to_dev(tg)], nsteps, s.sx.knots[None, :])
+    assert np.abs(grad).max() < 1e-5
+
+
+def test_auto_falls_back_to_checkpoints_when_drift_tolerance_is_zero():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nsteps = 30
+    s = control_setup(1, nsteps=nsteps)
+    batch = gpe.Batch([s])
+    p0, tg = states(s, 1)
+    a = gpe.adjoint(batch, [to_dev(p0)], [to_dev(tg)], nsteps, s.sx.knots[None, :], mode="auto", drift_tol=0.0)
+    assert a[2]["mode"] == "checkpoint" and a[2]["forward_steps"] == 2 * nsteps
+    r = gpe.adjoint(batch, [to_dev(p0)], [to_dev(tg)], nsteps, s.sx.knots[None, :], mode="reconstruct")
+    assert np.linalg.norm(a[1] - r[1]) / np.linalg.norm(r[1]) < 1e-4

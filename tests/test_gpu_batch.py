@@ -1,0 +1,85 @@
+"""Batched propagation: every member must equal the plain solver on the same
+parameters (same kernels' arithmetic) and the FP64 oracle within the parity bar."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, state
+from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def small_sweep(seed=0):
+    """A reduced mixed-size sweep with the same recipe as the 208-member one."""
+    return W.sweep_208(seed, counts=(3, 2, 1))
+
+
+def members_psi0(setups):
+    return [W.to_c64(W.gaussian(s, 1.0)) for s in setups]
+
+
+@pytest.mark.parametrize("nsteps", [1, 7, 180])
+def test_batch_members_match_plain_solver_and_oracle(nsteps):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = small_sweep()
+    psi0 = members_psi0(setups)
+    b = gpe.Batch(setups)
+    groups = b.groups()
+    assert {(g["nx"], g["lds"]) for g in groups} == {(128, True), (256, False), (512, False)}
+    devs = [to_dev(p) for p in psi0]
+    b.step(devs, nsteps, 0.0)
+    for i, s in enumerate(setups):
+        plain = gpe.Plan.from_setup(s)
+        d = to_dev(psi0[i])
+        plain.step_real(d, nsteps, 0.0)
+        out = to_host(devs[i])
+        assert rel_l2(out, to_host(d)) < 1e-6, i
+        if s.nx <= 256 or nsteps < 100:
+            ref, _ = O.step_real(problem(s), state(s), psi0[i], nsteps)
+            assert rel_l2(out, ref) < 1e-4, i
+
+
+def test_batch_calls_compose_and_graph_replay_matches_direct_launches():
+    """A long call (graph-replayed chunks) equals the same steps split into short
+    calls (direct launches), with time carried by t0."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = small_sweep(1)
+    psi0 = members_psi0(setups)
+    b = gpe.Batch(setups)
+    a_dev = [to_dev(p) for p in psi0]
+    b.step(a_dev, 230, 0.0)
+    b2 = gpe.Batch(setups)
+    c_dev = [to_dev(p) for p in psi0]
+    t = 0.0
+    for k in (10, 40, 180):
+        b2.step(c_dev, k, t)
+        t += k * setups[0].dt
+    for i in range(len(setups)):
+        assert rel_l2(to_host(a_dev[i]), to_host(c_dev[i])) < 1e-5, i
+
+
+def test_batch_tune_keeps_results_and_writes_cache(tmp_path):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = small_sweep(2)
+    psi0 = members_psi0(setups)
+    b = gpe.Batch(setups)
+    cache = str(tmp_path / "tune.txt")
+    b.tune(cache)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 2  # one line per multi-pass size group
+    devs = [to_dev(p) for p in psi0]
+    b.step(devs, 60, 0.0)
+    for i, s in enumerate(setups):
+        ref, _ = O.step_real(problem(s), state(s), psi0[i], 60)
+        assert rel_l2(to_host(devs[i]), ref) < 1e-4
+    b2 = gpe.Batch(setups)
+    b2.tune(cache)  # read back from the cache
+    assert [g["radix"] for g in b2.groups()] == [g["radix"] for g in b.groups()]
