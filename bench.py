@@ -77,6 +77,99 @@ def cpu_baseline(setup, psi0, budget_s: float):
     }
 
 
+def bench_batched(steps: int, tune_cache: str | None):
+    """The 208-member mixed-size sweep (128 x 128^2, 64 x 256^2, 16 x 512^2, dx = 0.125,
+    lattice depth and g from seed 0): one batched call vs looping the plain solver."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    setups = W.sweep_208(0)
+    psis = [torch.from_numpy(W.to_c64(W.gaussian(s, 1.0))).to("cuda") for s in setups]
+    pts = sum(s.nx * s.ny for s in setups)
+    b = gpe.Batch(setups)
+    t = time.perf_counter()
+    b.tune(tune_cache)
+    tune_s = time.perf_counter() - t
+    b.step(psis, 60, 0.0)  # warm-up: kernels loaded, step graph captured
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    b.step(psis, steps, 0.0)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_b = ev0.elapsed_time(ev1) / 1e3
+    plans = [gpe.Plan.from_setup(s) for s in setups]
+    for p, x in zip(plans, psis):
+        p.step_real(x, 2, 0.0)
+    torch.cuda.synchronize()
+    ev0.record()
+    for p, x in zip(plans, psis):
+        p.step_real(x, steps, 0.0)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_p = ev0.elapsed_time(ev1) / 1e3
+    return {
+        "workload": "208 real-time condensates (128 x 128^2, 64 x 256^2, 16 x 512^2), trap + 2D lattice, "
+                    "per-member depth U[0,20] and g U[50,1000] from seed 0, dt=5e-4, c64 state",
+        "steps": steps,
+        "value": pts * steps / t_b,
+        "unit": "grid-point-steps/s",
+        "plain_loop_value": pts * steps / t_p,
+        "speedup_vs_plain_loop": t_p / t_b,
+        "groups": b.groups(),
+        "tune_s": tune_s,
+    }
+
+
+def bench_adjoint(steps: int, nb: int):
+    """Optimal-control gradient: nb members at 512^2, `steps` real-time steps, lattice
+    depth over 200 knots from PCG64(member), g = 300; loss = 1 - |<target|psi(T)>|^2 with
+    the target the ground state at V0 = 15.  Forward alone vs forward + reverse."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    setups = [W.control_512(b, nsteps=steps) for b in range(nb)]
+    s0 = setups[0]
+    # ground states on the GPU (imaginary time): psi(0) at V0 = 0, target at V0 = 15
+    gs = s0.with_(dt=0.01, sx=W.Schedule("const", 0.0))
+    tg = s0.with_(dt=0.01, sx=W.Schedule("const", 15.0))
+    states = []
+    for s in (gs, tg):
+        p = gpe.Plan.from_setup(s)
+        x = torch.from_numpy(W.to_c64(W.gaussian(s, 1.5))).to("cuda")
+        p.step_imag(x, 800, 0.0)
+        states.append(x)
+    psi0 = [states[0].clone() for _ in range(nb)]
+    tgts = [states[1] for _ in range(nb)]
+    knots = np.stack([s.sx.knots for s in setups])
+    b = gpe.Batch(setups)
+    gpe.adjoint(b, psi0, tgts, 20, knots[:, :], mode="reconstruct")  # warm-up
+    work = [x.clone() for x in psi0]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.step(work, steps, 0.0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    out = {"workload": f"{nb} x 512^2 real-time control problems, {steps} steps, dt=5e-4, 200 knots, g=300",
+           "steps": steps, "forward_s": t_fwd}
+    for mode in ("reconstruct", "checkpoint"):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        loss, grad, info = gpe.adjoint(b, psi0, tgts, steps, knots, mode=mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[mode] = {"forward_plus_reverse_s": dt, "ratio_to_forward": dt / t_fwd, "drift": info["drift"],
+                     "workspace_bytes": info["workspace_bytes"], "mean_loss": float(np.mean(loss)),
+                     "grad_norm": float(np.linalg.norm(grad))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +178,10 @@ def main() -> int:
     ap.add_argument("--timing-every", type=int, default=16,
                     help="bracket every k-th step's passes with HIP events (roofline)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0: skip)")
+    ap.add_argument("--batched-steps", type=int, default=200, help="steps of the 208-member sweep (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=5000, help="steps of the control gradient (0: skip)")
+    ap.add_argument("--adjoint-batch", type=int, default=16)
+    ap.add_argument("--tune-cache", default=os.path.join(HERE, "profiles", "tune_cache.txt"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -180,6 +277,12 @@ def main() -> int:
                           "frac": 2 * B_PASS * value / (HBM_PEAK_GBS * 1e9)},
         "wall_s": wall,
     }
+    if args.batched_steps > 0:
+        log("batched sweep ...")
+        out["batched"] = bench_batched(args.batched_steps, args.tune_cache)
+    if args.adjoint_steps > 0:
+        log("adjoint ...")
+        out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
     if args.cpu_budget > 0:
         log(f"timing the oracle for ~{args.cpu_budget:.0f} s ...")
         out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget)
