@@ -16,6 +16,8 @@
 // pass (or by the tail kernel), which also advances the cavity field.
 //
 // LDS path (nx ny <= 16384): the whole grid stays in one work-group's LDS for all steps.
+#include <hip/hip_ext.h>
+
 #include "fft_engine.h"
 #include "physics.h"
 
@@ -541,8 +543,10 @@ __global__ void __launch_bounds__((NX * NY / kLdsRadix) < 1024 ? NX * NY / kLdsR
 }
 
 // ------------------------------------------------------------------- launchers
+// With e0/e1, the launch records the kernel's own start and end in those events
+// (hipExtLaunchKernel), which times the kernel without extra queue markers.
 template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowArgs &a, int blocks, int threads,
-                                                size_t shmem, hipStream_t s)
+                                                size_t shmem, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
 #define GPE_ROW(M, I)                                                                              \
     do {                                                                                           \
@@ -553,7 +557,10 @@ template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowAr
             if (e_ != hipSuccess) return e_;                                                       \
             attr_ = true;                                                                          \
         }                                                                                          \
-        hipLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), shmem, s, a);         \
+        if (e0)                                                                                    \
+            hipExtLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), (uint32_t)shmem, s, e0, e1, 0, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), shmem, s, a);     \
     } while (0)
     if (imag) {
         if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, true);
@@ -571,24 +578,24 @@ template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowAr
 }
 
 hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
-                      hipStream_t s)
+                      hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     switch (n) {
-    case 16: return row_dispatch<16>(mode, imag, a, blocks, threads, shmem, s);
-    case 32: return row_dispatch<32>(mode, imag, a, blocks, threads, shmem, s);
-    case 64: return row_dispatch<64>(mode, imag, a, blocks, threads, shmem, s);
-    case 128: return row_dispatch<128>(mode, imag, a, blocks, threads, shmem, s);
-    case 256: return row_dispatch<256>(mode, imag, a, blocks, threads, shmem, s);
-    case 512: return row_dispatch<512>(mode, imag, a, blocks, threads, shmem, s);
-    case 1024: return row_dispatch<1024>(mode, imag, a, blocks, threads, shmem, s);
-    case 2048: return row_dispatch<2048>(mode, imag, a, blocks, threads, shmem, s);
-    case 4096: return row_dispatch<4096>(mode, imag, a, blocks, threads, shmem, s);
+    case 16: return row_dispatch<16>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 32: return row_dispatch<32>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 64: return row_dispatch<64>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 128: return row_dispatch<128>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 256: return row_dispatch<256>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 512: return row_dispatch<512>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 1024: return row_dispatch<1024>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 2048: return row_dispatch<2048>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 4096: return row_dispatch<4096>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int blocks, int threads, size_t shmem,
-                                                hipStream_t s)
+                                                hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
 #define GPE_COL(M)                                                                                 \
     do {                                                                                           \
@@ -599,7 +606,10 @@ template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int 
             if (e_ != hipSuccess) return e_;                                                       \
             attr_ = true;                                                                          \
         }                                                                                          \
-        hipLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), shmem, s, a);            \
+        if (e0)                                                                                    \
+            hipExtLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), (uint32_t)shmem, s, e0, e1, 0, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), shmem, s, a);        \
     } while (0)
     if (mode == COL_KIN_REAL) GPE_COL(COL_KIN_REAL);
     else if (mode == COL_KIN_IMAG) GPE_COL(COL_KIN_IMAG);
@@ -609,18 +619,19 @@ template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int 
     return hipGetLastError();
 }
 
-hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
+hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1)
 {
     switch (n) {
-    case 16: return col_dispatch<16>(mode, a, blocks, threads, shmem, s);
-    case 32: return col_dispatch<32>(mode, a, blocks, threads, shmem, s);
-    case 64: return col_dispatch<64>(mode, a, blocks, threads, shmem, s);
-    case 128: return col_dispatch<128>(mode, a, blocks, threads, shmem, s);
-    case 256: return col_dispatch<256>(mode, a, blocks, threads, shmem, s);
-    case 512: return col_dispatch<512>(mode, a, blocks, threads, shmem, s);
-    case 1024: return col_dispatch<1024>(mode, a, blocks, threads, shmem, s);
-    case 2048: return col_dispatch<2048>(mode, a, blocks, threads, shmem, s);
-    case 4096: return col_dispatch<4096>(mode, a, blocks, threads, shmem, s);
+    case 16: return col_dispatch<16>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 32: return col_dispatch<32>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 64: return col_dispatch<64>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 128: return col_dispatch<128>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 256: return col_dispatch<256>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 512: return col_dispatch<512>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 1024: return col_dispatch<1024>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 2048: return col_dispatch<2048>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 4096: return col_dispatch<4096>(mode, a, blocks, threads, shmem, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

@@ -366,16 +366,13 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         ca.do_tail = (ta.npartials > 0 || ta.advance_alpha) ? 1 : 0;
         const bool timed = p->timing_every > 0 && n % p->timing_every == 0 && n + 1 < nsteps;
         hipEvent_t *ec = timed ? timing_pair(p, 0) : nullptr;
-        if (ec) HIP_OK(hipEventRecord(ec[0], p->stream));
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
-        if (ec) HIP_OK(hipEventRecord(ec[1], p->stream));
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream,
+                             ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
         ra.n = (int)n;
         ra.reduce = red ? 1 : 0;
         hipEvent_t *er = timed ? timing_pair(p, 1) : nullptr;
-        if (er) HIP_OK(hipEventRecord(er[0], p->stream));
         LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, ra, sh.row_blocks, sh.row_threads,
-                             sh.row_shmem, p->stream));
-        if (er) HIP_OK(hipEventRecord(er[1], p->stream));
+                             sh.row_shmem, p->stream, er ? er[0] : nullptr, er ? er[1] : nullptr));
     }
     if (red) {
         TailArgs ta{};

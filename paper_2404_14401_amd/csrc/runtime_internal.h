@@ -12,8 +12,9 @@
 
 namespace gpe {
 hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
-                      hipStream_t s);
-hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+                      hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
 hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
 hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);

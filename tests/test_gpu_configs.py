@@ -1,0 +1,164 @@
+"""Full-size workloads on the GPU against the FP64 oracle, at their own step counts.
+
+* dipole + lattice ramp, 256^2, 1e4 steps: psi and energy vs the oracle, norm, the
+  Kohn dipole closed form, energy drift once the Hamiltonian is constant;
+* cavity, 1024^2, 2e4 steps: sampled final state, energy and the cavity field vs the
+  stored oracle run (tests/golden, written by make_cavity_1024.py);
+* 208-member sweep, 5000 steps: sampled members vs the plain solver and the oracle;
+* 16 x 512^2 control gradient, 5000 steps: GPU finite differences, reconstruction drift,
+  and the oracle adjoint on a shorter horizon.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, state
+from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel_e(a, b):
+    return abs(a - b) / abs(b)
+
+
+@pytest.fixture(scope="module")
+def dipole_start():
+    s = W.dipole_lattice_256()
+    s0 = s.with_(y0=0.0, sx=W.Schedule("const", 0.0), dt=0.005)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.thomas_fermi_guess(s0, float(np.sqrt(s.g / np.pi))), 3000)
+    return s, W.to_c64(gs)
+
+
+def test_dipole_lattice_256_full_length(dipole_start):
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s, psi0 = dipole_start
+    n = W.DIPOLE_256_STEPS
+    ref, robs = O.step_real(problem(s), state(s), psi0, n, want_obs=True)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    half = n // 2
+    plan.step_real(d, half, 0.0, obs[:half])
+    e_mid = plan.energy(d, half * s.dt)["e"]
+    plan.step_real(d, n - half, half * s.dt, obs[half:])
+    out = to_host(d)
+    assert rel_l2(out, ref) < 1e-4
+    e_end = plan.energy(d, n * s.dt)["e"]
+    assert rel_e(e_end, O.energy(problem(s), ref, n * s.dt)["e"]) < 1e-5
+    # lattice constant after step 5000: the energy is conserved
+    assert rel_e(e_end, e_mid) < 1e-5
+    o = obs.cpu().numpy()
+    assert np.abs(o[:, 0] - 1.0).max() < 1e-5
+    # Kohn: the y dipole follows the discrete leapfrog exactly in the continuum
+    t = s.dt * np.arange(1, n + 1)
+    wd = np.arccos(1 - s.dt**2 / 2) / s.dt
+    kohn = s.y0 * (1 - np.cos(wd * t))
+    assert np.abs(o[:, 5] - kohn).max() < 1e-4
+    assert np.abs(o[:, 5] - robs[:, 5]).max() < 1e-5
+
+
+def test_cavity_1024_full_length_against_stored_oracle_run():
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    path = os.path.join(HERE, "golden", "cavity_1024_seed0.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated (tests/golden/make_cavity_1024.py)")
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("make_cavity_1024", os.path.join(HERE, "golden", "make_cavity_1024.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    g = np.load(path)
+    s = W.cavity_1024(int(g["seed"]))
+    n = int(g["nsteps"])
+    psi0 = mk.start_state(s)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, n, 0.0, obs)
+    out = to_host(d)
+    sub = int(g["sub"])
+    assert rel_l2(out[::sub, ::sub], g["psi_sub"]) < 1e-4
+    alpha = plan.cavity()["alpha"]
+    e = plan.energy(d, n * s.dt)
+    assert rel_e(e["e"], g["energy"][3]) < 1e-5
+    o = obs.cpu().numpy()
+    a_gpu = o[99::100, 2] + 1j * o[99::100, 3]
+    assert np.abs(a_gpu - g["alpha"]).max() <= 1e-4 * max(np.abs(g["alpha"]).max(), 1e-3)
+    assert abs(alpha - g["alpha"][-1]) <= 1e-4 * max(abs(g["alpha"][-1]), 1e-3)
+    assert np.abs(o[99::100, 1] - g["theta"]).max() < 1e-5
+
+
+def test_sweep_208_full_length_sampled_members():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = W.sweep_208(0)
+    psi0 = [W.to_c64(W.gaussian(s, 1.0)) for s in setups]
+    devs = [to_dev(p) for p in psi0]
+    b = gpe.Batch(setups)
+    n = W.SWEEP_STEPS
+    b.step(devs, n, 0.0)
+    for i in (0, 127, 128, 191, 192, 207):
+        s = setups[i]
+        plain = gpe.Plan.from_setup(s)
+        d = to_dev(psi0[i])
+        plain.step_real(d, n, 0.0)
+        out = to_host(devs[i])
+        assert rel_l2(out, to_host(d)) < 1e-5, i
+        if s.nx <= 256 and i in (0, 191):
+            ref, _ = O.step_real(problem(s), state(s), psi0[i], n)
+            assert rel_l2(out, ref) < 1e-4, i
+
+
+def test_control_512_full_size_gradient():
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nb, n = W.CONTROL_BATCH, W.CONTROL_STEPS
+    setups = [W.control_512(b) for b in range(nb)]
+    s0 = setups[0]
+    gs = s0.with_(dt=0.01, sx=W.Schedule("const", 0.0))
+    tg = s0.with_(dt=0.01, sx=W.Schedule("const", 15.0))
+    st = []
+    for s in (gs, tg):
+        p = gpe.Plan.from_setup(s)
+        x = to_dev(W.to_c64(W.gaussian(s, 1.5)))
+        p.step_imag(x, 800, 0.0)
+        st.append(x)
+    psi0 = [st[0].clone() for _ in range(nb)]
+    tgts = [st[1] for _ in range(nb)]
+    knots = np.stack([s.sx.knots for s in setups])
+    b = gpe.Batch(setups)
+    loss, grad, info = gpe.adjoint(b, psi0, tgts, n, knots, mode="auto", drift_tol=1e-4)
+    assert info["mode"] == "reconstruct" and info["drift"] < 1e-4
+    # central differences of the GPU loss on sampled knots of member 3; over 5000 steps
+    # the complex64 loss carries ~1e-6 of trajectory rounding noise, so the step is
+    # 0.05 (truncation ~h^2) rather than 1e-3 (noise / 2h would exceed the gradient)
+    h = 0.05
+    for m in (10, 100, 190):
+        kp, km = knots.copy(), knots.copy()
+        kp[3, m] += h
+        km[3, m] -= h
+        lp, _, _ = gpe.adjoint(b, psi0, tgts, n, kp)
+        lm, _, _ = gpe.adjoint(b, psi0, tgts, n, km)
+        fd = (lp[3] - lm[3]) / (2 * h)
+        assert abs(grad[3, m] - fd) <= 3e-2 * np.abs(grad[3]).max(), (m, grad[3, m], fd)
+    # the oracle adjoint on the same grid over a shorter horizon (200 steps, 20 knots)
+    ns = 200
+    sh = W.control_512(5, nknots=20, nsteps=ns)
+    p0 = to_host(st[0]).astype(np.complex64)
+    t0 = to_host(st[1]).astype(np.complex64)
+    bs = gpe.Batch([sh])
+    l_g, g_g, _ = gpe.adjoint(bs, [to_dev(p0)], [to_dev(t0)], ns, sh.sx.knots[None, :], mode="reconstruct")
+    l_o, g_o, _ = O.adjoint(problem(sh), 0.0, p0, t0, ns)
+    assert abs(l_g[0] - l_o) < 1e-5
+    assert np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o) < 1e-3
