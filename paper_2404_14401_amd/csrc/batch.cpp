@@ -36,6 +36,21 @@ struct BGroup {
     std::vector<LdsArgs> h_lds;
 };
 
+struct AdjWork {
+    int nx = 0, ny = 0, nb = 0;
+    int64_t cap_steps = 0;
+    std::vector<float2 *> psi, lam;
+    std::vector<double *> kick_grad, partials;
+    std::vector<float2 *> ckpt;  // [slot * nb + member]
+    int ckpt_slots = 0;
+    AdjInst *d_adj = nullptr;
+    InstDesc *d_fwd = nullptr;
+    const float2 **d_pa = nullptr, **d_pb = nullptr;
+    float2 **d_dst = nullptr;
+    double2 *d_coef = nullptr;
+    double *d_sums = nullptr;
+    size_t bytes = 0;
+};
 }  // namespace
 
 struct gpe_batch {
@@ -53,6 +68,7 @@ struct gpe_batch {
     hipGraph_t graph_def = nullptr;
     int chunk = 50;
     bool warmed = false;
+    AdjWork *adj = nullptr;  // adjoint workspace, created by the first gpe_adjoint call
 };
 
 static int balloc(gpe_batch *b, void **p, size_t bytes)
@@ -234,6 +250,7 @@ int gpe_batch_destroy(gpe_batch *b)
     if (b->work) (void)hipStreamSynchronize(b->work);
     if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(b);
+    delete b->adj;
     for (gpe_plan *p : b->plans) gpe_plan_destroy(p);
     for (void *a : b->allocs) (void)hipFree(a);
     for (hipEvent_t e : {b->ev_in, b->ev_fork, b->ev_side, b->ev_out})
@@ -429,33 +446,12 @@ int gpe_batch_info(gpe_batch *b, int group, int out[8])
 
 // --------------------------------------------------------------------- adjoint
 
-namespace {
-struct AdjWork {
-    int nx = 0, ny = 0, nb = 0;
-    int64_t cap_steps = 0;
-    std::vector<float2 *> psi, lam;
-    std::vector<double *> kick_grad, partials;
-    std::vector<float2 *> ckpt;  // [slot * nb + member]
-    int ckpt_slots = 0;
-    AdjInst *d_adj = nullptr;
-    InstDesc *d_fwd = nullptr;
-    const float2 **d_pa = nullptr, **d_pb = nullptr;
-    float2 **d_dst = nullptr;
-    double2 *d_coef = nullptr;
-    double *d_sums = nullptr;
-    size_t bytes = 0;
-};
-}  // namespace
 
-static std::vector<std::pair<gpe_batch *, AdjWork *>> g_adj;  // one workspace per batch
-
+// The batch owns its adjoint workspace (its device buffers are in b->allocs).
 static AdjWork *adj_work(gpe_batch *b)
 {
-    for (auto &p : g_adj)
-        if (p.first == b) return p.second;
-    AdjWork *w = new AdjWork();
-    g_adj.push_back({b, w});
-    return w;
+    if (!b->adj) b->adj = new AdjWork();
+    return b->adj;
 }
 
 // Hat weights of the piecewise-linear schedule at time t (same clamping as the device).
@@ -582,15 +578,15 @@ static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     const int rblocks = sh.row_blocks * nb, cblocks = sh.col_blocks * nb;
     ca.xcd_swizzle = (cblocks % 8 == 0 && cblocks >= 64) ? 1 : 0;
     // rows need 2 arrays' worth of registers: at most 256 threads per work-group
+    const size_t rsh = adj_row_shmem(w->nx, sh.row_lines, 8), csh = adj_col_shmem(w->ny, sh.col_cols, 8);
     ra.kick = (int)n1;
-    LAUNCH_OK(launch_row_adj(w->nx, ADJ_FIRST, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+    LAUNCH_OK(launch_row_adj(w->nx, ADJ_FIRST, ra, rblocks, sh.row_threads, rsh, b->work));
     int pending = (int)n1;
     for (int64_t n = n1 - 1; n >= n0; --n) {
         ca.tail_kick = pending;
-        LAUNCH_OK(launch_col_adj(w->ny, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
+        LAUNCH_OK(launch_col_adj(w->ny, ca, cblocks, sh.col_threads, csh, b->work));
         ra.kick = (int)n;
-        LAUNCH_OK(launch_row_adj(w->nx, n > n0 ? ADJ_MID : ADJ_LAST, ra, rblocks, sh.row_threads, sh.row_shmem,
-                                 b->work));
+        LAUNCH_OK(launch_row_adj(w->nx, n > n0 ? ADJ_MID : ADJ_LAST, ra, rblocks, sh.row_threads, rsh, b->work));
         pending = (int)n;
     }
     LAUNCH_OK(launch_adj_tail(w->d_adj, nb, sh.row_blocks, pending, b->work));
@@ -621,6 +617,12 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, 256);
     if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, nx / std::max(1, 512 / (ny / 8)));
     if (sh.col_threads > 512) return fail(GPE_ERR_UNSUPPORTED, "column shape");
+    // the adjoint column pass holds two exchange areas: narrow the tiles until they fit LDS
+    for (int tiles = nx / sh.col_cols * 2; adj_col_shmem(ny, sh.col_cols, 8) > 158 * 1024 && sh.col_cols > 1;
+         tiles *= 2)
+        sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, tiles);
+    if (adj_col_shmem(ny, sh.col_cols, 8) > 158 * 1024 || adj_row_shmem(nx, sh.row_lines, 8) > 158 * 1024)
+        return fail(GPE_ERR_UNSUPPORTED, "adjoint passes exceed the LDS of a work-group");
     AdjWork *w = adj_work(b);
     const int64_t seg = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
     const int64_t nseg = (nsteps + seg - 1) / seg;

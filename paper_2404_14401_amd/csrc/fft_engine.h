@@ -16,6 +16,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#ifndef GPE_TW_POW2
+#define GPE_TW_POW2 1
+#endif
+
 namespace gpe {
 
 template <typename Real> struct cplx_t;
@@ -167,11 +171,29 @@ __device__ __forceinline__ void fft_pass(C (&v)[R], const View &lds, int t, cons
             for (int r = 0; r < Rp; ++r) a[r] = v[q + r * Q];
             if constexpr (Ns > 1) {
                 constexpr int stride = N / (Ns * Rp);
+#if GPE_TW_POW2
+                // powers w^1, w^2, w^4 from the table, the others as FP64 products
+                // (rounding ~1e-16 per product, far below the complex64 storage)
+                C w[Rp];
+                w[1] = tw[j * stride];
+                if constexpr (Rp > 2) w[2] = tw[2 * j * stride];
+                if constexpr (Rp > 4) w[4] = tw[4 * j * stride];
+                if constexpr (Rp > 2) w[3] = cmul(w[1], w[2]);
+                if constexpr (Rp > 4) {
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                }
+                static_assert(Rp <= 8, "power-of-two twiddle reconstruction is written for radix <= 8");
+#pragma unroll
+                for (int r = 1; r < Rp; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
+#else
 #pragma unroll
                 for (int r = 1; r < Rp; ++r) {
                     C w = tw[r * j * stride];
                     a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
                 }
+#endif
             }
             Dft<Rp, INV, C>::run(a);
 #pragma unroll
@@ -199,6 +221,82 @@ template <int N, int R, bool INV, typename C, typename View>
 __device__ __forceinline__ void fft_line(C (&v)[R], const View &lds, int t, const C *__restrict__ tw)
 {
     fft_pass<N, R, INV, 0>(v, lds, t, tw);
+}
+
+
+// Two lines transformed together (same length, same direction, same twiddles): the
+// twiddles are read once and applied to both, the exchanges of both lines share their
+// barriers.  Used by the adjoint passes (state and adjoint move through the same
+// transforms).  lds_b must not overlap lds_a.
+template <int N, int R, bool INV, int PASS, typename C, typename View>
+__device__ __forceinline__ void fft_pass2(C (&v)[R], C (&u)[R], const View &la, const View &lb, int t,
+                                          const C *__restrict__ tw)
+{
+    using S = FftShape<N, R>;
+    if constexpr (PASS < S::NPASS) {
+        constexpr int Rp = (PASS < S::NFULL) ? R : S::RL;
+        constexpr int Q = R / Rp;
+        constexpr int Ns = 1 << (PASS * S::LGR);
+        constexpr int T = S::T;
+        constexpr bool LAST = (PASS == S::NPASS - 1);
+        if constexpr (PASS > 0) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                v[m] = la.template ld<C>(t + m * T);
+                u[m] = lb.template ld<C>(t + m * T);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int uu = t + q * T;
+            const int j = uu & (Ns - 1);
+            C a[Rp], b[Rp];
+#pragma unroll
+            for (int r = 0; r < Rp; ++r) {
+                a[r] = v[q + r * Q];
+                b[r] = u[q + r * Q];
+            }
+            if constexpr (Ns > 1) {
+                constexpr int stride = N / (Ns * Rp);
+#pragma unroll
+                for (int r = 1; r < Rp; ++r) {
+                    C w = tw[r * j * stride];
+                    a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
+                    b[r] = INV ? cmulc(b[r], w) : cmul(b[r], w);
+                }
+            }
+            Dft<Rp, INV, C>::run(a);
+            Dft<Rp, INV, C>::run(b);
+#pragma unroll
+            for (int r = 0; r < Rp; ++r) {
+                v[q + r * Q] = a[r];
+                u[q + r * Q] = b[r];
+            }
+        }
+        if constexpr (!LAST) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int uu = t + q * T;
+                const int j = uu & (Ns - 1);
+                const int base = (uu / Ns) * Ns * Rp + j;
+#pragma unroll
+                for (int r = 0; r < Rp; ++r) {
+                    la.st(base + r * Ns, v[q + r * Q]);
+                    lb.st(base + r * Ns, u[q + r * Q]);
+                }
+            }
+            __syncthreads();
+            fft_pass2<N, R, INV, PASS + 1>(v, u, la, lb, t, tw);
+        }
+    }
+}
+
+template <int N, int R, bool INV, typename C, typename View>
+__device__ __forceinline__ void fft_line2(C (&v)[R], C (&u)[R], const View &la, const View &lb, int t,
+                                          const C *__restrict__ tw)
+{
+    fft_pass2<N, R, INV, 0>(v, u, la, lb, t, tw);
 }
 
 // LDS accessors: ld<C>(i) / st(i, v) convert between the arithmetic type C and the

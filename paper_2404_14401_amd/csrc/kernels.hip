@@ -29,10 +29,10 @@ namespace gpe {
 #define GPE_RADIX 8
 #endif
 #ifndef GPE_XCHG_FLOAT
-#define GPE_XCHG_FLOAT 0
+#define GPE_XCHG_FLOAT 1
 #endif
 #ifndef GPE_TW_LDS
-#define GPE_TW_LDS 1
+#define GPE_TW_LDS 0
 #endif
 constexpr int kRadix = GPE_RADIX;
 constexpr int kLgR = ilog2(GPE_RADIX);
@@ -69,6 +69,17 @@ int kernel_radix() { return kRadix; }
 size_t xchg_bytes() { return sizeof(XchgT); }
 // extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
 size_t staged_table_bytes(int n) { return GPE_TW_LDS ? (size_t)n * (sizeof(double2) + sizeof(float4)) : 0; }
+// LDS of the adjoint passes: two exchange areas (state and adjoint) plus the tables
+size_t adj_row_shmem(int n, int lines, int r)
+{
+    const size_t words = (size_t)n + (n >> ilog2(r));
+    return align16(2 * lines * words * sizeof(XchgT)) + (size_t)n * (sizeof(double2) + sizeof(float4));
+}
+size_t adj_col_shmem(int n, int w, int r)
+{
+    const size_t words = (size_t)n * w + (n >> ilog2(r)) + w;
+    return align16(2 * words * sizeof(XchgT)) + (size_t)n * 2 * sizeof(double2);
+}
 
 // --------------------------------------------------------------------- row pass
 // One work-group transforms `lines` rows.  `row` is this thread's row; the caller has
@@ -855,7 +866,15 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     const GridDev &gd = I.grid;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int row = lb * lines + line;
-    View lds{smem + line * View::words(N)};
+    // exchange lines: [state lines][adjoint lines], then the staged tables
+    View la{smem + line * View::words(N)};
+    View lb2{smem + (lines + line) * View::words(N)};
+    double2 *s_tw = (double2 *)((char *)smem + align16(2 * lines * View::words(N) * sizeof(XchgT)));
+    float4 *s_tx = (float4 *)(s_tw + N);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s_tw[i] = gd.tw_x[i];
+        s_tx[i] = I.pot.tx[i];
+    }
     float2 *pp = I.psi + (size_t)row * N;
     float2 *pl = I.lam + (size_t)row * N;
     C v[R], w[R];
@@ -865,10 +884,8 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
         v[m] = {(double)a.x, (double)a.y};
         w[m] = {(double)b.x, (double)b.y};
     }
-    if constexpr (MODE != ADJ_FIRST) {
-        fft_line<N, R, true>(v, lds, t, gd.tw_x);
-        fft_line<N, R, true>(w, lds, t, gd.tw_x);
-    }
+    __syncthreads();
+    if constexpr (MODE != ADJ_FIRST) fft_line2<N, R, true>(v, w, la, lb2, t, s_tw);
     const double tk = I.st->t0 + kick * gd.dt;
     const double tau = (MODE == ADJ_MID) ? gd.dt : 0.5 * gd.dt;
     const VLine vl = vline_cav(I.pot, row, tk, 0.0, 0.0);
@@ -877,7 +894,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int i = t + m * T;
-        const float4 tx = I.pot.tx[i];
+        const float4 tx = s_tx[i];
         double V = vpoint(vl, tx);
         if (vu) V += (double)vu[i];
         const double th = (V + gd.g * (v[m].x * v[m].x + v[m].y * v[m].y)) * tau;
@@ -892,10 +909,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     }
     block_sum<1>(part, red);
     if (threadIdx.x == 0) I.partials[lb] = part[0];
-    if constexpr (MODE != ADJ_LAST) {
-        fft_line<N, R, false>(v, lds, t, gd.tw_x);
-        fft_line<N, R, false>(w, lds, t, gd.tw_x);
-    }
+    if constexpr (MODE != ADJ_LAST) fft_line2<N, R, false>(v, w, la, lb2, t, s_tw);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         store_c64(pp + t + m * T, v[m]);
@@ -938,7 +952,15 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
     const int c = threadIdx.x % w, t = threadIdx.x / w;
     const int col = lt * w + c;
     const int nx = gd.nx;
-    View lds{smem + c, w};
+    const size_t words = View::words(N, w);
+    View la{smem + c, w};
+    View lb{smem + words + c, w};
+    double2 *s_tw = (double2 *)((char *)smem + align16(2 * words * sizeof(XchgT)));
+    double2 *s_ky = s_tw + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s_tw[i] = gd.tw_y[i];
+        s_ky[i] = gd.kin_y[i];
+    }
     C v[R], u[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -946,17 +968,16 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
         v[m] = {(double)f.x, (double)f.y};
         u[m] = {(double)h.x, (double)h.y};
     }
-    fft_line<N, R, false>(v, lds, t, gd.tw_y);
-    fft_line<N, R, false>(u, lds, t, gd.tw_y);
+    __syncthreads();
+    fft_line2<N, R, false>(v, u, la, lb, t, s_tw);
     const C kx = gd.kin_x[col];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const C f = cmul(kx, gd.kin_y[t + m * T]);
+        const C f = cmul(kx, s_ky[t + m * T]);
         v[m] = cmulc(v[m], f);
         u[m] = cmulc(u[m], f);
     }
-    fft_line<N, R, true>(v, lds, t, gd.tw_y);
-    fft_line<N, R, true>(u, lds, t, gd.tw_y);
+    fft_line2<N, R, true>(v, u, la, lb, t, s_tw);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         store_c64(I.psi + (size_t)(t + m * T) * nx + col, v[m]);

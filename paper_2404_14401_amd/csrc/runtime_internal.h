@@ -39,6 +39,8 @@ int lds_threads(int nx, int ny);
 int kernel_radix();
 size_t xchg_bytes();
 size_t staged_table_bytes(int n);
+size_t adj_row_shmem(int n, int lines, int r);
+size_t adj_col_shmem(int n, int w, int r);
 }  // namespace gpe
 
 using namespace gpe;

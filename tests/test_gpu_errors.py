@@ -1,0 +1,75 @@
+"""Failure handling on the GPU path: non-finite detection, argument validation of live
+plans, memory cap.  Every condition is forced from the host; no kernel faults."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2404_14401_amd import workloads as W
+from tests.gpu_util import to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def test_nan_in_psi_is_reported_at_the_next_sync():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.cavity_scaled(256, 0)
+    plan = gpe.Plan.from_setup(s)
+    psi = W.to_c64(W.gaussian(s, 1.0))
+    psi[10, 10] = np.nan
+    d = to_dev(psi)
+    plan.step_real(d, 5, 0.0)  # cavity on: the overlap reduction sees the NaN
+    with pytest.raises(gpe.GpeError) as e:
+        plan.sync()
+    assert e.value.code == gpe.ERR_NONFINITE
+
+
+def test_live_plan_validates_arguments():
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.imag_ground_64(0.0)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(W.gaussian(s, 1.0))
+    with pytest.raises(gpe.GpeError) as e:
+        plan.step_real(d, -1, 0.0)
+    assert e.value.code == gpe.ERR_INVALID
+    with pytest.raises(gpe.GpeError):
+        plan.step_real(d, 1, float("inf"))
+    bad = W.Setup(**{**s.__dict__, "sx": W.Schedule("ramp", 0.0, 1.0, 2.0, 1.0)})
+    with pytest.raises(gpe.GpeError):
+        plan.set_potential(bad)
+    with pytest.raises(ValueError):
+        plan.step_real(torch.zeros((64, 64), dtype=torch.complex128, device="cuda"), 1, 0.0)
+
+
+def test_memory_cap_is_enforced():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.Plan(1024, 1024, 64.0, 64.0, 1e-3, 1.0, max_bytes=1 << 20)
+    assert e.value.code == gpe.ERR_NOMEM
+
+
+def test_checkpoint_resume_of_cavity_state_is_bitwise():
+    """Stopping after n steps, saving (psi, alpha, Theta history) and resuming in a
+    fresh plan reproduces the uninterrupted run exactly."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.cavity_scaled(256, 1)
+    psi0 = W.to_c64(W.gaussian(s, 1.0))
+    a = gpe.Plan.from_setup(s)
+    da = to_dev(psi0)
+    a.step_real(da, 40, 0.0)
+    saved_psi = da.clone()
+    cav = a.cavity()
+    a.step_real(da, 40, 40 * s.dt)
+    b = gpe.Plan.from_setup(s)
+    b.set_cavity(cav["alpha"], cav["theta"], cav["theta_prev"], True)
+    b.step_real(saved_psi, 40, 40 * s.dt)
+    assert (da == saved_psi).all()
+    assert b.cavity()["alpha"] == a.cavity()["alpha"]
