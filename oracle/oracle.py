@@ -317,3 +317,28 @@ def adjoint(prob: Problem, t0: float, psi0, target, nsteps: int, ckpt: int = 0, 
     if rc != 0:
         raise ValueError("oracle adjoint: unsupported problem (cavity on or controls not knots)")
     return lossv.value, grad, fin
+
+
+def _step_k(fn, prob: Problem, state: State, psik, nsteps: int, want_obs: bool):
+    p, keep = prob.cstruct()
+    s = state._to_c()
+    out = _c128(psik).copy()
+    assert out.shape == (prob.ny, prob.nx)
+    obs = np.zeros(nsteps) if want_obs else None
+    rc = fn(C.byref(p), C.byref(s), out.ctypes.data, int(nsteps), obs.ctypes.data if want_obs else None)
+    if rc != 0:
+        raise ValueError("the Fourier-space ordering runs without the cavity")
+    state._from_c(s)
+    return out, obs
+
+
+def step_real_k(prob: Problem, state: State, psik, nsteps: int, want_obs: bool = False):
+    """Real-time steps in the T/2-V-T/2 ordering with psi_k = FFT2(psi) kept in Fourier space."""
+    lib().orc_step_real_k.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    return _step_k(lib().orc_step_real_k, prob, state, psik, nsteps, want_obs)
+
+
+def step_imag_k(prob: Problem, state: State, psik, nsteps: int, want_obs: bool = False):
+    """Imaginary-time steps in the T/2-V-T/2 ordering (Fourier-space state)."""
+    lib().orc_step_imag_k.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    return _step_k(lib().orc_step_imag_k, prob, state, psik, nsteps, want_obs)

@@ -399,3 +399,44 @@ def test_lattice_without_wavenumber_is_a_global_phase():
     target = W.gaussian(s, 0.9, -0.2, 0.1)
     _, grad, _ = O.adjoint(problem(s), 0.0, psi0, target, nsteps)
     assert np.abs(grad).max() < 1e-12
+
+
+# ------------------------------- the printed T/2-V-T/2 ordering, Fourier-space state
+
+@pytest.mark.parametrize("dtau", [0.1, 0.05])
+def test_printed_ordering_imaginary_fixed_point(dtau):
+    """With the kinetic halves outside (Sec. 3.1, Eq. 4) the harmonic g = 0 fixed point
+    is exp(-a r^2/2) with a = 1/sqrt(1 + dtau^2/4) (Gaussian map: b -> b/(1 + b dtau/2)
+    for a kinetic half, b -> b + dtau for the kick), i.e. the reciprocal of the
+    V/2-T-V/2 value."""
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dtau, g=0.0)
+    psik = np.fft.fft2(W.gaussian(s, 1.3, 0.2, -0.1))
+    out, _ = O.step_imag_k(problem(s), state(s), psik, int(40 / dtau))
+    a = 1 / np.sqrt(1 + dtau**2 / 4)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    ref = W.normalise(s, np.exp(-a * (x**2 + y**2) / 2).astype(complex))
+    assert rel_l2(np.fft.ifft2(out), ref) < 1e-9
+    assert abs(O.energy(problem(s), np.fft.ifft2(out))["e"] - (a + 1 / a) / 2) < 1e-9
+
+
+def test_printed_ordering_free_flow_and_kohn():
+    s = W.Setup(nx=32, ny=16, lx=12.0, ly=6.0, dt=0.01, g=0.0, wx=0.0, wy=0.0)
+    psi0 = W.gaussian(s, 0.7, 0.5, -0.3) * np.exp(1j * 1.3 * s.xs()[None, :])
+    out, _ = O.step_real_k(problem(s), state(s), np.fft.fft2(psi0), 37)
+    kx = 2 * np.pi * np.fft.fftfreq(s.nx, s.lx / s.nx)
+    ky = 2 * np.pi * np.fft.fftfreq(s.ny, s.ly / s.ny)
+    k2 = kx[None, :] ** 2 + ky[:, None] ** 2
+    assert rel_l2(out, np.fft.fft2(psi0) * np.exp(-0.5j * k2 * 37 * s.dt)) < 1e-13
+    # Kohn with the drift-kick-drift composition: same closed form u_n = u_0 cos(w_d t_n)
+    s0 = W.Setup(nx=64, ny=64, lx=20.0, ly=20.0, dt=0.01)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.gaussian(s0, 1.2), 3000)
+    d, dt = 0.5, 0.02
+    s1 = s0.with_(y0=d, dt=dt)
+    psik = np.fft.fft2(gs)
+    ys = []
+    for _ in range(200):
+        psik, _ = O.step_real_k(problem(s1), state(s1), psik, 1)
+        p = np.fft.ifft2(psik)
+        ys.append(np.sum(np.abs(p) ** 2 * s1.ys()[:, None]) * (s1.lx / s1.nx) * (s1.ly / s1.ny))
+    wd = np.arccos(1 - dt**2 / 2) / dt
+    assert np.abs(np.array(ys) - d * (1 - np.cos(wd * dt * np.arange(1, 201)))).max() < 1e-10
