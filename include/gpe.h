@@ -73,12 +73,17 @@ typedef struct {
     size_t max_bytes;
 } gpe_plan_desc;
 
-/* Lattice depth versus time.  CONST: v0.  RAMP: v0 at t0 to v1 at t1, linear,
- * clamped outside.  KNOTS: nknots >= 2 values spread evenly on [t0, t1], linear in
- * between, clamped outside; the host array is copied when the descriptor is set. */
+/* Lattice depth versus time, evaluated at each kick's time.  CONST: v0.  RAMP: v0 at
+ * t0 to v1 at t1, linear, clamped outside.  KNOTS: nknots >= 2 values spread evenly on
+ * [t0, t1], linear in between, clamped outside; the host array is copied when the
+ * descriptor is set.  PULSE: the flashed lattice of Sec. 5.2, v0 for t0 <= t < t1 and
+ * v1 otherwise; the kicks inside the pulse add up to its length t1 - t0 when its edges
+ * fall half a step from kick times (kicks sit at t0_call + n dt in gpe_step_real, at
+ * t0_call + (n + 1/2) dt in gpe_step_real_k), or on the first kick of a call. */
 #define GPE_SCHED_CONST 0
 #define GPE_SCHED_RAMP 1
 #define GPE_SCHED_KNOTS 2
+#define GPE_SCHED_PULSE 3
 typedef struct {
     int32_t kind;
     int32_t nknots;
@@ -121,6 +126,15 @@ int gpe_set_potential(gpe_plan *plan, const gpe_potential_desc *pot);
  * and the overlap history carry over from the previous call on this plan. */
 int gpe_step_real(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t0, double *obs);
 
+/* nsteps real-time steps in the ordering the paper prints (Sec. 3.1, Eq. 4) with the
+ * state kept in Fourier space: psi_k <- e^{T/2} F[e^{V} F^{-1}[e^{T/2} psi_k]], the kick
+ * over the full dt at the step midpoint t0 + (n + 1/2) dt.  psik: device [ny][nx]
+ * gpe_c64 holding FFT2(psi) (unscaled forward transform), updated in place; momentum
+ * populations are |psik|^2 directly (Sec. 5.2).  obs (nullable): per step, the
+ * observables of the real-space state at the kick (norm, Theta, alpha, <x>, <y>).
+ * The cavity must be off (GPE_ERR_UNSUPPORTED otherwise). */
+int gpe_step_real_k(gpe_plan *plan, gpe_c64 *psik, int64_t nsteps, double t0, double *obs);
+
 /* nsteps imaginary-time steps (Sec. 3.3) with the potential frozen at time t and the
  * cavity field held fixed; psi ends with unit norm.  obs as for gpe_step_real. */
 int gpe_step_imag(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t, double *obs);
@@ -130,6 +144,17 @@ int gpe_step_imag(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t, double
  * E_kin = sum_k |k|^2/2 |psi_k|^2 from the spectrum, E_int = g/2 int |psi|^4,
  * mu = E_kin + E_pot + 2 E_int. */
 int gpe_energy(gpe_plan *plan, const gpe_c64 *psi, double t, double out[6]);
+
+/* Populations of the momentum orders |2 n hbar k> of a Fourier-space state (Sec. 5.2:
+ * read off the reciprocal-space amplitude), synchronous.  psik: device [ny][nx]
+ * FFT2(psi) as kept by gpe_step_real_k.  axis: 0 (x) or 1 (y); order_step: FFT bins
+ * between neighbouring orders, 2 k L / (2 pi) for a lattice commensurate with the box
+ * (L the box length along the axis).  Bin j (signed, -n/2 <= j < n/2) belongs to order
+ * floor((j + floor(order_step / 2)) / order_step).  out (host, 2 nmax + 2 doubles):
+ * out[n + nmax] = sum of |psik|^2 in order n over the total, n = -nmax..nmax; then the
+ * norm sum |psik|^2 dx dy / (nx ny).  Errors: GPE_ERR_INVALID for an axis outside
+ * {0, 1}, order_step < 1, or (2 nmax + 1) order_step above the points on the axis. */
+int gpe_momentum_orders(gpe_plan *plan, const gpe_c64 *psik, int axis, int order_step, int nmax, double *out);
 
 /* sum |psi|^2 dx dy (synchronous). */
 int gpe_norm(gpe_plan *plan, const gpe_c64 *psi, double *out);

@@ -26,7 +26,9 @@
  *     <psi| cos kx cos ky |psi>                               (Sec. 5.3, Eq. 17), here as
  *                                                              the driven-damped ODE
  *     d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta, whose fixed point is Eq. 17
- *     with eta standing for N sqrt(V0 U0) and the undressed detuning.
+ *     with eta standing for N sqrt(V0 U0) and the undressed detuning (cavity = 1);
+ *     or Eq. 17 itself, recomputed from the current density before every kick, with
+ *     the dispersively shifted detuning of Eq. 18 (cavity = 2).
  *
  * The FFT is an iterative radix-2 Cooley-Tukey transform (bit reversal, then
  * butterflies) with every twiddle factor taken from cos/sin of its own index.
@@ -73,11 +75,14 @@ typedef struct {
     /* lattices Vx(t) cos^2(kx x) and Vy(t) cos^2(ky y) (Sec. 5.2) */
     double kx_lat, ky_lat;
     orc_sched sx, sy;
-    /* cavity (Sec. 5.3): the pump is the y lattice, depth Vy(t), wavenumber kc */
+    /* cavity (Sec. 5.3): the pump is the y lattice, depth Vy(t), wavenumber kc.
+     * cavity 0: off; 1: field from the driven-damped ODE (coupling eta); 2: field from
+     * the adiabatic expression of Eqs. 17-18 with n_atoms atoms (eta unused) */
     int cavity;
     double vc, kc, delta_c, kappa, eta;
     /* optional extra static potential [ny][nx] (may be NULL) */
     const double *vuser;
+    double n_atoms;
 } orc_problem;
 
 /* Propagation state carried between calls. */
@@ -98,6 +103,9 @@ static double sched_eval(const orc_sched *s, double t)
         if (t >= s->t1) return s->v1;
         return s->v0 + (s->v1 - s->v0) * (t - s->t0) / (s->t1 - s->t0);
     }
+    /* kind 3: the light shift of a lattice flashed on for t0 <= t < t1, the unit
+     * pulse Pi of Sec. 5.2 (v1 outside the pulse) */
+    if (s->kind == 3) return (t >= s->t0 && t < s->t1) ? s->v0 : s->v1;
     /* kind 2: knots */
     int m = s->nknots;
     if (m == 1 || t <= s->t0) return s->knots[0];
@@ -297,6 +305,42 @@ double orc_theta(const orc_problem *p, const cplx *psi)
     return s * da;
 }
 
+/* C = integral cos^2(kc x) |psi|^2 dx dy, the overlap in the dispersive shift
+ * (Sec. 5.3, Eq. 18). */
+double orc_cos2(const orc_problem *p, const cplx *psi)
+{
+    double s = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+            double c = cos(p->kc * xcoord(p, i));
+            s += c * c * dens;
+        }
+    return s * da;
+}
+
+/* The adiabatic cavity field of the density of psi at time t (Sec. 5.3, Eqs. 17-18):
+ *   alpha = N sqrt(Vp(t) U0) Theta / (Delta_c~ + i kappa),
+ *   Delta_c~ = Delta_c - N U0 C,
+ * Theta and C per unit norm (psi describes one atom; N = n_atoms counts them in both
+ * the coupling and the shift), U0 = vc, Vp(t) the pump (y lattice) depth. */
+static cplx alpha_adiabatic(const orc_problem *p, const cplx *psi, double t)
+{
+    double nrm = orc_norm(p, psi);
+    double th = orc_theta(p, psi) / nrm, c2 = orc_cos2(p, psi) / nrm;
+    double vp = sched_eval(&p->sy, t);
+    double dtil = p->delta_c - p->n_atoms * p->vc * c2;
+    return p->n_atoms * sqrt(vp * p->vc) * th / (dtil + I * p->kappa);
+}
+
+void orc_alpha_adiabatic(const orc_problem *p, const cplx *psi, double t, double *out)
+{
+    cplx a = alpha_adiabatic(p, psi, t);
+    out[0] = creal(a);
+    out[1] = cimag(a);
+}
+
 /* <x>, <y> (unnormalised integrals of x|psi|^2 and y|psi|^2). */
 void orc_moments(const orc_problem *p, const cplx *psi, double *mx, double *my)
 {
@@ -347,11 +391,27 @@ static void record(const orc_problem *p, const cplx *psi, cplx alpha, double the
  *   3. psi* = IFFT2( exp(-i k^2 dt/2) FFT2(psi') )
  *   4. psi_{n+1} = psi* exp(-i [V(t_{n+1}; alpha_{n+1}) + g|psi*|^2] dt/2)
  *   5. (cavity) Theta_{n+1} from psi_{n+1}
+ * With the adiabatic field (cavity 2) steps 1 and 5 are replaced by alpha evaluated
+ * from the density about to be kicked: alpha(psi_n, t_n) in 2, alpha(psi*, t_{n+1}) in 4.
  * obs (nullable): nsteps * ORC_NOBS doubles. */
 int orc_step_real(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps, double *obs)
 {
     double h = 0.5 * p->dt;
     cplx alpha = s->alpha_re + I * s->alpha_im;
+    if (p->cavity == 2) {
+        for (int64_t n = 0; n < nsteps; n++) {
+            double tn = s->t, tn1 = s->t + p->dt;
+            kick(p, psi, tn, alpha_adiabatic(p, psi, tn), h, 0);
+            kinetic(p, psi, 0);
+            alpha = alpha_adiabatic(p, psi, tn1);
+            kick(p, psi, tn1, alpha, h, 0);
+            s->t = tn1;
+            if (obs) record(p, psi, alpha, orc_theta(p, psi), obs + n * ORC_NOBS);
+        }
+        s->alpha_re = creal(alpha);
+        s->alpha_im = cimag(alpha);
+        return 0;
+    }
     if (p->cavity && !s->have_theta) {
         s->theta = orc_theta(p, psi);
         s->theta_prev = s->theta;
@@ -380,13 +440,17 @@ int orc_step_real(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps,
 }
 
 /* Imaginary-time split step (Sec. 3.3): dt -> -i dtau in every factor, potential
- * frozen at time s->t, cavity field held fixed, then psi <- psi / sqrt(norm). */
+ * frozen at time s->t, then psi <- psi / sqrt(norm).  The ODE cavity field is held
+ * fixed; the adiabatic one (cavity 2) is evaluated once per step from the state
+ * entering it (the kicks change the density in imaginary time, so one value per step
+ * is taken, and a converged state is then a fixed point of the frozen-field step). */
 int orc_step_imag(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps, double *obs)
 {
     double h = 0.5 * p->dt;
     cplx alpha = s->alpha_re + I * s->alpha_im;
     size_t npts = (size_t)p->nx * p->ny;
     for (int64_t n = 0; n < nsteps; n++) {
+        if (p->cavity == 2) alpha = alpha_adiabatic(p, psi, s->t);
         kick(p, psi, s->t, alpha, h, 1);
         kinetic(p, psi, 1);
         kick(p, psi, s->t, alpha, h, 1);
@@ -398,6 +462,10 @@ int orc_step_imag(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps,
             record(p, psi, alpha, orc_theta(p, psi), o);
             o[0] = nrm; /* pre-normalisation norm: -ln(o[0]) / (2 dtau) estimates mu */
         }
+    }
+    if (p->cavity == 2) {
+        s->alpha_re = creal(alpha);
+        s->alpha_im = cimag(alpha);
     }
     return 0;
 }
@@ -695,4 +763,30 @@ int orc_step_imag_k(const orc_problem *p, orc_state *s, cplx *psik, int64_t nste
 {
     if (p->cavity) return -1;
     return step_k(p, s, psik, nsteps, 1, obs);
+}
+
+/* Momentum-order populations of a Fourier-space state (Sec. 5.2: the populations of
+ * |2 n hbar k> are read off the reciprocal-space amplitude).  psik = FFT2(psi), [ny][nx].
+ * The signed bin m along `axis` (0: x, 1: y) belongs to order floor((m + floor(B/2)) / B),
+ * B = order_step FFT bins between orders.  out[n + nmax] = fraction of sum |psik|^2 in
+ * order n for |n| <= nmax; out[2 nmax + 1] = sum |psik|^2 dx dy / (nx ny) (Parseval). */
+int orc_momentum_orders(const orc_problem *p, const cplx *psik, int axis, int order_step, int nmax, double *out)
+{
+    int n = axis == 0 ? p->nx : p->ny;
+    if ((axis != 0 && axis != 1) || order_step < 1 || nmax < 0 || (2 * nmax + 1) * order_step > n) return -1;
+    for (int q = 0; q < 2 * nmax + 1; q++) out[q] = 0.0;
+    double tot = 0.0;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            int b = axis == 0 ? i : j;
+            int m = b >= n / 2 ? b - n : b;
+            int ord = (int)floor((double)(m + order_step / 2) / order_step);
+            double w = creal(psik[(size_t)j * p->nx + i]) * creal(psik[(size_t)j * p->nx + i]) +
+                       cimag(psik[(size_t)j * p->nx + i]) * cimag(psik[(size_t)j * p->nx + i]);
+            tot += w;
+            if (ord >= -nmax && ord <= nmax) out[ord + nmax] += w;
+        }
+    for (int q = 0; q < 2 * nmax + 1; q++) out[q] = tot > 0 ? out[q] / tot : 0.0;
+    out[2 * nmax + 1] = tot * (p->lx / p->nx) * (p->ly / p->ny) / ((double)p->nx * p->ny);
+    return 0;
 }

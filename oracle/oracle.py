@@ -70,6 +70,7 @@ class _Problem(C.Structure):
         ("kappa", C.c_double),
         ("eta", C.c_double),
         ("vuser", C.POINTER(C.c_double)),
+        ("n_atoms", C.c_double),
     ]
 
 
@@ -117,7 +118,8 @@ def set_threads(n: int = 0) -> int:
 
 @dataclass
 class Sched:
-    """Lattice depth vs time: const (v0), ramp (v0 -> v1 on [t0, t1]) or knots."""
+    """Lattice depth vs time: const (v0), ramp (v0 -> v1 on [t0, t1]), knots, or
+    pulse (v0 on t0 <= t < t1, v1 outside)."""
 
     kind: str = "const"
     v0: float = 0.0
@@ -145,16 +147,17 @@ class Problem:
     ky_lat: float = 0.0
     sx: Sched = field(default_factory=Sched)
     sy: Sched = field(default_factory=Sched)
-    cavity: bool = False
+    cavity: int = 0          # 0 off, 1 (True) field ODE, 2 adiabatic field (Eqs. 17-18)
     vc: float = 0.0
     kc: float = 0.0
     delta_c: float = 0.0
     kappa: float = 0.0
     eta: float = 0.0
     vuser: np.ndarray | None = None
+    n_atoms: float = 0.0
 
     def _sched(self, s: Sched, keep: list) -> _Sched:
-        kind = {"const": 0, "ramp": 1, "knots": 2}[s.kind]
+        kind = {"const": 0, "ramp": 1, "knots": 2, "pulse": 3}[s.kind]
         out = _Sched(kind, 0, s.v0, s.v1, s.t0, s.t1, None)
         if kind == 2:
             k = np.ascontiguousarray(s.knots, dtype=np.float64)
@@ -173,6 +176,7 @@ class Problem:
         p.sy = self._sched(self.sy, keep)
         p.cavity = int(self.cavity)
         p.vc, p.kc, p.delta_c, p.kappa, p.eta = self.vc, self.kc, self.delta_c, self.kappa, self.eta
+        p.n_atoms = self.n_atoms
         if self.vuser is not None:
             v = np.ascontiguousarray(self.vuser, dtype=np.float64)
             assert v.shape == (self.ny, self.nx)
@@ -264,6 +268,25 @@ def theta(prob: Problem, psi) -> float:
     return lib().orc_theta(C.byref(p), a.ctypes.data)
 
 
+def cos2(prob: Problem, psi) -> float:
+    """integral cos^2(kc x) |psi|^2 dx dy (the dispersive-shift overlap)."""
+    lib().orc_cos2.restype = C.c_double
+    lib().orc_cos2.argtypes = [C.c_void_p, C.c_void_p]
+    p, keep = prob.cstruct()
+    a = _c128(psi)
+    return float(lib().orc_cos2(C.byref(p), a.ctypes.data))
+
+
+def alpha_adiabatic(prob: Problem, psi, t: float = 0.0) -> complex:
+    """The adiabatic cavity field of the density of psi at time t (Eqs. 17-18)."""
+    lib().orc_alpha_adiabatic.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+    p, keep = prob.cstruct()
+    a = _c128(psi)
+    out = np.zeros(2)
+    lib().orc_alpha_adiabatic(C.byref(p), a.ctypes.data, float(t), out.ctypes.data)
+    return complex(out[0], out[1])
+
+
 def potential(prob: Problem, t: float = 0.0, alpha: complex = 0j) -> np.ndarray:
     p, keep = prob.cstruct()
     v = np.zeros((prob.ny, prob.nx))
@@ -342,3 +365,16 @@ def step_imag_k(prob: Problem, state: State, psik, nsteps: int, want_obs: bool =
     """Imaginary-time steps in the T/2-V-T/2 ordering (Fourier-space state)."""
     lib().orc_step_imag_k.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     return _step_k(lib().orc_step_imag_k, prob, state, psik, nsteps, want_obs)
+
+
+def momentum_orders(prob: Problem, psik, axis: int, order_step: int, nmax: int):
+    """Populations of the momentum orders -nmax..nmax (fractions) and the norm of a
+    Fourier-space state psik = FFT2(psi)."""
+    lib().orc_momentum_orders.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]
+    p, keep = prob.cstruct()
+    a = _c128(psik)
+    assert a.shape == (prob.ny, prob.nx)
+    out = np.zeros(2 * nmax + 2)
+    if lib().orc_momentum_orders(C.byref(p), a.ctypes.data, int(axis), int(order_step), int(nmax), out.ctypes.data):
+        raise ValueError("bad axis, order_step or nmax")
+    return out[:-1], float(out[-1])

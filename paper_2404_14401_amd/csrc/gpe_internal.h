@@ -44,6 +44,9 @@ struct GridDev {
     const double2 *kin_x, *kin_y;    // real time: e^{-i kx^2 dt/2}, e^{-i ky^2 dt/2} / (nx ny)
     const double *kim_x, *kim_y;     // imaginary time: e^{-kx^2 dt/2}, e^{-ky^2 dt/2} / (nx ny)
     const double2 *tw_x, *tw_y;      // W_N^m, m < N, for the x and y transforms
+    // kinetic half steps of the Fourier-space ordering: e^{-i kx^2 dt/4}, and
+    // e^{-i ky^2 dt/4} with (entry) and without (exit) the 1/(nx ny) of the round trip
+    const double2 *kh_x, *kh_yin, *kh_yout;
 };
 
 constexpr int NPART = 4;  // norm, Theta, x moment, y moment (per work-group partials)
@@ -62,6 +65,8 @@ enum ColMode : int {
     COL_KIN_REAL = 0,  // FFT_y -> e^{-i k^2 dt/2}/(nx ny) -> IFFT_y
     COL_KIN_IMAG = 1,  // FFT_y -> e^{-k^2 dt/2}/(nx ny) -> IFFT_y
     COL_EKIN = 2,      // FFT_y -> partials of sum k^2/2 |psi_k|^2 (no store)
+    COL_KHALF_INV = 3, // (Fourier-space state) kinetic half step -> IFFT_y
+    COL_FWD_KHALF = 4, // FFT_y -> kinetic half step (Fourier-space state out)
 };
 
 struct RowArgs {
@@ -71,9 +76,10 @@ struct RowArgs {
     PotDev pot;
     DevState *st;
     double *partials;  // [gridDim.x][NPART]
-    int n;             // step index within the call; kick time = st->t0 + (n or n+1) dt
+    int n;             // step index within the call; kick time = st->t0 + (n or n+1) dt + t_shift
     int reduce;        // write partials
     int lines_per_wg;
+    double t_shift;    // -dt/2 for the midpoint kick of the Fourier-space ordering
 };
 
 // Work done by work-group 0 of a column pass before its own columns: reduce the

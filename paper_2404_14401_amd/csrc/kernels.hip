@@ -87,7 +87,7 @@ size_t adj_col_shmem(int n, int w, int r)
 template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
                                          const PotDev &pot, const DevState *st, double *partials, int n, int lb,
-                                         int lines, XchgT *smem, double *red)
+                                         int lines, XchgT *smem, double *red, double t_shift = 0.0)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -125,7 +125,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
 
     // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes V
     double tk = st->t0;
-    if (!IMAG) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt;
+    if (!IMAG) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt + t_shift;
     const VLine vl = vline_cav(pot, row, tk, st->alpha_re, st->alpha_im);
     const float4 ty = pot.ty[row];
     const double cy = ty.z, yv = ty.w;
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
     __shared__ double red[8 * NPART];
     row_body<N, kRadix, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
                                      a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
-                                     a.lines_per_wg, smem, red);
+                                     a.lines_per_wg, smem, red, a.t_shift);
 }
 
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
@@ -241,7 +241,26 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
 #if GPE_TW_LDS
     __syncthreads();
 #endif
+    if constexpr (MODE == COL_KHALF_INV) {
+        // Fourier-space state: kinetic half step, then back to real space along y
+        const C kx = gd.kh_x[col];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kh_yin[t + m * T]));
+        fft_line<N, R, true>(v, lds, t, twy);
+#pragma unroll
+        for (int m = 0; m < R; ++m) store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
+        return;
+    }
     fft_line<N, R, false>(v, lds, t, twy);
+    if constexpr (MODE == COL_FWD_KHALF) {
+        const C kx = gd.kh_x[col];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            v[m] = cmul(v[m], cmul(kx, gd.kh_yout[t + m * T]));
+            store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
+        }
+        return;
+    }
     if constexpr (MODE == COL_EKIN) {
         const int ix = col >= nx / 2 ? col - nx : col;
         const double kx = 2.0 * M_PI * ix / gd.lx;
@@ -341,6 +360,33 @@ __global__ void __launch_bounds__(256) norm_kernel(const float2 *psi, size_t n, 
     }
     block_sum<1>(s, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// Marginals of |psi|^2: axis 1 sums every row (out[j], one work-group per row), axis 0
+// every column (out[i]; a work-group owns 64 columns, its four waves take every fourth
+// row and are combined in a fixed order).  Fixed summation order throughout.
+__global__ void __launch_bounds__(256) marginal_kernel(const float2 *psi, int nx, int ny, int axis, double *out)
+{
+    __shared__ double red[4 * 64];
+    if (axis == 1) {
+        const float2 *row = psi + (size_t)blockIdx.x * nx;
+        double s[1] = {0.0};
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) s[0] += (double)row[i].x * row[i].x + (double)row[i].y * row[i].y;
+        block_sum<1>(s, red);
+        if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+        return;
+    }
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (col < nx)
+        for (int j = q; j < ny; j += 4) {
+            const float2 p = psi[(size_t)j * nx + col];
+            s += (double)p.x * p.x + (double)p.y * p.y;
+        }
+    red[q * 64 + lane] = s;
+    __syncthreads();
+    if (q == 0 && col < nx) out[col] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
 }
 
 // ------------------------------------------------------------- whole grid in LDS
@@ -625,6 +671,8 @@ template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int 
     if (mode == COL_KIN_REAL) GPE_COL(COL_KIN_REAL);
     else if (mode == COL_KIN_IMAG) GPE_COL(COL_KIN_IMAG);
     else if (mode == COL_EKIN) GPE_COL(COL_EKIN);
+    else if (mode == COL_KHALF_INV) GPE_COL(COL_KHALF_INV);
+    else if (mode == COL_FWD_KHALF) GPE_COL(COL_FWD_KHALF);
     else return hipErrorInvalidValue;
 #undef GPE_COL
     return hipGetLastError();
@@ -670,6 +718,13 @@ hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_h
 hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(norm_kernel, dim3(blocks), dim3(256), 0, s, psi, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_marginal(const float2 *psi, int nx, int ny, int axis, double *out, hipStream_t s)
+{
+    const int blocks = axis == 1 ? ny : (nx + 63) / 64;
+    hipLaunchKernelGGL(marginal_kernel, dim3(blocks), dim3(256), 0, s, psi, nx, ny, axis, out);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ __device__ __forceinline__ double sched_eval(const Sched &s, double t)
         if (t >= s.t1) return s.v1;
         return s.v0 + (s.v1 - s.v0) * (t - s.t0) / (s.t1 - s.t0);
     }
+    if (s.kind == 3) return (t >= s.t0 && t < s.t1) ? s.v0 : s.v1;  // flashed lattice (Sec. 5.2)
     const int m = s.nknots;
     if (m == 1 || t <= s.t0) return s.knots[0];
     if (t >= s.t1) return s.knots[m - 1];

@@ -111,8 +111,9 @@ static Sched to_sched(const gpe_schedule &s, const double *dev_knots)
 
 static int check_sched(const gpe_schedule &s, const char *name)
 {
-    if (s.kind < 0 || s.kind > 2) return fail(GPE_ERR_INVALID, std::string(name) + ": unknown schedule kind");
-    if (s.kind == GPE_SCHED_RAMP && !(s.t1 > s.t0)) return fail(GPE_ERR_INVALID, std::string(name) + ": ramp needs t1 > t0");
+    if (s.kind < 0 || s.kind > 3) return fail(GPE_ERR_INVALID, std::string(name) + ": unknown schedule kind");
+    if ((s.kind == GPE_SCHED_RAMP || s.kind == GPE_SCHED_PULSE) && !(s.t1 > s.t0))
+        return fail(GPE_ERR_INVALID, std::string(name) + ": ramp and pulse need t1 > t0");
     if (s.kind == GPE_SCHED_KNOTS && (s.nknots < 2 || !s.knots || !(s.t1 > s.t0)))
         return fail(GPE_ERR_INVALID, std::string(name) + ": knots need nknots >= 2, a host array and t1 > t0");
     return GPE_OK;
@@ -220,12 +221,13 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     if ((rc = dalloc(p, (void **)&p->st, sizeof(DevState)))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->tx, sizeof(float4) * nx))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->ty, sizeof(float4) * ny))) return cleanup(rc);
-    std::vector<double2> kx(nx), ky(ny), twx(nx), twy(ny);
+    std::vector<double2> kx(nx), ky(ny), twx(nx), twy(ny), khx(nx), khyi(ny), khyo(ny);
     std::vector<double> kmx(nx), kmy(ny);
     const double inv = 1.0 / ((double)nx * ny);
     for (int i = 0; i < nx; ++i) {
         const double k = kval(i, nx, d->lx), ph = 0.5 * k * k * d->dt;
         kx[i] = make_double2(std::cos(ph), -std::sin(ph));
+        khx[i] = make_double2(std::cos(0.5 * ph), -std::sin(0.5 * ph));
         kmx[i] = std::exp(-ph);
         const double a = -2.0 * M_PI * i / nx;
         twx[i] = make_double2(std::cos(a), std::sin(a));
@@ -233,12 +235,15 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     for (int j = 0; j < ny; ++j) {
         const double k = kval(j, ny, d->ly), ph = 0.5 * k * k * d->dt;
         ky[j] = make_double2(std::cos(ph) * inv, -std::sin(ph) * inv);
+        khyi[j] = make_double2(std::cos(0.5 * ph) * inv, -std::sin(0.5 * ph) * inv);
+        khyo[j] = make_double2(std::cos(0.5 * ph), -std::sin(0.5 * ph));
         kmy[j] = std::exp(-ph) * inv;
         const double a = -2.0 * M_PI * j / ny;
         twy[j] = make_double2(std::cos(a), std::sin(a));
     }
     if ((rc = upload(p, &p->kin_x, kx)) || (rc = upload(p, &p->kin_y, ky)) || (rc = upload(p, &p->kim_x, kmx)) ||
-        (rc = upload(p, &p->kim_y, kmy)) || (rc = upload(p, &p->tw_x, twx)) || (rc = upload(p, &p->tw_y, twy)))
+        (rc = upload(p, &p->kim_y, kmy)) || (rc = upload(p, &p->tw_x, twx)) || (rc = upload(p, &p->tw_y, twy)) ||
+        (rc = upload(p, &p->kh_x, khx)) || (rc = upload(p, &p->kh_yin, khyi)) || (rc = upload(p, &p->kh_yout, khyo)))
         return cleanup(rc);
     p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 256);
     if ((rc = dalloc(p, (void **)&p->partials, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
@@ -262,6 +267,9 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     gd.kim_y = p->kim_y;
     gd.tw_x = p->tw_x;
     gd.tw_y = p->tw_y;
+    gd.kh_x = p->kh_x;
+    gd.kh_yin = p->kh_yin;
+    gd.kh_yout = p->kh_yout;
     gpe_potential_desc pot{};
     pot.wx = pot.wy = 1.0;
     if ((rc = gpe_set_potential(p, &pot))) return cleanup(rc);
@@ -385,6 +393,36 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
     return GPE_OK;
 }
 
+int gpe_step_real_k(gpe_plan *p, gpe_c64 *psik, int64_t nsteps, double t0, double *obs)
+{
+    if (!p || !psik || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
+    if (!std::isfinite(t0)) return fail(GPE_ERR_INVALID, "t0 must be finite");
+    if (p->pot.cavity) return fail(GPE_ERR_UNSUPPORTED, "the Fourier-space ordering runs without the cavity");
+    if (nsteps == 0) return GPE_OK;
+    const Shape &sh = p->shape;
+    float2 *f = (float2 *)psik;
+    LAUNCH_OK(launch_set_call(p->st, t0, 0, 0, p->stream));
+    ColArgs ca = col_args(p, f);
+    ca.do_tail = 0;
+    LAUNCH_OK(launch_col(p->ny, COL_KHALF_INV, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+    RowArgs ra = row_args(p, f);
+    ra.t_shift = -0.5 * p->dt;  // kick at the step midpoint
+    ra.reduce = obs ? 1 : 0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        ra.n = (int)n;
+        LAUNCH_OK(launch_row(p->nx, ROW_MID, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        ColArgs cb = col_args(p, f);
+        TailArgs &ta = cb.tail;
+        ta.partials = p->partials;
+        ta.npartials = obs ? sh.row_blocks : 0;
+        ta.obs = obs ? obs + n * NOBS : nullptr;
+        cb.do_tail = obs ? 1 : 0;
+        LAUNCH_OK(launch_col(p->ny, n + 1 < nsteps ? COL_KIN_REAL : COL_FWD_KHALF, cb, sh.col_blocks, sh.col_threads,
+                             sh.col_shmem, p->stream));
+    }
+    return GPE_OK;
+}
+
 int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *obs)
 {
     if (!p || !psi || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
@@ -443,6 +481,34 @@ int gpe_norm(gpe_plan *p, const gpe_c64 *psi, double *out)
     double s = 0;
     for (int i = 0; i < blocks; ++i) s += p->hpart[i];
     *out = s * p->grid.dA;
+    return GPE_OK;
+}
+
+int gpe_momentum_orders(gpe_plan *p, const gpe_c64 *psik, int axis, int order_step, int nmax, double *out)
+{
+    if (!p || !psik || !out) return fail(GPE_ERR_INVALID, "null argument");
+    if (axis != 0 && axis != 1) return fail(GPE_ERR_INVALID, "axis must be 0 (x) or 1 (y)");
+    const int n = axis == 0 ? p->nx : p->ny;
+    if (order_step < 1 || order_step > n) return fail(GPE_ERR_INVALID, "order_step must be in [1, grid points on the axis]");
+    if (nmax < 0 || (2LL * nmax + 1) * order_step > n)
+        return fail(GPE_ERR_INVALID, "nmax < 0 or the orders' windows exceed the grid");
+    double *marg = (double *)p->scratch;  // n doubles fit in the nx*ny*8-byte scratch grid
+    LAUNCH_OK(launch_marginal((const float2 *)psik, p->nx, p->ny, axis, marg, p->stream));
+    std::vector<double> h((size_t)n);
+    HIP_OK(hipMemcpyAsync(h.data(), marg, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    std::vector<double> pop((size_t)(2 * nmax + 1), 0.0);
+    double tot = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const int js = j >= n / 2 ? j - n : j;  // signed bin
+        const int a = js + order_step / 2;
+        const int ord = a >= 0 ? a / order_step : -((-a + order_step - 1) / order_step);
+        tot += h[j];
+        if (ord >= -nmax && ord <= nmax) pop[ord + nmax] += h[j];
+    }
+    if (!std::isfinite(tot)) return fail(GPE_ERR_NONFINITE, "non-finite momentum distribution");
+    for (int q = 0; q <= 2 * nmax; ++q) out[q] = tot > 0 ? pop[q] / tot : 0.0;
+    out[2 * nmax + 1] = tot * p->grid.dA / ((double)p->nx * p->ny);
     return GPE_OK;
 }
 

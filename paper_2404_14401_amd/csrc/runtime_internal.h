@@ -18,6 +18,7 @@ hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads
 hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
 hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
 hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
+hipError_t launch_marginal(const float2 *psi, int nx, int ny, int axis, double *out, hipStream_t s);
 hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s);
 hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s);
 hipError_t launch_row_batched(int n, int r, int mode, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
@@ -81,6 +82,7 @@ struct gpe_plan {
     DevState *st = nullptr;
     float4 *tx = nullptr, *ty = nullptr;
     double2 *kin_x = nullptr, *kin_y = nullptr, *tw_x = nullptr, *tw_y = nullptr;
+    double2 *kh_x = nullptr, *kh_yin = nullptr, *kh_yout = nullptr;
     double *kim_x = nullptr, *kim_y = nullptr;
     double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
     int npart_max = 0;

@@ -21,13 +21,14 @@ LIB_PATH = os.environ.get("GPE_LIB_PATH") or os.path.join(_HERE, "libgpe.so")
 OK = 0
 ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONFINITE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 NOBS = 6
-SCHED = {"const": 0, "ramp": 1, "knots": 2}
+SCHED = {"const": 0, "ramp": 1, "knots": 2, "pulse": 3}
 LOSS = {"fidelity": 0, "energy": 1}
 ADJ_MODE = {"auto": 0, "reconstruct": 1, "checkpoint": 2}
 
 # Every entry point the header declares (checked by the CPU tests against include/gpe.h).
 EXPORTS = (
-    "gpe_plan_create", "gpe_plan_destroy", "gpe_set_potential", "gpe_step_real", "gpe_step_imag",
+    "gpe_plan_create", "gpe_plan_destroy", "gpe_set_potential", "gpe_step_real", "gpe_step_real_k",
+    "gpe_step_imag", "gpe_momentum_orders",
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
     "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
@@ -81,6 +82,8 @@ def lib():
         L.gpe_set_potential.argtypes = [P, C.POINTER(PotentialDesc)]
         L.gpe_step_real.argtypes = [P, P, I64, D, P]
         L.gpe_step_imag.argtypes = [P, P, I64, D, P]
+        L.gpe_step_real_k.argtypes = [P, P, I64, D, P]
+        L.gpe_momentum_orders.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P]
         L.gpe_energy.argtypes = [P, P, D, P]
         L.gpe_norm.argtypes = [P, P, P]
         L.gpe_get_cavity.argtypes = [P, P]
@@ -189,6 +192,19 @@ class Plan:
     def step_real(self, psi, nsteps: int, t0: float = 0.0, obs=None):
         check(lib().gpe_step_real(self._h, _ptr(psi), int(nsteps), float(t0),
                                   _ptr(obs, "float64") if obs is not None else None))
+
+    def step_real_k(self, psik, nsteps: int, t0: float = 0.0, obs=None):
+        """Real-time steps in the T/2-V-T/2 ordering on the Fourier-space state FFT2(psi)."""
+        check(lib().gpe_step_real_k(self._h, _ptr(psik), int(nsteps), float(t0),
+                                    _ptr(obs, "float64") if obs is not None else None))
+
+    def momentum_orders(self, psik, axis: int, order_step: int, nmax: int):
+        """Populations of the momentum orders -nmax..nmax (fractions of the total) and
+        the norm, from a Fourier-space state."""
+        out = np.zeros(2 * nmax + 2)
+        check(lib().gpe_momentum_orders(self._h, _ptr(psik), int(axis), int(order_step), int(nmax),
+                                        out.ctypes.data))
+        return out[:-1], float(out[-1])
 
     def step_imag(self, psi, nsteps: int, t: float = 0.0, obs=None):
         check(lib().gpe_step_imag(self._h, _ptr(psi), int(nsteps), float(t),

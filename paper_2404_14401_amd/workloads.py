@@ -22,8 +22,9 @@ import numpy as np
 
 @dataclass
 class Schedule:
-    """Lattice depth vs time: 'const' (v0), 'ramp' (v0 -> v1 on [t0, t1], clamped)
-    or 'knots' (piecewise-linear through `knots` spread evenly on [t0, t1])."""
+    """Lattice depth vs time: 'const' (v0), 'ramp' (v0 -> v1 on [t0, t1], clamped),
+    'knots' (piecewise-linear through `knots` spread evenly on [t0, t1]) or 'pulse'
+    (v0 for t0 <= t < t1, v1 outside: a lattice flashed on)."""
 
     kind: str = "const"
     v0: float = 0.0
@@ -58,6 +59,11 @@ class Setup:
     kappa: float = 0.0
     eta: float = 0.0
     alpha0: complex = 0j
+    # "ode": the field follows d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta;
+    # "adiabatic": alpha = N sqrt(Vp U0) Theta / (Delta_c - N U0 C + i kappa) from the
+    # current density (Sec. 5.3), N = n_atoms
+    cavity_mode: str = "ode"
+    n_atoms: float = 0.0
 
     def xs(self) -> np.ndarray:
         return -0.5 * self.lx + np.arange(self.nx) * (self.lx / self.nx)
@@ -152,6 +158,39 @@ def cavity_scaled(n: int, seed: int = 0) -> Setup:
     dx = 1/16 (box n/16), for parity at sizes the oracle finishes in seconds."""
     s = cavity_1024(seed)
     return s.with_(nx=n, ny=n, lx=n / 16.0, ly=n / 16.0)
+
+
+# Kapitza-Dirac diffraction (Sec. 5.2, Fig. 4), dimensionless (hbar = m = 1, unit trap
+# frequency): the paper's 2^9 grid and a box of 30 length units, a y lattice
+# commensurate with the box (48 periods of cos^2, so neighbouring momentum orders 2k
+# apart sit KD_ORDER_STEP = 48 FFT bins apart, orders up to |n| = 4 below the grid's
+# Nyquist bin), depth -10 E_r (a red-detuned light shift), E_r = k^2/2, and
+# dt = 1.75e-4 ~ 2.2e-3 hbar/E_r.  The populations are read at the steps of
+# KD_SNAPSHOTS, t E_r / hbar = 0.46, 0.87, 1.40, spaced as the paper's 18, 34, 55 us.
+# g = 1000 puts the Thomas-Fermi radius at ~6 (about ten lattice periods).
+KD_ORDER_STEP = 48
+KD_SNAPSHOTS = (210, 396, 640)
+KD_G = 1000.0
+
+
+def kapitza_dirac_512(g: float = 0.0) -> Setup:
+    """Isotropic unit trap plus a lattice V0 cos^2(k y) flashed on at t = 0 for the
+    whole run; g = 0 (non-interacting) or KD_G (interacting)."""
+    lx = 30.0
+    k = np.pi * KD_ORDER_STEP / lx
+    er = 0.5 * k * k
+    dt = 1.75e-4
+    return Setup(nx=512, ny=512, lx=lx, ly=lx, dt=dt, g=g, wx=1.0, wy=1.0, ky_lat=k,
+                 sy=Schedule("pulse", -10.0 * er, 0.0, 0.0, KD_SNAPSHOTS[-1] * dt))
+
+
+def kapitza_dirac_start(s: Setup) -> np.ndarray:
+    """The condensate before the flash: the trap's Gaussian ground state for g = 0, the
+    Thomas-Fermi profile sqrt((mu - V)/g) with mu = sqrt(g / pi) (2D, unit trap) for g > 0;
+    rounded to complex64."""
+    if s.g == 0.0:
+        return to_c64(gaussian(s, 1.0))
+    return to_c64(thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi))))
 
 
 @dataclass

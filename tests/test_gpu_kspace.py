@@ -1,0 +1,150 @@
+"""The ordering the paper prints (Sec. 3.1, Eq. 4: kinetic half steps around a full
+kick, state kept in Fourier space) on the GPU against the FP64 oracle's.
+
+The state handed over is FFT2(psi) (unscaled forward transform); momentum populations
+are read straight off it (Sec. 5.2)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, state
+from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def plan_for(s):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    return gpe.Plan.from_setup(s)
+
+
+@pytest.mark.parametrize("shape", [(64, 32), (32, 64), (256, 128)])
+def test_kspace_steps_with_every_potential_term(shape):
+    """Trap (displaced, anisotropic), both lattices (ramp and const), g > 0; a few steps
+    from a random state on non-square grids (the 256 x 128 grid takes the
+    XCD-swizzled column launch)."""
+    torch = torch_cuda()
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=12.0 * nx / 64, ly=12.0 * ny / 64, dt=0.02, g=30.0, wx=1.1, wy=0.8,
+                x0=0.3, y0=-0.2, kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("ramp", 1.0, 3.0, 0.0, 0.1),
+                sy=W.Schedule("const", 2.0))
+    psik0 = W.to_c64(O.fft2d(W.random_state(s, 11)))
+    ref, robs = O.step_real_k(problem(s), state(s, 0.05), psik0, 3, want_obs=True)
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    obs = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+    plan.step_real_k(d, 3, 0.05, obs)
+    assert rel_l2(to_host(d), ref) < 2e-6
+    # the norm is conserved by every factor, so the norm at the kick is the oracle's
+    assert np.abs(obs.cpu().numpy()[:, 0] - robs).max() < 1e-6
+
+
+def test_kspace_ground_state_in_ramped_lattice():
+    """64^2 ground state, 2000 steps of a lattice ramp: the parity bar on psi_k, the
+    energy and the populations of the +-2 k_lat momentum orders."""
+    torch = torch_cuda()
+    s0 = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=0.01, g=100.0)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.gaussian(s0, 1.5), 1500)
+    s = s0.with_(dt=1e-3, y0=0.5, kx_lat=np.pi / 2, sx=W.Schedule("ramp", 0.0, 5.0, 0.0, 1.0))
+    psik0 = W.to_c64(O.fft2d(W.to_c64(gs)))
+    n = 2000
+    ref, robs = O.step_real_k(problem(s), state(s), psik0, n, want_obs=True)
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_real_k(d, n, 0.0, obs)
+    out = to_host(d)
+    assert rel_l2(out, ref) < 1e-4
+    t = n * s.dt
+    e_gpu = O.energy(problem(s), O.fft2d(out, inverse=True), t)["e"]
+    e_ref = O.energy(problem(s), O.fft2d(ref, inverse=True), t)["e"]
+    assert abs(e_gpu - e_ref) / abs(e_ref) < 1e-5
+    assert np.abs(obs.cpu().numpy()[:, 0] - robs).max() < 1e-5
+    # momentum orders along x: 2 k_lat apart = 8 FFT bins on this machine
+    pop_g, nrm_g = plan.momentum_orders(d, 0, 8, 3)
+    pop_r, nrm_r = O.momentum_orders(problem(s), ref, 0, 8, 3)
+    assert np.abs(pop_g - pop_r).max() < 1e-5 and abs(nrm_g - nrm_r) < 1e-5
+    assert pop_r[2] > 1e-3   # the lattice has populated the +-1 orders
+
+
+@pytest.mark.parametrize("g", [0.0, W.KD_G])
+def test_kapitza_dirac_512_populations(g):
+    """The flashed lattice of Sec. 5.2 on the paper's 2^9 grid: the momentum-order
+    populations at the three snapshot times and the final psi_k against the oracle."""
+    s = W.kapitza_dirac_512(g)
+    psik0 = W.to_c64(O.fft2d(W.kapitza_dirac_start(s)))
+    st = state(s)
+    ref = psik0
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    n0 = 0
+    for snap in W.KD_SNAPSHOTS:
+        ref, _ = O.step_real_k(problem(s), st, ref, snap - n0)
+        plan.step_real_k(d, snap - n0, n0 * s.dt)
+        n0 = snap
+        pop_g, nrm_g = plan.momentum_orders(d, 1, W.KD_ORDER_STEP, 4)
+        pop_r, nrm_r = O.momentum_orders(problem(s), ref, 1, W.KD_ORDER_STEP, 4)
+        assert np.abs(pop_g - pop_r).max() < 1e-5, (snap, pop_g, pop_r)
+        assert abs(nrm_g - 1.0) < 1e-5
+        # the observable itself: the GPU reduction of the GPU state equals the oracle's
+        pop_o, nrm_o = O.momentum_orders(problem(s), to_host(d), 1, W.KD_ORDER_STEP, 4)
+        # (the two sums run in different orders over 2^18 points)
+        assert np.abs(pop_g - pop_o).max() < 1e-10 and abs(nrm_g - nrm_o) < 1e-10 * nrm_o
+    assert pop_r[4] < 0.95 and pop_r[3] > 0.05   # a real transfer into the first orders
+    assert rel_l2(to_host(d), ref) < 1e-4
+
+
+def test_kspace_calls_compose():
+    """Splitting the steps over calls, with the time carried by t0, changes nothing."""
+    s = W.Setup(nx=128, ny=64, lx=16.0, ly=10.0, dt=0.005, g=40.0, kx_lat=1.0,
+                sx=W.Schedule("ramp", 0.0, 4.0, 0.0, 0.5))
+    psik0 = W.to_c64(O.fft2d(W.gaussian(s, 1.2)))
+    plan = plan_for(s)
+    a = to_dev(psik0)
+    plan.step_real_k(a, 90, 0.0)
+    b = to_dev(psik0)
+    t = 0.0
+    for k in (1, 29, 60):
+        plan.step_real_k(b, k, t)
+        t += k * s.dt
+    assert rel_l2(to_host(a), to_host(b)) < 1e-6
+
+
+def test_kspace_rejects_cavity_and_accepts_zero_steps():
+    from paper_2404_14401_amd import gpe
+
+    s = W.cavity_scaled(64, 0)
+    plan = plan_for(s)
+    d = to_dev(O.fft2d(W.gaussian(s, 1.0)))
+    before = to_host(d)
+    with pytest.raises(gpe.GpeError) as e:
+        plan.step_real_k(d, 3, 0.0)
+    assert e.value.code == gpe.ERR_UNSUPPORTED
+    free = plan_for(s.with_(cavity=False))
+    free.step_real_k(d, 0, 0.0)
+    assert np.array_equal(to_host(d), before)
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_pulse_schedule_in_both_orderings(path, monkeypatch):
+    """A lattice flashed on and off inside the run (edges half a step from the kicks):
+    the real-space ordering on both paths and the Fourier-space one against the oracle."""
+    monkeypatch.setenv("GPE_PATH", path)
+    s = W.Setup(nx=64, ny=64, lx=12.0, ly=12.0, dt=2e-3, g=50.0, ky_lat=np.pi * 8 / 12.0,
+                sy=W.Schedule("pulse", -40.0, 0.0, 30.5 * 2e-3, 70.5 * 2e-3))
+    psi0 = W.to_c64(W.gaussian(s, 2.0))
+    plan = plan_for(s)
+    ref, _ = O.step_real(problem(s), state(s), psi0, 100)
+    d = to_dev(psi0)
+    plan.step_real(d, 100, 0.0)
+    assert rel_l2(to_host(d), ref) < 1e-5
+    s2 = s.with_(sy=W.Schedule("pulse", -40.0, 0.0, 30 * 2e-3, 70 * 2e-3))
+    psik0 = W.to_c64(O.fft2d(psi0))
+    ref, _ = O.step_real_k(problem(s2), state(s2), psik0, 100)
+    plan2 = plan_for(s2)
+    d = to_dev(psik0)
+    plan2.step_real_k(d, 100, 0.0)
+    assert rel_l2(to_host(d), ref) < 1e-5

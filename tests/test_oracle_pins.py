@@ -440,3 +440,166 @@ def test_printed_ordering_free_flow_and_kohn():
         ys.append(np.sum(np.abs(p) ** 2 * s1.ys()[:, None]) * (s1.lx / s1.nx) * (s1.ly / s1.ny))
     wd = np.arccos(1 - dt**2 / 2) / dt
     assert np.abs(np.array(ys) - d * (1 - np.cos(wd * dt * np.arange(1, 201)))).max() < 1e-10
+
+
+# ------------------------------------------- Kapitza-Dirac few-mode model (Sec. 5.2)
+
+def few_mode_populations(v0, k, tau, nmax):
+    """|2 n k> populations after a lattice pulse v0 cos^2(k y) of length tau on a
+    condensate at rest (no trap, g = 0): the plane-wave basis closes under the
+    Hamiltonian, H_nn = (2 n k)^2 / 2 + v0 / 2 and H_{n, n+-1} = v0 / 4."""
+    from scipy.linalg import expm
+
+    n = np.arange(-nmax, nmax + 1)
+    h = np.diag(0.5 * (2 * n * k) ** 2 + 0.5 * v0) + np.diag(np.full(2 * nmax, 0.25 * v0), 1) \
+        + np.diag(np.full(2 * nmax, 0.25 * v0), -1)
+    c0 = (n == 0).astype(complex)
+    return np.abs(expm(-1j * h * tau) @ c0) ** 2
+
+
+def kd_box(dt, sched):
+    """A periodic box holding 4 lattice periods along y, no trap, g = 0."""
+    ly = 8.0
+    k = np.pi * 4 / ly
+    return W.Setup(nx=4, ny=64, lx=1.0, ly=ly, dt=dt, g=0.0, wx=0.0, wy=0.0, ky_lat=k, sy=sched), k
+
+
+def orders_from_psik(psik, ly, k, nmax):
+    """Population of |2 n k> along y: the FFT bin j = 2 n k ly / (2 pi)."""
+    pop = (np.abs(psik) ** 2).sum(axis=1)
+    pop = pop / pop.sum()
+    step = int(round(2 * k * ly / (2 * np.pi)))
+    return np.array([pop[(n * step) % psik.shape[0]] for n in range(-nmax, nmax + 1)])
+
+
+@pytest.mark.parametrize("ordering", ["k", "v"])
+def test_kapitza_dirac_matches_few_mode_model(ordering):
+    """Flashing v0 = 10 E_r for 1.2 hbar/E_r and then switching it off: the populations
+    follow the few-mode model during the pulse (to the O(dt^2) splitting error) and
+    freeze after it."""
+    dt = 2e-3
+    s, k = kd_box(dt, None)
+    er = 0.5 * k * k
+    v0 = 10 * er
+    m = int(round(1.2 / er / dt))
+    # pulse edges half a step from the kicks: kicks at (n + 1/2) dt in the Fourier-space
+    # ordering, at n dt (the first one a half kick) in the real-space one
+    tau = m * dt if ordering == "k" else (m + 0.5) * dt
+    s = s.with_(sy=W.Schedule("pulse", v0, 0.0, 0.0, tau))
+    psi0 = np.full((s.ny, s.nx), 1.0 / np.sqrt(s.lx * s.ly), dtype=complex)
+    nmax = 4
+
+    def model(t):
+        return few_mode_populations(v0, k, t, 12)[12 - nmax:12 + nmax + 1]
+
+    assert model(tau)[nmax] < 0.9 and model(tau)[nmax + 1] > 0.05   # a real transfer
+    for extra in (0, 40):
+        # the lattice acts for min(t, tau); an edge misplaced by half a step moves the
+        # populations by ~4e-4, ten times the bar
+        want = model(min((m + extra) * dt, tau))
+        if ordering == "k":
+            out, _ = O.step_real_k(problem(s), state(s), O.fft2d(psi0), m + extra)
+        else:
+            psi, _ = O.step_real(problem(s), state(s), psi0, m + extra)
+            out = O.fft2d(psi)
+        got = orders_from_psik(out, s.ly, k, nmax)
+        assert np.abs(got - want).max() < 4e-5, (extra, got, want)
+        assert np.abs(got - got[::-1]).max() < 1e-12   # +-n symmetry of a standing wave
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_momentum_orders_of_known_plane_waves(axis):
+    """A superposition of plane waves e^{i 2 pi m u / L} with chosen bins m: each
+    order collects exactly its waves, window edges included (bin n B - B/2 opens order
+    n, bin n B + B/2 opens order n + 1, B even), and the norm equals the real-space one."""
+    nx, ny = (64, 8) if axis == 0 else (8, 64)
+    s = W.Setup(nx=nx, ny=ny, lx=6.0, ly=5.0, dt=0.01)
+    n_ax, L = (nx, s.lx) if axis == 0 else (ny, s.ly)
+    u = (s.xs()[None, :] if axis == 0 else s.ys()[:, None]) + 0.5 * L
+    B, nmax = 8, 3
+    waves = {0: 1.0, 3: 0.3 - 0.2j, -4: 0.5j, 4: -0.7, 12: 0.25, -13: 0.4, 28: 0.3}
+    psi = sum(c * np.exp(2j * np.pi * m * u / L) for m, c in waves.items()) * np.ones((ny, nx))
+    want = np.zeros(2 * nmax + 1)
+    tot = 0.0
+    for m, c in waves.items():
+        # m = -4 = -B/2 opens order 0; m = 4 = B/2 opens order 1; m = 28 is order 4 (dropped)
+        order = {0: 0, 3: 0, -4: 0, 4: 1, 12: 2, -13: -2, 28: 4}[m]
+        tot += abs(c) ** 2
+        if abs(order) <= nmax:
+            want[order + nmax] += abs(c) ** 2
+    pop, nrm = O.momentum_orders(problem(s), O.fft2d(psi), axis, B, nmax)
+    assert np.abs(pop - want / tot).max() < 1e-13
+    assert abs(nrm - O.norm(problem(s), psi)) < 1e-12 * nrm
+    with pytest.raises(ValueError):
+        O.momentum_orders(problem(s), O.fft2d(psi), axis, B, (n_ax // B + 1) // 2)
+
+
+# ----------------------------------- adiabatic cavity field (Sec. 5.3, Eqs. 17-18)
+
+def adiabatic_setup(**kw):
+    base = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=2e-3, g=10.0, x0=0.3, ky_lat=2.0,
+                   sy=W.Schedule("const", -5.0), cavity=True, vc=-0.5, kc=2.0)
+    return base.with_(**kw)
+
+
+@pytest.mark.parametrize("x0,y0", [(0.0, 0.0), (0.35, -0.2)])
+def test_adiabatic_alpha_of_a_gaussian_density(x0, y0):
+    """|psi|^2 a Gaussian of variance s^2 centred at (x0, y0): Theta = e^{-k^2 s^2}
+    cos(k x0) cos(k y0), C = (1 + e^{-2 k^2 s^2} cos(2 k x0)) / 2, so that
+    alpha = N sqrt(Vp(t) U0) Theta / (Delta_c - N U0 C + i kappa), with the pump read
+    off a ramp at t (both lattices red detuned: Vp, U0 < 0)."""
+    w, k, n_at, u0 = 1.1, 1.7, 250.0, -0.04
+    s = W.Setup(nx=128, ny=128, lx=24.0, ly=24.0, dt=0.01, sy=W.Schedule("ramp", -1.0, -9.0, 0.0, 2.0),
+                cavity=True, cavity_mode="adiabatic", vc=u0, kc=k, delta_c=-30.0, kappa=7.0, n_atoms=n_at)
+    psi = W.gaussian(s, w, x0, y0)            # density exp(-r^2 / w^2): variance w^2 / 2
+    var = 0.5 * w * w
+    theta = np.exp(-k * k * var) * np.cos(k * x0) * np.cos(k * y0)
+    c2 = 0.5 * (1.0 + np.exp(-2 * k * k * var) * np.cos(2 * k * x0))
+    t = 0.5
+    vp = -1.0 + (-9.0 + 1.0) * t / 2.0
+    want = n_at * np.sqrt(vp * u0) * theta / (s.delta_c - n_at * u0 * c2 + 1j * s.kappa)
+    got = O.alpha_adiabatic(problem(s), 3.0 * psi, t)      # per unit norm: scale-free
+    assert abs(got - want) < 1e-10 * abs(want)
+    assert abs(O.cos2(problem(s), psi) - c2) < 1e-12
+
+
+def test_adiabatic_field_is_the_fast_cavity_limit_of_the_field_ode():
+    """The ODE cavity (pinned separately) with kappa = -Delta_c growing and the coupling
+    eta = N sqrt(Vp U0) (N ~ sqrt(kappa), so the field's effect on psi stays
+    comparable) follows the adiabatic field ever closer: the psi difference, relative
+    to the field's own effect on psi, falls at least as 1/kappa."""
+    psi0 = W.gaussian(adiabatic_setup(), 1.2, 0.3, 0.0)
+    ratios = []
+    for kap in (100.0, 400.0, 1600.0):
+        n_at = 4 * np.sqrt(kap)
+        sa = adiabatic_setup(cavity_mode="adiabatic", n_atoms=n_at, kappa=kap, delta_c=-kap, dt=1e-3)
+        pa = problem(sa)
+        c0 = O.cos2(pa, psi0) / O.norm(pa, psi0)
+        # the ODE's fixed detuning carries the initial dispersive shift
+        so = adiabatic_setup(eta=n_at * np.sqrt(5.0 * 0.5), kappa=kap, delta_c=-kap + 0.5 * n_at * c0,
+                             alpha0=O.alpha_adiabatic(pa, psi0, 0.0), dt=1e-3)
+        sn = adiabatic_setup(cavity=False, dt=1e-3)
+        ra, _ = O.step_real(pa, state(sa), psi0, 600)
+        ro, _ = O.step_real(problem(so), state(so), psi0, 600)
+        rn, _ = O.step_real(problem(sn), state(sn), psi0, 600)
+        ratios.append(rel_l2(ra, ro) / rel_l2(ra, rn))
+    # 1/kappa gives ~4 per step of kappa; a coupling or shift off by a factor that does
+    # not vanish with kappa stalls the ratio
+    assert ratios[0] / ratios[1] > 3.0 and ratios[1] / ratios[2] > 3.0, ratios
+    assert ratios[2] < 0.005, ratios
+
+
+def test_adiabatic_imaginary_time_fixed_point_is_self_consistent():
+    """Converged imaginary time with the adiabatic field (one value per step, from the
+    state entering it): the field of the converged state is the last one used, and
+    freezing the field at that value (the ODE model holds it fixed in imaginary time)
+    leaves the state a fixed point."""
+    sa = adiabatic_setup(cavity_mode="adiabatic", n_atoms=40.0, kappa=20.0, delta_c=-20.0, dt=0.01, g=20.0)
+    st = state(sa)
+    gs, _ = O.step_imag(problem(sa), st, W.gaussian(sa, 1.2, 0.3, 0.0), 3000)
+    a_fin = st.alpha
+    assert abs(a_fin) > 1e-2
+    assert abs(O.alpha_adiabatic(problem(sa), gs, 0.0) - a_fin) < 1e-9
+    sf = sa.with_(cavity_mode="ode", eta=0.0, kappa=0.0, delta_c=0.0, alpha0=a_fin)
+    out, _ = O.step_imag(problem(sf), state(sf), gs, 20)
+    assert rel_l2(out, gs) < 1e-7
