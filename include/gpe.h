@@ -16,10 +16,16 @@
  *     + Vc |alpha|^2 cos^2(kc x)
  *     + 2 sqrt(Vy(t) Vc) Re(alpha) cos(kc x) cos(kc y)             cavity (Sec. 5.3, Eqs. 13-16)
  *     + V_user(x, y)                                              optional static array
- * and, with the cavity on, the field alpha obeys
+ * and the cavity field alpha either (GPE_CAVITY_ODE) obeys
  *   d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta,  Theta = <psi| cos kc x cos kc y |psi>
  * (the driven-damped form whose fixed point is Sec. 5.3, Eq. 17), advanced once per
- * step by an exponential integrator with the forcing extrapolated to second order.
+ * step by an exponential integrator with the forcing extrapolated to second order, or
+ * (GPE_CAVITY_ADIABATIC) is Eq. 17 itself with the dispersive shift of Eq. 18,
+ *   alpha = N sqrt(Vy(t) Vc) Theta / (Delta_c - N Vc C + i kappa),  C = <psi| cos^2 kc x |psi>,
+ * Theta and C per unit norm, N = n_atoms, evaluated from the density about to be kicked:
+ * before every kick in real time (a probe pass reduces that density first), once per
+ * step from the state entering it in imaginary time.  The on-axis cavity probe of
+ * Sec. 5.4 adds Omega_c e^{i (Delta_p t + phi)} / (Delta_c - N Vc C + i kappa) to it.
  *
  * Grid: x_i = -lx/2 + i lx/nx (i < nx), likewise y; psi is stored row-major
  * [ny][nx] (x fastest) as interleaved (re, im) floats; periodic boundaries (the FFT
@@ -92,9 +98,15 @@ typedef struct {
 } gpe_schedule;
 
 /* Potential description (Sec. 5.1-5.3).  The pump lattice of the cavity model is the
- * y lattice (depth Vy(t)); its interference term uses kc.  v_user: optional device
- * float array [ny][nx], borrowed for as long as the plan uses it.  Setting a
- * potential resets the cavity field to alpha0 and forgets the overlap history. */
+ * y lattice (depth Vy(t)); its interference term uses kc and sqrt(Vy Vc), so the pump
+ * schedule's values and vc must not differ in sign (GPE_ERR_INVALID).  cavity: one of
+ * GPE_CAVITY_*; eta is the ODE's coupling, n_atoms the adiabatic field's N.  v_user:
+ * optional device float array [ny][nx], borrowed for as long as the plan uses it.
+ * Setting a potential resets the cavity field to alpha0 and forgets the overlap
+ * history. */
+#define GPE_CAVITY_OFF 0
+#define GPE_CAVITY_ODE 1
+#define GPE_CAVITY_ADIABATIC 2
 typedef struct {
     double wx, wy, x0, y0;
     double kx_lat, ky_lat;
@@ -103,6 +115,8 @@ typedef struct {
     double vc, kc, delta_c, kappa, eta;
     double alpha0_re, alpha0_im;
     const float *v_user;
+    double n_atoms;
+    double probe_omega, probe_detuning, probe_phase;  // Omega_c, Delta_p, phi (adiabatic field only)
 } gpe_potential_desc;
 
 /* Per-step observables written by gpe_step_real / gpe_step_imag into a device array
@@ -135,8 +149,10 @@ int gpe_step_real(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t0, doubl
  * The cavity must be off (GPE_ERR_UNSUPPORTED otherwise). */
 int gpe_step_real_k(gpe_plan *plan, gpe_c64 *psik, int64_t nsteps, double t0, double *obs);
 
-/* nsteps imaginary-time steps (Sec. 3.3) with the potential frozen at time t and the
- * cavity field held fixed; psi ends with unit norm.  obs as for gpe_step_real. */
+/* nsteps imaginary-time steps (Sec. 3.3) with the potential frozen at time t; the ODE
+ * cavity field is held fixed, the adiabatic one follows the state (its value for the
+ * returned state is left in the plan); psi ends with unit norm.  obs as for
+ * gpe_step_real (the field recorded is the one the step used). */
 int gpe_step_imag(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t, double *obs);
 
 /* Energy functional of psi at time t with the plan's current cavity field
@@ -198,6 +214,11 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path);
 /* Description of size group g (synchronous): out = {nx, ny, members, lds-resident,
  * radix, row threads per work-group, column work-groups per member, number of groups}. */
 int gpe_batch_info(gpe_batch *b, int group, int out[8]);
+
+/* Cavity state of batch member m after the batch's last call, as gpe_get_cavity
+ * (synchronous; the adiabatic field of Sec. 5.3, Eqs. 17-18, is the only cavity model a
+ * batch runs, on members up to 128^2). */
+int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 
 /* ------------------------------------------------------------------ adjoint
  * Gradient of a loss of psi(T), T = t0 + nsteps dt, with respect to the knot values

@@ -83,6 +83,9 @@ typedef struct {
     /* optional extra static potential [ny][nx] (may be NULL) */
     const double *vuser;
     double n_atoms;
+    /* on-axis cavity probe of the adiabatic field (Sec. 5.4): strength Omega_c,
+     * detuning Delta_p from the pump, phase phi */
+    double probe_omega, probe_detuning, probe_phase;
 } orc_problem;
 
 /* Propagation state carried between calls. */
@@ -324,14 +327,18 @@ double orc_cos2(const orc_problem *p, const cplx *psi)
  *   alpha = N sqrt(Vp(t) U0) Theta / (Delta_c~ + i kappa),
  *   Delta_c~ = Delta_c - N U0 C,
  * Theta and C per unit norm (psi describes one atom; N = n_atoms counts them in both
- * the coupling and the shift), U0 = vc, Vp(t) the pump (y lattice) depth. */
+ * the coupling and the shift), U0 = vc, Vp(t) the pump (y lattice) depth.  With the
+ * on-axis probe of Sec. 5.4 the field becomes alpha + delta alpha(t),
+ *   delta alpha = Omega_c exp(i (Delta_p t + phi)) / (Delta_c~ + i kappa). */
 static cplx alpha_adiabatic(const orc_problem *p, const cplx *psi, double t)
 {
     double nrm = orc_norm(p, psi);
     double th = orc_theta(p, psi) / nrm, c2 = orc_cos2(p, psi) / nrm;
     double vp = sched_eval(&p->sy, t);
     double dtil = p->delta_c - p->n_atoms * p->vc * c2;
-    return p->n_atoms * sqrt(vp * p->vc) * th / (dtil + I * p->kappa);
+    cplx alpha = p->n_atoms * sqrt(vp * p->vc) * th / (dtil + I * p->kappa);
+    cplx dalpha = p->probe_omega * cexp(I * (p->probe_detuning * t + p->probe_phase)) / (dtil + I * p->kappa);
+    return alpha + dalpha;
 }
 
 void orc_alpha_adiabatic(const orc_problem *p, const cplx *psi, double t, double *out)
@@ -443,7 +450,8 @@ int orc_step_real(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps,
  * frozen at time s->t, then psi <- psi / sqrt(norm).  The ODE cavity field is held
  * fixed; the adiabatic one (cavity 2) is evaluated once per step from the state
  * entering it (the kicks change the density in imaginary time, so one value per step
- * is taken, and a converged state is then a fixed point of the frozen-field step). */
+ * is taken, and a converged state is then a fixed point of the frozen-field step);
+ * the state's field afterwards is that of the returned psi. */
 int orc_step_imag(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps, double *obs)
 {
     double h = 0.5 * p->dt;
@@ -463,7 +471,9 @@ int orc_step_imag(const orc_problem *p, orc_state *s, cplx *psi, int64_t nsteps,
             o[0] = nrm; /* pre-normalisation norm: -ln(o[0]) / (2 dtau) estimates mu */
         }
     }
-    if (p->cavity == 2) {
+    if (p->cavity == 2 && nsteps > 0) {
+        /* the field that belongs to the returned state */
+        alpha = alpha_adiabatic(p, psi, s->t);
         s->alpha_re = creal(alpha);
         s->alpha_im = cimag(alpha);
     }

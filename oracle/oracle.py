@@ -71,6 +71,9 @@ class _Problem(C.Structure):
         ("eta", C.c_double),
         ("vuser", C.POINTER(C.c_double)),
         ("n_atoms", C.c_double),
+        ("probe_omega", C.c_double),
+        ("probe_detuning", C.c_double),
+        ("probe_phase", C.c_double),
     ]
 
 
@@ -155,6 +158,9 @@ class Problem:
     eta: float = 0.0
     vuser: np.ndarray | None = None
     n_atoms: float = 0.0
+    probe_omega: float = 0.0
+    probe_detuning: float = 0.0
+    probe_phase: float = 0.0
 
     def _sched(self, s: Sched, keep: list) -> _Sched:
         kind = {"const": 0, "ramp": 1, "knots": 2, "pulse": 3}[s.kind]
@@ -177,6 +183,7 @@ class Problem:
         p.cavity = int(self.cavity)
         p.vc, p.kc, p.delta_c, p.kappa, p.eta = self.vc, self.kc, self.delta_c, self.kappa, self.eta
         p.n_atoms = self.n_atoms
+        p.probe_omega, p.probe_detuning, p.probe_phase = self.probe_omega, self.probe_detuning, self.probe_phase
         if self.vuser is not None:
             v = np.ascontiguousarray(self.vuser, dtype=np.float64)
             assert v.shape == (self.ny, self.nx)

@@ -161,7 +161,9 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
         if (descs[i].dt != descs[0].dt) return fail(GPE_ERR_INVALID, "batch members must share dt");
-        if (pots[i].cavity) return fail(GPE_ERR_UNSUPPORTED, "batched cavity members are not supported");
+        if (pots[i].cavity == GPE_CAVITY_ODE ||
+            (pots[i].cavity == GPE_CAVITY_ADIABATIC && !lds_supported(descs[i].nx, descs[i].ny)))
+            return fail(GPE_ERR_UNSUPPORTED, "batched cavity members: adiabatic field on grids up to 128^2 only");
     }
     gpe_batch *b = new gpe_batch();
     b->n = n;
@@ -442,6 +444,14 @@ int gpe_batch_info(gpe_batch *b, int group, int out[8])
     out[6] = g.shape.col_blocks;
     out[7] = (int)b->groups.size();
     return GPE_OK;
+}
+
+int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4])
+{
+    if (!b || !out || member < 0 || member >= b->n) return fail(GPE_ERR_INVALID, "bad member");
+    HIP_OK(hipStreamSynchronize(b->work));
+    HIP_OK(hipStreamSynchronize(b->side));
+    return gpe_get_cavity(b->plans[member], out);
 }
 
 // --------------------------------------------------------------------- adjoint

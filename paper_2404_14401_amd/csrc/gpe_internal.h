@@ -20,10 +20,14 @@ struct PotDev {
     const float4 *ty;  // [ny]
     const float *vuser;  // [ny][nx] or null
     Sched sx, sy;
-    int cavity;
+    int cavity;  // 0 off, 1 field ODE, 2 adiabatic field (Sec. 5.3, Eqs. 17-18)
     double vc;
     // cavity field step: alpha_{n+1} = ecav alpha_n + phi1 (-i eta Theta_bar)
     double ecav_re, ecav_im, phi1_re, phi1_im, eta;
+    // adiabatic field: alpha = N sqrt(Vp U0) Theta / (Delta_c - N U0 C + i kappa),
+    // plus the on-axis probe Omega_c e^{i (Delta_p t + phi)} over the same denominator
+    double delta_c, kappa, n_atoms;
+    double probe_omega, probe_detuning, probe_phase;
 };
 
 // Mutable device-side state of a plan (one per plan, in device memory).
@@ -49,7 +53,8 @@ struct GridDev {
     const double2 *kh_x, *kh_yin, *kh_yout;
 };
 
-constexpr int NPART = 4;  // norm, Theta, x moment, y moment (per work-group partials)
+// Per-work-group partials: norm, Theta, x moment, y moment, C = cos^2(kc x) overlap.
+constexpr int NPART = 5;
 constexpr int NOBS = 6;
 
 // Row-pass modes.
@@ -58,6 +63,8 @@ enum RowMode : int {
     ROW_MID = 1,    // IFFT_x -> merged kick at t_{n+1} -> FFT_x (real time)
     ROW_EXIT = 2,   // IFFT_x -> half kick at t_{n+1} -> real-space psi
     ROW_FWD = 3,    // real-space psi -> FFT_x, energy partials (E_pot, E_int, norm)
+    ROW_PROBE_REAL = 4,  // real-space psi -> partials of norm, Theta, C (no store)
+    ROW_PROBE_MID = 5,   // IFFT_x -> partials of norm, Theta, C (no store)
 };
 
 // Column-pass modes.
@@ -80,6 +87,8 @@ struct RowArgs {
     int reduce;        // write partials
     int lines_per_wg;
     double t_shift;    // -dt/2 for the midpoint kick of the Fourier-space ordering
+    const double *probe;  // adiabatic field: partials of the density about to be kicked
+    int nprobe;           // (0: take the field from the state)
 };
 
 // Work done by work-group 0 of a column pass before its own columns: reduce the
@@ -91,6 +100,7 @@ struct TailArgs {
     double *obs;       // record slot (NOBS doubles) or null
     int imag;          // imaginary-time bookkeeping (scale, pre-normalisation norm)
     int advance_alpha; // compute alpha_{n+1} after the reduction
+    int alpha_from_partials;  // adiabatic field of the reduced density (imaginary time)
 };
 
 struct ColArgs {

@@ -86,8 +86,9 @@ size_t adj_col_shmem(int n, int w, int r)
 // placed `smem` (exchange lines, then the staged tables).
 template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
-                                         const PotDev &pot, const DevState *st, double *partials, int n, int lb,
-                                         int lines, XchgT *smem, double *red, double t_shift = 0.0)
+                                         const PotDev &pot, DevState *st, double *partials, int n, int lb,
+                                         int lines, XchgT *smem, double *red, double t_shift = 0.0,
+                                         const double *probe = nullptr, int nprobe = 0)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -123,17 +124,58 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     __syncthreads();
 #endif
 
-    // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes V
-    double tk = st->t0;
-    if (!IMAG) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt + t_shift;
-    const VLine vl = vline_cav(pot, row, tk, st->alpha_re, st->alpha_im);
     const float4 ty = pot.ty[row];
     const double cy = ty.z, yv = ty.w;
+    if constexpr (MODE == ROW_PROBE_REAL || MODE == ROW_PROBE_MID) {
+        // integrals of the density about to be kicked: norm, Theta, C
+        if constexpr (MODE == ROW_PROBE_MID) fft_line<N, R, true>(v, lds, t, twx);
+        double part[NPART] = {};
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const double cx = txt[t + m * T].z;
+            const double d = v[m].x * v[m].x + v[m].y * v[m].y;
+            part[0] += d;
+            part[1] += cx * cy * d;
+            part[4] += cx * cx * d;
+        }
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) partials[k] = part[k];
+        return;
+    }
+
+    // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes
+    // V; the energy pass evaluates V at the call's own time
+    double tk = st->t0;
+    if (!IMAG && MODE != ROW_FWD) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt + t_shift;
+    double are, aim;
+    if (probe) {
+        // adiabatic field of the probed density, the same sum in every work-group
+        double s[NPART] = {};
+        for (int i = threadIdx.x; i < nprobe; i += blockDim.x)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) s[k] += probe[i * NPART + k];
+        block_sum<NPART>(s, red);
+        if (threadIdx.x == 0) alpha_adiabatic(pot, tk, s[0], s[1], s[4], &red[0], &red[1]);
+        __syncthreads();
+        are = red[0];
+        aim = red[1];
+        __syncthreads();
+        if (lb == 0 && threadIdx.x == 0) {
+            st->alpha_re = are;
+            st->alpha_im = aim;
+        }
+    } else {
+        are = st->alpha_re;
+        aim = st->alpha_im;
+    }
+    const VLine vl = vline_cav(pot, row, tk, are, aim);
     const float *vu = pot.vuser ? pot.vuser + (size_t)row * N : nullptr;
 
     if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, twx);
 
-    double part[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double part[NPART] = {};
     if constexpr (MODE == ROW_ENTRY && IMAG) {
         const double sc = st->scale;
 #pragma unroll
@@ -161,6 +203,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                     part[1] += (double)tx.z * cy * d2;
                     part[2] += (double)tx.w * d2;
                     part[3] += yv * d2;
+                    part[4] += (double)tx.z * tx.z * d2;
                 }
             } else {
                 // |psi| is the same before and after a phase kick
@@ -168,6 +211,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                 part[1] += (double)tx.z * cy * d;
                 part[2] += (double)tx.w * d;
                 part[3] += yv * d;
+                part[4] += (double)tx.z * tx.z * d;
                 v[m] = kick_real(v[m], th);
             }
         }
@@ -192,7 +236,7 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
     __shared__ double red[8 * NPART];
     row_body<N, kRadix, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
                                      a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
-                                     a.lines_per_wg, smem, red, a.t_shift);
+                                     a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe);
 }
 
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
@@ -264,7 +308,7 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
     if constexpr (MODE == COL_EKIN) {
         const int ix = col >= nx / 2 ? col - nx : col;
         const double kx = 2.0 * M_PI * ix / gd.lx;
-        double part[NPART] = {0.0, 0.0, 0.0, 0.0};
+        double part[NPART] = {};
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int j = t + m * T;
@@ -417,8 +461,9 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
     DevState *st = a.st;
     const int rl = threadIdx.x % LR, rt = threadIdx.x / LR;
     const int cl = threadIdx.x % LC, ct = threadIdx.x / LC;
-    const bool cav = pot.cavity && !a.imag;
-    const bool want = cav || a.obs != nullptr || a.imag;
+    const bool cav = pot.cavity == 1 && !a.imag;  // field ODE (real time only)
+    const bool adia = pot.cavity == 2;             // adiabatic field, both times
+    const bool want = cav || adia || a.obs != nullptr || a.imag;
     const double t0 = st->t0;
 
     for (int i = threadIdx.x; i < NX * NY; i += NTH) g[(i / NX) * P + (i % NX)] = a.psi[i];
@@ -461,6 +506,7 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
                     part[1] += (double)tx.z * (double)ty.z * d2;
                     part[2] += (double)tx.w * d2;
                     part[3] += (double)ty.w * d2;
+                    part[4] += (double)tx.z * (double)tx.z * d2;
                 }
                 g[row * P + i] = make_float2((float)p.x, (float)p.y);
             }
@@ -502,9 +548,31 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
         }
     };
 
+    // adiabatic field of the density now in LDS (norm, Theta, C), at time tk
+    auto probe_alpha = [&](double tk) {
+        double part[NPART] = {};
+        for (int r0 = 0; r0 < NY; r0 += LR) {
+            const int row = r0 + rl;
+            const double cy = pot.ty[row].z;
+            for (int m = 0; m < R; ++m) {
+                const int i = rt + m * TX;
+                const double cx = pot.tx[i].z;
+                const float2 f = g[row * P + i];
+                const double d = (double)f.x * f.x + (double)f.y * f.y;
+                part[0] += d;
+                part[1] += cx * cy * d;
+                part[4] += cx * cx * d;
+            }
+        }
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0) alpha_adiabatic(pot, tk, part[0], part[1], part[4], &s_are, &s_aim);
+        __syncthreads();
+    };
+    if (adia) probe_alpha(t0);
+
     if (cav && !st->have_theta) {
         // Theta_0 starts the overlap history
-        double part[NPART] = {0, 0, 0, 0};
+        double part[NPART] = {};
         for (int r0 = 0; r0 < NY; r0 += LR) {
             const int row = r0 + rl;
             const double cy = pot.ty[row].z;
@@ -536,12 +604,13 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
             s_are = nr;
             s_aim = ni;
         }
-        double part[NPART] = {0, 0, 0, 0};
+        double part[NPART] = {};
         kick_rows(tn, are0, aim0, sc, false, part);
         __syncthreads();
         rows_fft(std::integral_constant<bool, false>{});
         cols_kin();
         rows_fft(std::integral_constant<bool, true>{});
+        if (adia && !a.imag) probe_alpha(tn1);  // real time: field of the density at t_{n+1}
         kick_rows(tn1, s_are, s_aim, 1.0, want, part);
         __syncthreads();
         if (want) {
@@ -564,6 +633,8 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
                     o[4] = part[2] * inv;
                     o[5] = part[3] * inv;
                 }
+                // imaginary time: the field of the state just reduced drives the next step
+                if (adia && a.imag) alpha_adiabatic(pot, t0, part[0], part[1], part[4], &s_are, &s_aim);
             }
             __syncthreads();
         }
@@ -628,6 +699,8 @@ template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowAr
         else if (mode == ROW_MID) GPE_ROW(ROW_MID, false);
         else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, false);
         else if (mode == ROW_FWD) GPE_ROW(ROW_FWD, false);
+        else if (mode == ROW_PROBE_REAL) GPE_ROW(ROW_PROBE_REAL, false);
+        else if (mode == ROW_PROBE_MID) GPE_ROW(ROW_PROBE_MID, false);
         else return hipErrorInvalidValue;
     }
 #undef GPE_ROW

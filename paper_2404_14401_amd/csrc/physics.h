@@ -121,6 +121,27 @@ template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], dou
     __syncthreads();
 }
 
+// Adiabatic cavity field (Sec. 5.3, Eqs. 17-18) of a density with integrals nrm,
+// Theta = th and C = c2 at time t, with the on-axis probe of Sec. 5.4:
+//   [N sqrt(Vp(t) U0) (th/nrm) + Omega_c e^{i (Delta_p t + phi)}] / (Delta_c - N U0 c2/nrm + i kappa).
+__device__ __forceinline__ void alpha_adiabatic(const PotDev &p, double t, double nrm, double th, double c2,
+                                                double *are, double *aim)
+{
+    const double vp = sched_eval(p.sy, t);
+    const double inv = 1.0 / nrm;
+    const double dtil = p.delta_c - p.n_atoms * p.vc * c2 * inv;
+    double nr = p.n_atoms * sqrt(fmax(vp * p.vc, 0.0)) * th * inv, ni = 0.0;
+    if (p.probe_omega != 0.0) {
+        double s, c;
+        sincos(p.probe_detuning * t + p.probe_phase, &s, &c);
+        nr += p.probe_omega * c;
+        ni += p.probe_omega * s;
+    }
+    const double den = dtil * dtil + p.kappa * p.kappa;
+    *are = (nr * dtil + ni * p.kappa) / den;
+    *aim = (ni * dtil - nr * p.kappa) / den;
+}
+
 // Cavity field over one step (exponential integrator, second-order extrapolated
 // forcing): alpha <- ecav alpha + phi1 (-i eta (3 Theta_n - Theta_{n-1}) / 2).
 __device__ __forceinline__ void cavity_advance(const PotDev &p, DevState *st)
@@ -140,7 +161,7 @@ __device__ __forceinline__ void cavity_advance(const PotDev &p, DevState *st)
 __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot,
                                          DevState *st, double *red)
 {
-    double s[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double s[NPART] = {};
     if (ta.npartials > 0) {
         for (int i = threadIdx.x; i < ta.npartials; i += blockDim.x)
 #pragma unroll
@@ -164,7 +185,7 @@ __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, 
                     ta.obs[5] = my * inv;
                 }
             } else {
-                if (pot.cavity) {
+                if (pot.cavity == 1) {
                     if (ta.first_theta) {
                         st->theta = th;
                         st->theta_prev = th;
@@ -184,7 +205,11 @@ __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, 
                 }
             }
         }
-        if (ta.advance_alpha && pot.cavity) cavity_advance(pot, st);
+        // imaginary time: the adiabatic field of the state just reduced drives the next
+        // step (after the observables above recorded the field this step used)
+        if (ta.npartials > 0 && ta.alpha_from_partials && pot.cavity == 2)
+            alpha_adiabatic(pot, st->t0, s[0], s[1], s[4], &st->alpha_re, &st->alpha_im);
+        if (ta.advance_alpha && pot.cavity == 1) cavity_advance(pot, st);
     }
 }
 

@@ -141,7 +141,21 @@ int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
     int rc = check_sched(v->sx, "sx");
     if (rc) return rc;
     if ((rc = check_sched(v->sy, "sy"))) return rc;
-    if (v->cavity && v->vc < 0) return fail(GPE_ERR_INVALID, "cavity: vc must be >= 0");
+    if (v->cavity < 0 || v->cavity > 2) return fail(GPE_ERR_INVALID, "cavity must be 0, 1 (field ODE) or 2 (adiabatic)");
+    if (v->cavity) {
+        // the interference lattice carries sqrt(Vp U0): pump and cavity lattices share a sign
+        auto same_sign = [&](double x) { return x * v->vc >= 0; };
+        bool ok = same_sign(v->sy.v0) && (v->sy.kind == GPE_SCHED_CONST || same_sign(v->sy.v1));
+        if (v->sy.kind == GPE_SCHED_KNOTS && v->sy.knots)
+            for (int i = 0; i < v->sy.nknots; ++i) ok = ok && same_sign(v->sy.knots[i]);
+        if (!ok) return fail(GPE_ERR_INVALID, "cavity: the pump depth (y lattice) and vc must not differ in sign");
+    }
+    if (v->cavity == 2 && !(v->n_atoms >= 0 && std::isfinite(v->n_atoms)))
+        return fail(GPE_ERR_INVALID, "cavity: n_atoms must be finite and >= 0");
+    if (!std::isfinite(v->probe_omega) || !std::isfinite(v->probe_detuning) || !std::isfinite(v->probe_phase))
+        return fail(GPE_ERR_INVALID, "probe parameters must be finite");
+    if (v->probe_omega != 0 && v->cavity != 2)
+        return fail(GPE_ERR_INVALID, "the cavity probe acts on the adiabatic field only");
     HIP_OK(hipStreamSynchronize(p->stream));
     const int nx = p->nx, ny = p->ny;
     std::vector<float4> tx(nx), ty(ny);
@@ -167,9 +181,15 @@ int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
     d.vuser = v->v_user;
     d.sx = to_sched(v->sx, p->knots_x);
     d.sy = to_sched(v->sy, p->knots_y);
-    d.cavity = v->cavity ? 1 : 0;
+    d.cavity = v->cavity;
     d.vc = v->vc;
     d.eta = v->eta;
+    d.delta_c = v->delta_c;
+    d.kappa = v->kappa;
+    d.n_atoms = v->n_atoms;
+    d.probe_omega = v->probe_omega;
+    d.probe_detuning = v->probe_detuning;
+    d.probe_phase = v->probe_phase;
     const std::complex<double> lam(-v->kappa, v->delta_c);
     const std::complex<double> e = std::exp(lam * p->dt);
     const std::complex<double> phi1 = std::abs(lam) > 0 ? (e - 1.0) / lam : std::complex<double>(p->dt, 0.0);
@@ -248,6 +268,7 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 256);
     if ((rc = dalloc(p, (void **)&p->partials, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->partials2, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
+    if ((rc = dalloc(p, (void **)&p->probe, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->scratch, sizeof(float2) * (size_t)nx * ny))) return cleanup(rc);
     if (hipHostMalloc((void **)&p->hpart, sizeof(double) * NPART * p->npart_max) != hipSuccess)
         return cleanup(fail(GPE_ERR_NOMEM, "hipHostMalloc"));
@@ -346,12 +367,60 @@ static int run_lds(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *
     return GPE_OK;
 }
 
+}  // extern "C"
+
+// Real time with the adiabatic field (multi-pass): before every kick a probe pass
+// reduces the density about to be kicked (norm, Theta, C), and each work-group of
+// the kicking row pass turns those sums into alpha at the kick time:
+//   probe(psi_0), entry kick at t_0 | per step: columns, probe (IFFT_x), merged kick.
+static int step_real_adiabatic(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *obs)
+{
+    const Shape &sh = p->shape;
+    float2 *f = (float2 *)psi;
+    LAUNCH_OK(launch_set_call(p->st, t0, 0, 0, p->stream));
+    RowArgs pa = row_args(p, f);
+    pa.partials = p->probe;
+    pa.reduce = 1;
+    LAUNCH_OK(launch_row(p->nx, ROW_PROBE_REAL, false, pa, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+    RowArgs ra = row_args(p, f);
+    ra.probe = p->probe;
+    ra.nprobe = sh.row_blocks;
+    ra.n = 0;
+    LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+    ra.reduce = obs ? 1 : 0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        ColArgs ca = col_args(p, f);
+        TailArgs &ta = ca.tail;
+        ta.partials = p->partials;
+        ta.npartials = (n >= 1 && obs) ? sh.row_blocks : 0;
+        ta.obs = (n >= 1 && obs) ? obs + (n - 1) * NOBS : nullptr;
+        ca.do_tail = ta.npartials > 0 ? 1 : 0;
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        pa.n = (int)n;
+        LAUNCH_OK(launch_row(p->nx, ROW_PROBE_MID, false, pa, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        ra.n = (int)n;
+        LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, ra, sh.row_blocks, sh.row_threads,
+                             sh.row_shmem, p->stream));
+    }
+    if (obs) {
+        TailArgs ta{};
+        ta.partials = p->partials;
+        ta.npartials = sh.row_blocks;
+        ta.obs = obs + (nsteps - 1) * NOBS;
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+    }
+    return GPE_OK;
+}
+
+extern "C" {
+
 int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *obs)
 {
     if (!p || !psi || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
     if (!std::isfinite(t0)) return fail(GPE_ERR_INVALID, "t0 must be finite");
     if (nsteps == 0) return GPE_OK;
     if (use_lds(p)) return run_lds(p, psi, nsteps, t0, obs, false);
+    if (p->pot.cavity == 2) return step_real_adiabatic(p, psi, nsteps, t0, obs);
     const Shape &sh = p->shape;
     float2 *f = (float2 *)psi;
     const bool cav = p->pot.cavity != 0;
@@ -432,6 +501,19 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
     const Shape &sh = p->shape;
     float2 *f = (float2 *)psi;
     LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
+    const bool adia = p->pot.cavity == 2;
+    if (adia) {
+        // the adiabatic field of psi_0 drives the first step
+        RowArgs pa = row_args(p, f);
+        pa.partials = p->probe;
+        pa.reduce = 1;
+        LAUNCH_OK(launch_row(p->nx, ROW_PROBE_REAL, false, pa, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        TailArgs ta{};
+        ta.partials = p->probe;
+        ta.npartials = sh.row_blocks;
+        ta.alpha_from_partials = 1;
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+    }
     RowArgs ra = row_args(p, f);
     for (int64_t n = 0; n < nsteps; ++n) {
         ra.n = (int)n;
@@ -446,6 +528,7 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
         ta.partials = p->partials;
         ta.npartials = sh.row_blocks;
         ta.imag = 1;
+        ta.alpha_from_partials = adia ? 1 : 0;
         ta.obs = obs ? obs + n * NOBS : nullptr;
         LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
     }

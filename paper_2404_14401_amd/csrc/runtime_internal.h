@@ -85,6 +85,7 @@ struct gpe_plan {
     double2 *kh_x = nullptr, *kh_yin = nullptr, *kh_yout = nullptr;
     double *kim_x = nullptr, *kim_y = nullptr;
     double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
+    double *probe = nullptr;  // partials of the density about to be kicked (adiabatic field)
     int npart_max = 0;
     float2 *scratch = nullptr;
     double *knots_x = nullptr, *knots_y = nullptr;

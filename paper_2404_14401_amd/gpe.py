@@ -32,7 +32,7 @@ EXPORTS = (
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
     "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
-    "gpe_adjoint",
+    "gpe_batch_get_cavity", "gpe_adjoint",
 )
 
 
@@ -62,7 +62,8 @@ class PotentialDesc(C.Structure):
         ("kx_lat", C.c_double), ("ky_lat", C.c_double), ("sx", Schedule), ("sy", Schedule),
         ("cavity", C.c_int32), ("vc", C.c_double), ("kc", C.c_double), ("delta_c", C.c_double),
         ("kappa", C.c_double), ("eta", C.c_double), ("alpha0_re", C.c_double), ("alpha0_im", C.c_double),
-        ("v_user", C.c_void_p),
+        ("v_user", C.c_void_p), ("n_atoms", C.c_double), ("probe_omega", C.c_double),
+        ("probe_detuning", C.c_double), ("probe_phase", C.c_double),
     ]
 
 
@@ -97,6 +98,7 @@ def lib():
         L.gpe_step_batched.argtypes = [P, P, I64, D]
         L.gpe_batch_tune.argtypes = [P, C.c_char_p]
         L.gpe_batch_info.argtypes = [P, I, P]
+        L.gpe_batch_get_cavity.argtypes = [P, I, P]
         L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, D, P, P, P, P]
         for name in EXPORTS:
             if name != "gpe_last_error":
@@ -137,7 +139,9 @@ def potential_desc(setup, v_user=None):
     d.kx_lat, d.ky_lat = setup.kx_lat, setup.ky_lat
     d.sx = _sched(setup.sx, keep)
     d.sy = _sched(setup.sy, keep)
-    d.cavity = int(setup.cavity)
+    d.cavity = (2 if setup.cavity_mode == "adiabatic" else 1) if setup.cavity else 0
+    d.n_atoms = float(setup.n_atoms)
+    d.probe_omega, d.probe_detuning, d.probe_phase = setup.probe_omega, setup.probe_detuning, setup.probe_phase
     d.vc, d.kc, d.delta_c, d.kappa, d.eta = setup.vc, setup.kc, setup.delta_c, setup.kappa, setup.eta
     a0 = complex(setup.alpha0)
     d.alpha0_re, d.alpha0_im = a0.real, a0.imag
@@ -293,6 +297,12 @@ class Batch:
             res.append(dict(nx=out[0], ny=out[1], members=out[2], lds=bool(out[3]), radix=out[4],
                             row_threads=out[5], col_blocks=out[6]))
         return res
+
+    def cavity(self, member: int) -> complex:
+        """Cavity field of one member after the last call."""
+        out = np.zeros(4)
+        check(lib().gpe_batch_get_cavity(self._h, int(member), out.ctypes.data))
+        return complex(out[0], out[1])
 
 
 def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, mode: str = "auto",

@@ -64,6 +64,11 @@ class Setup:
     # current density (Sec. 5.3), N = n_atoms
     cavity_mode: str = "ode"
     n_atoms: float = 0.0
+    # on-axis probe of the adiabatic field (Sec. 5.4): alpha += Omega_c e^{i (Delta_p t + phi)}
+    # / (Delta_c - N U0 C + i kappa)
+    probe_omega: float = 0.0
+    probe_detuning: float = 0.0
+    probe_phase: float = 0.0
 
     def xs(self) -> np.ndarray:
         return -0.5 * self.lx + np.arange(self.nx) * (self.lx / self.nx)
@@ -190,6 +195,47 @@ def kapitza_dirac_start(s: Setup) -> np.ndarray:
     rounded to complex64."""
     if s.g == 0.0:
         return to_c64(gaussian(s, 1.0))
+    return to_c64(thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi))))
+
+
+# Self-organisation in a transversely pumped cavity (Sec. 5.3, Fig. 5), dimensionless:
+# a 128^2 grid on [-8, 8)^2 (dx = 1/8), unit isotropic trap, g = 200 (Thomas-Fermi
+# radius ~4, about five lattice periods), pump lattice Vp cos^2(k y) and cavity mode
+# along x with k = 2 (E_r = k^2/2 = 2), both red detuned (Vp, U0 < 0), U0 = -2e-3,
+# N = 2000 atoms (N |U0| = 4, so the dispersive shift is ~2), kappa = 5 and a negative
+# detuning.  Each member ramps the pump from 0 to its final depth linearly over T = 2
+# (a shortened stand-in for the paper's 0 -> 15 E_r ramp), then holds it.  The sweep
+# is a grid of final depths (0.5 .. 15 E_r) times detunings, Fig. 5b's axes.
+SO_DT = 1e-3
+SO_RAMP = 2.0
+
+
+def self_organisation_128(vp_er: float, delta_c: float, g: float = 200.0) -> Setup:
+    k = 2.0
+    er = 0.5 * k * k
+    return Setup(nx=128, ny=128, lx=16.0, ly=16.0, dt=SO_DT, g=g, wx=1.0, wy=1.0, ky_lat=k,
+                 sy=Schedule("ramp", 0.0, -vp_er * er, 0.0, SO_RAMP), cavity=True, cavity_mode="adiabatic",
+                 vc=-2e-3, kc=k, delta_c=delta_c, kappa=5.0, n_atoms=2000.0)
+
+
+def self_organisation_sweep(n_vp: int = 16, detunings=(-5.0, -10.0, -20.0, -40.0, -80.0)) -> list[Setup]:
+    """Members in (detuning, depth) order: final depths evenly on [0.5, 15] E_r."""
+    return [self_organisation_128(float(v), float(d)) for d in detunings for v in np.linspace(0.5, 15.0, n_vp)]
+
+
+def bragg_probe_128(vp_er: float, delta_p: float, omega_er: float = 10.0, delta_c: float = -10.0) -> Setup:
+    """Cavity Bragg spectroscopy (Sec. 5.4, Fig. 6) on the self-organisation setup: the
+    pump held at vp_er E_r (below or near threshold) and the on-axis probe of strength
+    omega_er E_r at detuning delta_p from the pump.  The probing run starts from the
+    imaginary-time ground state of the same setup with the probe off."""
+    er = 2.0
+    s = self_organisation_128(vp_er, delta_c)
+    return s.with_(sy=Schedule("const", -vp_er * er), probe_omega=omega_er * er, probe_detuning=delta_p)
+
+
+def self_organisation_start(s: Setup) -> np.ndarray:
+    """Thomas-Fermi profile of the trap alone, mu = sqrt(g / pi); complex64.  The finite
+    trap gives Theta != 0 from the start, so no symmetry-breaking seed is needed."""
     return to_c64(thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi))))
 
 

@@ -15,7 +15,8 @@ def problem(s: Setup) -> O.Problem:
     return O.Problem(nx=s.nx, ny=s.ny, lx=s.lx, ly=s.ly, dt=s.dt, g=s.g, wx=s.wx, wy=s.wy, x0=s.x0,
                      y0=s.y0, kx_lat=s.kx_lat, ky_lat=s.ky_lat, sx=sch(s.sx), sy=sch(s.sy),
                      cavity=(2 if s.cavity_mode == "adiabatic" else 1) if s.cavity else 0, vc=s.vc, kc=s.kc,
-                     delta_c=s.delta_c, kappa=s.kappa, eta=s.eta, n_atoms=s.n_atoms)
+                     delta_c=s.delta_c, kappa=s.kappa, eta=s.eta, n_atoms=s.n_atoms, probe_omega=s.probe_omega,
+                     probe_detuning=s.probe_detuning, probe_phase=s.probe_phase)
 
 
 def state(s: Setup, t: float = 0.0) -> O.State:

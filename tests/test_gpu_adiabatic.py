@@ -1,0 +1,198 @@
+"""The adiabatic cavity field (Sec. 5.3, Eqs. 17-18: alpha from the current density, with
+the dispersively shifted detuning) on the GPU against the FP64 oracle, on both paths,
+in real and imaginary time, and in batched form over a Fig. 5-shaped sweep."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_14401_amd import workloads as W
+from tests.bridge import problem, state
+from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def make_plan(s, path, monkeypatch):
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    monkeypatch.setenv("GPE_PATH", path)
+    return gpe.Plan.from_setup(s)
+
+
+def close_alpha(a, ref, rel):
+    return abs(a - ref) <= rel * max(abs(ref), 1e-3)
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_adiabatic_few_steps_every_term(path, monkeypatch):
+    """Non-square grid, random state, displaced trap, both lattices, a pump ramp: three
+    real and three imaginary steps."""
+    s = W.Setup(nx=64, ny=32, lx=12.0, ly=8.0, dt=0.02, g=30.0, wx=1.1, wy=0.8, x0=0.3, y0=-0.2,
+                kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("const", 1.5), sy=W.Schedule("ramp", -1.0, -6.0, 0.0, 0.2),
+                cavity=True, cavity_mode="adiabatic", vc=-0.3, kc=1.7, delta_c=-4.0, kappa=2.0, n_atoms=30.0)
+    psi0 = W.random_state(s, 7)
+    for mode in ("real", "imag"):
+        st = state(s, 0.05)
+        fn = O.step_real if mode == "real" else O.step_imag
+        ref, robs = fn(problem(s), st, psi0, 3, want_obs=True)
+        plan = make_plan(s, path, monkeypatch)
+        import torch
+
+        d = to_dev(psi0)
+        obs = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+        (plan.step_real if mode == "real" else plan.step_imag)(d, 3, 0.05, obs)
+        assert rel_l2(to_host(d), ref) < 2e-6, mode
+        o = obs.cpu().numpy()
+        for n in range(3):
+            assert close_alpha(o[n, 2] + 1j * o[n, 3], robs[n, 2] + 1j * robs[n, 3], 1e-5), (mode, n)
+        assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-5), mode
+        assert abs(st.alpha) > 1e-2
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_adiabatic_real_time_self_organisation_128(path, monkeypatch):
+    """The deepest member of the sweep (ramp to 15 E_r, Delta_c = -10) over its first
+    1000 steps: psi, energy and the field at every step."""
+    s = W.self_organisation_128(15.0, -10.0)
+    psi0 = W.self_organisation_start(s)
+    n = 1000
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, n, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, n, 0.0, obs)
+    out = to_host(d)
+    assert rel_l2(out, ref) < 1e-4
+    t = n * s.dt
+    e_ref = O.energy(problem(s), ref, t, st.alpha)["e"]
+    assert abs(plan.energy(d, t)["e"] - e_ref) / abs(e_ref) < 1e-5
+    o = obs.cpu().numpy()
+    a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
+    assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
+    assert np.abs(o[:, 1] - robs[:, 1]).max() < 1e-6
+    assert np.abs(a_ref).max() > 0.05
+
+
+def test_adiabatic_real_time_multipass_256(monkeypatch):
+    """Same physics on a 256^2 grid over a 32^2 box (multi-pass only)."""
+    s = W.self_organisation_128(12.0, -10.0).with_(nx=256, ny=256, lx=32.0, ly=32.0)
+    psi0 = W.self_organisation_start(s)
+    n = 400
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, n, want_obs=True)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    plan.step_real(d, n, 0.0)
+    assert rel_l2(to_host(d), ref) < 1e-4
+    assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-4)
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_adiabatic_imaginary_time_ground_state(path, monkeypatch):
+    """Imaginary time at a fixed pump of 10 E_r: the self-consistent state, its field and
+    the field recorded at every step."""
+    s = W.self_organisation_128(10.0, -10.0).with_(dt=0.005, sy=W.Schedule("const", -20.0))
+    psi0 = W.self_organisation_start(s)
+    n = 600
+    st = state(s)
+    ref, robs = O.step_imag(problem(s), st, psi0, n, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_imag(d, n, 0.0, obs)
+    assert rel_l2(to_host(d), ref) < 1e-4
+    assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-4)
+    o = obs.cpu().numpy()
+    a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
+    assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
+    assert np.abs(o[:, 0] - robs[:, 0]).max() < 3e-7
+
+
+def test_adiabatic_batched_sweep_matches_plain_solver_and_oracle():
+    """A 3 x 4 (detuning x final depth) slice of the Fig. 5-shaped sweep in one batch:
+    every member equals the plain solver (same kernel arithmetic), two equal the oracle."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = W.self_organisation_sweep(n_vp=4, detunings=(-5.0, -10.0, -40.0))
+    psi0 = [W.self_organisation_start(s) for s in setups]
+    b = gpe.Batch(setups)
+    assert all(g["lds"] for g in b.groups())
+    devs = [to_dev(p) for p in psi0]
+    n = 300
+    b.step(devs, n, 0.0)
+    for i, s in enumerate(setups):
+        plain = gpe.Plan.from_setup(s)
+        d = to_dev(psi0[i])
+        plain.step_real(d, n, 0.0)
+        assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-6, i
+        assert close_alpha(b.cavity(i), plain.cavity()["alpha"], 1e-6), i
+        if i in (3, 7):
+            st = state(s)
+            ref, _ = O.step_real(problem(s), st, psi0[i], n)
+            assert rel_l2(to_host(devs[i]), ref) < 1e-4, i
+            assert close_alpha(b.cavity(i), st.alpha, 1e-4), i
+
+
+def test_batch_rejects_unsupported_cavity_members():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.Batch([W.self_organisation_128(5.0, -10.0).with_(nx=256, ny=256, lx=32.0, ly=32.0)])
+    assert e.value.code == gpe.ERR_UNSUPPORTED
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.Batch([W.cavity_scaled(64, 0)])
+    assert e.value.code == gpe.ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------ Bragg probe (Sec. 5.4)
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_probe_field_without_atoms(path, monkeypatch):
+    """N = 0: the recorded field is the driven cavity's closed form at every step."""
+    s = W.Setup(nx=32, ny=32, lx=8.0, ly=8.0, dt=0.01, g=5.0, ky_lat=2.0, sy=W.Schedule("const", 0.5),
+                cavity=True, cavity_mode="adiabatic", vc=1.0, kc=2.0, delta_c=-7.0, kappa=3.0, n_atoms=0.0,
+                probe_omega=2.5, probe_detuning=3.3, probe_phase=0.4)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(W.gaussian(s, 1.0))
+    obs = torch.zeros((50, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, 50, 0.2, obs)
+    o = obs.cpu().numpy()
+    t = 0.2 + s.dt * np.arange(1, 51)
+    want = 2.5 * np.exp(1j * (3.3 * t + 0.4)) / (-7.0 + 3.0j)
+    assert np.abs(o[:, 2] + 1j * o[:, 3] - want).max() < 1e-12
+
+
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_bragg_probe_on_the_cavity_ground_state(path, monkeypatch):
+    """Ground state at 6 E_r (imaginary time, probe off), then 800 probing steps at
+    Delta_p = 4: psi, the field at every step and the final energy against the oracle."""
+    s = W.bragg_probe_128(6.0, 4.0)
+    s0 = s.with_(probe_omega=0.0, dt=0.005)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.self_organisation_start(s0), 800)
+    psi0 = W.to_c64(gs)
+    n = 800
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, n, want_obs=True)
+    plan = make_plan(s, path, monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, n, 0.0, obs)
+    assert rel_l2(to_host(d), ref) < 1e-4
+    o = obs.cpu().numpy()
+    a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
+    assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
+    t = n * s.dt
+    e_ref = O.energy(problem(s), ref, t, st.alpha)["e"]
+    assert abs(plan.energy(d, t)["e"] - e_ref) / abs(e_ref) < 1e-5

@@ -83,6 +83,17 @@ def test_energy_and_norm_functionals(path, monkeypatch):
     assert rel_e(plan.norm(d), O.norm(problem(s), psi0)) < 1e-12
 
 
+@pytest.mark.parametrize("path", ["lds", "multipass"])
+def test_energy_inside_a_ramp_is_taken_at_the_given_time(path, monkeypatch):
+    """Energy with a lattice that is still ramping: V must be evaluated at t itself."""
+    s = W.Setup(nx=64, ny=64, lx=12.0, ly=12.0, dt=0.01, g=40.0, kx_lat=1.5, sx=W.Schedule("ramp", 0.0, 30.0, 0.0, 1.0))
+    psi0 = W.random_state(s, 9)
+    plan = make_plan(s, path, monkeypatch)
+    d = to_dev(psi0)
+    for t in (0.0, 0.37, 0.8):
+        assert rel_e(plan.energy(d, t)["e"], O.energy(problem(s), psi0, t)["e"]) < 1e-9, t
+
+
 # ----------------------------------------------- imaginary-time ground state
 
 @pytest.mark.parametrize("path", ["lds", "multipass"])

@@ -591,15 +591,59 @@ def test_adiabatic_field_is_the_fast_cavity_limit_of_the_field_ode():
 
 def test_adiabatic_imaginary_time_fixed_point_is_self_consistent():
     """Converged imaginary time with the adiabatic field (one value per step, from the
-    state entering it): the field of the converged state is the last one used, and
-    freezing the field at that value (the ODE model holds it fixed in imaginary time)
-    leaves the state a fixed point."""
+    state entering it): the field recorded for the last step is that of the returned
+    state, and freezing the field at that value (the ODE model holds it fixed in
+    imaginary time) leaves the state a fixed point."""
     sa = adiabatic_setup(cavity_mode="adiabatic", n_atoms=40.0, kappa=20.0, delta_c=-20.0, dt=0.01, g=20.0)
     st = state(sa)
-    gs, _ = O.step_imag(problem(sa), st, W.gaussian(sa, 1.2, 0.3, 0.0), 3000)
+    gs, obs = O.step_imag(problem(sa), st, W.gaussian(sa, 1.2, 0.3, 0.0), 3000, want_obs=True)
     a_fin = st.alpha
     assert abs(a_fin) > 1e-2
-    assert abs(O.alpha_adiabatic(problem(sa), gs, 0.0) - a_fin) < 1e-9
+    assert abs(obs[-1, 2] + 1j * obs[-1, 3] - a_fin) < 1e-9
     sf = sa.with_(cavity_mode="ode", eta=0.0, kappa=0.0, delta_c=0.0, alpha0=a_fin)
     out, _ = O.step_imag(problem(sf), state(sf), gs, 20)
     assert rel_l2(out, gs) < 1e-7
+
+
+# ------------------------------------------------- Bragg probe of the cavity (Sec. 5.4)
+
+def test_probe_field_without_atoms_is_the_driven_cavity():
+    """With no atoms coupled (N = 0) the adiabatic field is the probe's alone,
+    delta alpha(t) = Omega_c e^{i (Delta_p t + phi)} / (Delta_c + i kappa), recorded at
+    t_{n+1} after every real-time step."""
+    s = W.Setup(nx=32, ny=32, lx=8.0, ly=8.0, dt=0.01, g=5.0, ky_lat=2.0, sy=W.Schedule("const", 0.5),
+                cavity=True, cavity_mode="adiabatic", vc=1.0, kc=2.0, delta_c=-7.0, kappa=3.0, n_atoms=0.0,
+                probe_omega=2.5, probe_detuning=3.3, probe_phase=0.4)
+    st = state(s, 0.2)
+    _, obs = O.step_real(problem(s), st, W.gaussian(s, 1.0), 50, want_obs=True)
+    t = 0.2 + s.dt * np.arange(1, 51)
+    want = 2.5 * np.exp(1j * (3.3 * t + 0.4)) / (-7.0 + 3.0j)
+    assert np.abs(obs[:, 2] + 1j * obs[:, 3] - want).max() < 1e-13
+
+
+def bragg_response(g_n, dp):
+    """Population of the (+-k, +-k) modes of a uniform condensate after probing for
+    T = 20 at detuning dp (no atoms coupled to the cavity, a weak pump, k = 2)."""
+    k, L = 2.0, 2 * np.pi
+    s = W.Setup(nx=32, ny=32, lx=L, ly=L, dt=0.01, g=g_n * L * L, wx=0.0, wy=0.0, ky_lat=k,
+                sy=W.Schedule("const", 0.02), cavity=True, cavity_mode="adiabatic", vc=2.0, kc=k,
+                delta_c=-50.0, kappa=10.0, n_atoms=0.0, probe_omega=6.0, probe_detuning=float(dp))
+    out, _ = O.step_real(problem(s), state(s), np.full((32, 32), 1.0 / L, dtype=complex), 2000)
+    f = np.abs(O.fft2d(out)) ** 2
+    f /= f.sum()
+    return f[2, 2] + f[2, -2] + f[-2, 2] + f[-2, -2]   # bins +-k L / (2 pi) = +-2
+
+
+@pytest.mark.parametrize("g_n", [0.0, 2.0])
+def test_bragg_response_peaks_at_the_bogoliubov_energy(g_n):
+    """The probe's interference lattice cos(kx) cos(ky), modulated at Delta_p, drives
+    the mode k = (k, k) of a uniform condensate; its response peaks at the Bogoliubov
+    energy sqrt(eps (eps + 2 g n)), eps = |k|^2 / 2 (the dispersion of Sec. 5.4 without
+    the cavity-mediated term), to within the scan step."""
+    eps = 4.0
+    want = np.sqrt(eps * (eps + 2 * g_n))
+    coarse = np.arange(2.0, 9.01, 0.5)
+    c0 = coarse[np.argmax([bragg_response(g_n, d) for d in coarse])]
+    fine = np.arange(c0 - 0.5, c0 + 0.51, 0.1)
+    peak = fine[np.argmax([bragg_response(g_n, d) for d in fine])]
+    assert abs(peak - want) <= 0.1, (peak, want)
