@@ -170,6 +170,90 @@ def bench_adjoint(steps: int, nb: int):
     return out
 
 
+def _timed(fn) -> float:
+    import torch
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3
+
+
+def bench_widened(steps: int):
+    """The paths beyond the main step: the Fourier-space ordering with momentum-order
+    populations (Kapitza-Dirac, 512^2, and the 1024^2 grid without the cavity), the
+    adiabatic cavity field at 1024^2 (probe pass + two passes per step), and the
+    self-organisation sweep in batched form (80 members at 128^2)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    out = {}
+    # Fourier-space ordering on the 1024^2 grid (cavity off): two passes per step
+    s = W.cavity_1024(0).with_(cavity=False)
+    n = s.nx * s.ny
+    psik = torch.fft.fft2(torch.from_numpy(W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx))))
+                          .to("cuda"))
+    p = gpe.Plan.from_setup(s)
+    p.step_real_k(psik, 20, 0.0)
+    t = _timed(lambda: p.step_real_k(psik, steps, 0.0))
+    tm = _timed(lambda: [p.momentum_orders(psik, 1, 64, 7) for _ in range(20)]) / 20
+    out["kspace_1024"] = {"value": n * steps / t, "unit": "grid-point-steps/s", "steps": steps,
+                          "us_per_step": 1e6 * t / steps, "b_alg_per_point_step": 32,
+                          "hbm_frac": 32 * n * steps / t / (HBM_PEAK_GBS * 1e9),
+                          "momentum_orders_us": 1e6 * tm}
+    # adiabatic field at 1024^2: 8 B (probe read) + 2 x 16 B per point-step
+    s = W.cavity_1024_adiabatic(0)
+    psi = torch.from_numpy(W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx)))).to("cuda")
+    p = gpe.Plan.from_setup(s)
+    p.step_real(psi, 20, 0.0)
+    t = _timed(lambda: p.step_real(psi, steps, 20 * s.dt))
+    out["adiabatic_1024"] = {"value": n * steps / t, "unit": "grid-point-steps/s", "steps": steps,
+                             "us_per_step": 1e6 * t / steps, "b_alg_per_point_step": 40,
+                             "hbm_frac": 40 * n * steps / t / (HBM_PEAK_GBS * 1e9),
+                             "alpha": str(p.cavity()["alpha"])}
+    # Kapitza-Dirac at 512^2: the full flash with the three population snapshots
+    s = W.kapitza_dirac_512(W.KD_G)
+    psik = torch.fft.fft2(torch.from_numpy(W.kapitza_dirac_start(s)).to("cuda"))
+    p = gpe.Plan.from_setup(s)
+
+    def kd():
+        n0 = 0
+        pops = []
+        for snap in W.KD_SNAPSHOTS:
+            p.step_real_k(psik, snap - n0, n0 * s.dt)
+            n0 = snap
+            pops.append(p.momentum_orders(psik, 1, W.KD_ORDER_STEP, 2)[0].tolist())
+        return pops
+
+    kd()
+    psik = torch.fft.fft2(torch.from_numpy(W.kapitza_dirac_start(s)).to("cuda"))
+    res = []
+    t = _timed(lambda: res.append(kd()))
+    m = W.KD_SNAPSHOTS[-1]
+    out["kapitza_dirac_512"] = {"value": s.nx * s.ny * m / t, "unit": "grid-point-steps/s", "steps": m,
+                                "run_ms": 1e3 * t, "orders_-2..2_at_snapshots": res[0]}
+    # self-organisation sweep: 16 depths x 5 detunings at 128^2, batched vs plain loop
+    setups = W.self_organisation_sweep()
+    psis = [torch.from_numpy(W.self_organisation_start(x)).to("cuda") for x in setups]
+    b = gpe.Batch(setups)
+    b.step(psis, 20, 0.0)
+    t_b = _timed(lambda: b.step(psis, steps, 20 * W.SO_DT))
+    plans = [gpe.Plan.from_setup(x) for x in setups]
+    t_p = _timed(lambda: [q.step_real(y, steps, 0.0) for q, y in zip(plans, psis)])
+    pts = sum(x.nx * x.ny for x in setups)
+    out["self_organisation_sweep_128"] = {"members": len(setups), "value": pts * steps / t_b,
+                                          "unit": "grid-point-steps/s", "steps": steps,
+                                          "plain_loop_value": pts * steps / t_p, "speedup_vs_plain_loop": t_p / t_b,
+                                          "photons_max": float(max(abs(b.cavity(i)) ** 2 for i in range(len(setups))))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +265,8 @@ def main() -> int:
     ap.add_argument("--batched-steps", type=int, default=200, help="steps of the 208-member sweep (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="steps of the control gradient (0: skip)")
     ap.add_argument("--adjoint-batch", type=int, default=16)
+    ap.add_argument("--widened-steps", type=int, default=2000,
+                    help="steps of the Fourier-space, adiabatic-field and sweep legs (0: skip)")
     ap.add_argument("--tune-cache", default=os.path.join(HERE, "profiles", "tune_cache.txt"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (scale for rocprofv3 byte counters)")
@@ -280,6 +366,9 @@ def main() -> int:
     if args.batched_steps > 0:
         log("batched sweep ...")
         out["batched"] = bench_batched(args.batched_steps, args.tune_cache)
+    if args.widened_steps > 0:
+        log("widened rows ...")
+        out["widened"] = bench_widened(args.widened_steps)
     if args.adjoint_steps > 0:
         log("adjoint ...")
         out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)

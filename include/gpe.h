@@ -222,8 +222,11 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 
 /* ------------------------------------------------------------------ adjoint
  * Gradient of a loss of psi(T), T = t0 + nsteps dt, with respect to the knot values
- * of the x-lattice depth schedule (GPE_SCHED_KNOTS) of every member of a batch of
- * real-time problems of one grid size (no cavity).  Losses:
+ * of a lattice-depth schedule (GPE_SCHED_KNOTS) of every member of a batch of
+ * real-time problems of one grid size (no cavity): control GPE_CONTROL_X_LATTICE
+ * differentiates the x lattice Vx(t) cos^2(kx_lat x), GPE_CONTROL_PUMP the y lattice
+ * Vy(t) cos^2(ky_lat y), the pump of the cavity set-up (Sec. 5.3) with the cavity off.
+ * Losses:
  *   GPE_LOSS_FIDELITY: L = 1 - |<target|psi(T)>|^2, <a|b> = sum conj(a) b dx dy;
  *   GPE_LOSS_ENERGY:   L = E_kin + E_pot + E_int of psi(T) at time T.
  * The reverse sweep rebuilds the forward states by running each step backwards
@@ -233,7 +236,8 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
  * drift_tol (relative L2).
  * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each, target
  * ignored for the energy loss); knots: host, nb * nknots values (they replace the
- * members' x-lattice knots); loss: host, nb values; grad: host, nb * nknots values;
+ * members' knots of the controlled lattice); loss: host, nb values; grad: host,
+ * nb * nknots values;
  * psi_final (nullable): host array of nb device pointers receiving psi(T).
  * info (nullable): host, 4 doubles {mode used (1 reconstruct, 2 checkpoint),
  * reconstruction drift, peak scratch bytes, number of forward steps run}. */
@@ -242,9 +246,11 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 #define GPE_ADJ_AUTO 0
 #define GPE_ADJ_RECONSTRUCT 1
 #define GPE_ADJ_CHECKPOINT 2
+#define GPE_CONTROL_X_LATTICE 0
+#define GPE_CONTROL_PUMP 1
 int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *target, int64_t nsteps,
-                double t0, const double *knots, int nknots, int loss_kind, int mode, double drift_tol,
-                double *loss, double *grad, gpe_c64 *const *psi_final, double *info);
+                double t0, const double *knots, int nknots, int control, int loss_kind, int mode,
+                double drift_tol, double *loss, double *grad, gpe_c64 *const *psi_final, double *info);
 
 #ifdef __cplusplus
 }

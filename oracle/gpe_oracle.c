@@ -563,7 +563,17 @@ int orc_set_threads(int n)
  * Forward states are kept as checkpoints every `ckpt` steps; each segment is
  * recomputed forward before it is swept backward, so the gradient is the exact
  * adjoint of this file's own forward map.
+ * The controlled lattice is the x lattice (axis 0) or the y lattice (axis 1), the
+ * pump of the cavity set-up (Sec. 5.3) run here with the cavity off; dV/dc_m is
+ * w_m(t) cos^2(k_lat u) along that axis.
  */
+
+/* cos^2 of the controlled lattice at grid point (i, j) */
+static double control_weight(const orc_problem *p, int axis, int i, int j)
+{
+    double c = axis == 0 ? cos(p->kx_lat * xcoord(p, i)) : cos(p->ky_lat * ycoord(p, j));
+    return c * c;
+}
 
 static void hat_weights(const orc_sched *s, double t, int *i0, double *w0, double *w1)
 {
@@ -581,7 +591,7 @@ static void hat_weights(const orc_sched *s, double t, int *i0, double *w0, doubl
 /* Backward through one kick at time t.  zout is the kick's output; on return z holds
  * its input (reconstructed exactly as zout e^{+i theta}, |z| = |zout|) and G the
  * gradient with respect to it.  Accumulates dL/dc into grad. */
-static void kick_adjoint(const orc_problem *p, const cplx *zout, cplx *z, cplx *G, double t, double h,
+static void kick_adjoint(const orc_problem *p, int axis, const cplx *zout, cplx *z, cplx *G, double t, double h,
                          double *grad)
 {
     double lat_sum = 0;
@@ -595,12 +605,12 @@ static void kick_adjoint(const orc_problem *p, const cplx *zout, cplx *z, cplx *
             double s = cimag(conj(G[q]) * zout[q]);
             G[q] = G[q] * e + 2.0 * p->g * h * s * zin;
             z[q] = zin;
-            double c = cos(p->kx_lat * xcoord(p, i));
-            lat_sum += h * s * c * c;
+            lat_sum += h * s * control_weight(p, axis, i, j);
         }
-    if (grad && p->sx.kind == 2) {
+    const orc_sched *ctl = axis == 0 ? &p->sx : &p->sy;
+    if (grad && ctl->kind == 2) {
         int i0; double w0, w1;
-        hat_weights(&p->sx, t, &i0, &w0, &w1);
+        hat_weights(ctl, t, &i0, &w0, &w1);
         grad[i0] += w0 * lat_sum;
         grad[i0 + 1] += w1 * lat_sum;
     }
@@ -621,10 +631,11 @@ static void kinetic_adjoint(const orc_problem *p, cplx *G)
     orc_fft2d(G, p->nx, p->ny, 1);
 }
 
-int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *target, int64_t nsteps,
-                int64_t ckpt, int loss_kind, double *loss, double *grad, cplx *psi_final)
+int orc_adjoint_axis(const orc_problem *p, int axis, double t0, const cplx *psi0, const cplx *target,
+                     int64_t nsteps, int64_t ckpt, int loss_kind, double *loss, double *grad, cplx *psi_final)
 {
-    if (p->cavity || p->sx.kind != 2 || nsteps < 1) return -1;
+    const orc_sched *ctl = axis == 0 ? &p->sx : &p->sy;
+    if (p->cavity || (axis != 0 && axis != 1) || ctl->kind != 2 || nsteps < 1) return -1;
     if (ckpt < 1) ckpt = 1;
     size_t npts = (size_t)p->nx * p->ny;
     double da = (p->lx / p->nx) * (p->ly / p->ny), h = 0.5 * p->dt;
@@ -649,7 +660,7 @@ int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *t
     if (psi_final) memcpy(psi_final, psi, sizeof(cplx) * npts);
 
     /* terminal gradient */
-    for (int m = 0; m < p->sx.nknots; m++) grad[m] = 0;
+    for (int m = 0; m < ctl->nknots; m++) grad[m] = 0;
     if (loss_kind == 0) {
         cplx c = 0;
         for (size_t q = 0; q < npts; q++) c += conj(target[q]) * psi[q];
@@ -676,11 +687,10 @@ int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *t
                 size_t q = (size_t)j * p->nx + i;
                 double dens = creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
                 G[q] = 2.0 * da * (G[q] + (potential(p, i, j, T, 0) + p->g * dens) * psi[q]);
-                double cx = cos(p->kx_lat * xcoord(p, i));
-                lat_sum += da * cx * cx * dens;
+                lat_sum += da * control_weight(p, axis, i, j) * dens;
             }
         int i0; double w0, w1;
-        hat_weights(&p->sx, T, &i0, &w0, &w1);
+        hat_weights(ctl, T, &i0, &w0, &w1);
         grad[i0] += w0 * lat_sum;
         grad[i0 + 1] += w1 * lat_sum;
     }
@@ -700,13 +710,13 @@ int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *t
             double tn = t0 + (n0 + k) * p->dt, tn1 = tn + p->dt;
             const cplx *zout = seg + (size_t)(k + 1) * npts;
             /* second kick at t_{n+1}: output psi_{n+1}, input psi* -> a */
-            kick_adjoint(p, zout, a, G, tn1, h, grad);
+            kick_adjoint(p, axis, zout, a, G, tn1, h, grad);
             /* kinetic: psi' = U^H psi* -> b */
             memcpy(b, a, sizeof(cplx) * npts);
             kinetic_adjoint(p, b);
             kinetic_adjoint(p, G);
             /* first kick at t_n: output psi', input psi_n */
-            kick_adjoint(p, b, a, G, tn, h, grad);
+            kick_adjoint(p, axis, b, a, G, tn, h, grad);
         }
     }
     free(ck); free(seg); free(psi); free(G); free(a); free(b);
@@ -799,4 +809,11 @@ int orc_momentum_orders(const orc_problem *p, const cplx *psik, int axis, int or
     for (int q = 0; q < 2 * nmax + 1; q++) out[q] = tot > 0 ? out[q] / tot : 0.0;
     out[2 * nmax + 1] = tot * (p->lx / p->nx) * (p->ly / p->ny) / ((double)p->nx * p->ny);
     return 0;
+}
+
+/* The x-lattice control (axis 0). */
+int orc_adjoint(const orc_problem *p, double t0, const cplx *psi0, const cplx *target, int64_t nsteps,
+                int64_t ckpt, int loss_kind, double *loss, double *grad, cplx *psi_final)
+{
+    return orc_adjoint_axis(p, 0, t0, psi0, target, nsteps, ckpt, loss_kind, loss, grad, psi_final);
 }

@@ -109,6 +109,7 @@ def lib():
         _lib.orc_dft2d.argtypes = [P, P, C.c_int, C.c_int, C.c_int]
         _lib.orc_potential_grid.argtypes = [P, D, D, D, P]
         _lib.orc_adjoint.argtypes = [P, D, P, P, I64, I64, C.c_int, P, P, P]
+        _lib.orc_adjoint_axis.argtypes = [P, C.c_int, D, P, P, I64, I64, C.c_int, P, P, P]
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_set_threads.restype = C.c_int
     return _lib
@@ -329,21 +330,24 @@ def dft2d(a, inverse: bool = False) -> np.ndarray:
     return out
 
 
-def adjoint(prob: Problem, t0: float, psi0, target, nsteps: int, ckpt: int = 0, loss: str = "fidelity"):
-    """Loss and its gradient w.r.t. the x-lattice knot values (discrete adjoint).
+def adjoint(prob: Problem, t0: float, psi0, target, nsteps: int, ckpt: int = 0, loss: str = "fidelity",
+            control: str = "x"):
+    """Loss and its gradient w.r.t. the knot values of the x-lattice (control "x") or the
+    y-lattice, i.e. pump (control "y"), depth schedule (discrete adjoint).
 
     Returns (loss, grad[M], psi_final)."""
     p, keep = prob.cstruct()
     a0, tg = _c128(psi0), _c128(target)
-    m = prob.sx.knots.size
+    axis = {"x": 0, "y": 1}[control]
+    m = (prob.sx if axis == 0 else prob.sy).knots.size
     grad = np.zeros(m)
     lossv = C.c_double(0)
     fin = np.zeros_like(a0)
     if ckpt <= 0:
         ckpt = max(1, int(round(np.sqrt(nsteps))))
-    rc = lib().orc_adjoint(C.byref(p), float(t0), a0.ctypes.data, tg.ctypes.data, int(nsteps), int(ckpt),
-                           {"fidelity": 0, "energy": 1}[loss], C.byref(lossv), grad.ctypes.data,
-                           fin.ctypes.data)
+    rc = lib().orc_adjoint_axis(C.byref(p), axis, float(t0), a0.ctypes.data, tg.ctypes.data, int(nsteps),
+                                int(ckpt), {"fidelity": 0, "energy": 1}[loss], C.byref(lossv), grad.ctypes.data,
+                                fin.ctypes.data)
     if rc != 0:
         raise ValueError("oracle adjoint: unsupported problem (cavity on or controls not knots)")
     return lossv.value, grad, fin

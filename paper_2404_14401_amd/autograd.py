@@ -13,15 +13,16 @@ from . import gpe
 
 
 class GPEControl(torch.autograd.Function):
-    """loss = GPEControl.apply(knots, batch, psi0s, targets, nsteps, t0, mode)
+    """loss = GPEControl.apply(knots, batch, psi0s, targets, nsteps, t0, mode, control)
 
-    knots: float64 tensor (n, M) of x-lattice depth values (host or device);
+    knots: float64 tensor (n, M) of lattice depth values (host or device) for the x
+    lattice (control "x") or the pump, y lattice (control "pump");
     psi0s, targets: lists of n complex64 CUDA tensors (ny, nx)."""
 
     @staticmethod
-    def forward(ctx, knots, batch, psi0s, targets, nsteps, t0=0.0, mode="auto"):
+    def forward(ctx, knots, batch, psi0s, targets, nsteps, t0=0.0, mode="auto", control="x"):
         k = knots.detach().to("cpu", torch.float64).numpy()
-        loss, grad, info = gpe.adjoint(batch, psi0s, targets, nsteps, k, t0=t0, mode=mode)
+        loss, grad, info = gpe.adjoint(batch, psi0s, targets, nsteps, k, t0=t0, mode=mode, control=control)
         ctx.save_for_backward(torch.from_numpy(grad).to(knots.device))
         ctx.info = info
         return torch.from_numpy(loss).to(knots.device)
@@ -29,11 +30,11 @@ class GPEControl(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gloss):
         (grad,) = ctx.saved_tensors
-        return gloss[:, None].to(grad.dtype) * grad, None, None, None, None, None, None
+        return gloss[:, None].to(grad.dtype) * grad, None, None, None, None, None, None, None
 
 
-def control_loss(knots, batch, psi0s, targets, nsteps, t0=0.0, mode="auto"):
-    return GPEControl.apply(knots, batch, psi0s, targets, nsteps, t0, mode)
+def control_loss(knots, batch, psi0s, targets, nsteps, t0=0.0, mode="auto", control="x"):
+    return GPEControl.apply(knots, batch, psi0s, targets, nsteps, t0, mode, control)
 
 
 __all__ = ["GPEControl", "control_loss", "np"]

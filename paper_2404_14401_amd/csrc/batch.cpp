@@ -604,9 +604,12 @@ static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
 }
 
 int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *target, int64_t nsteps, double t0,
-                const double *knots, int nknots, int loss_kind, int mode, double drift_tol, double *loss,
+                const double *knots, int nknots, int control, int loss_kind, int mode, double drift_tol, double *loss,
                 double *grad, gpe_c64 *const *psi_final, double *info)
 {
+    if (control != GPE_CONTROL_X_LATTICE && control != GPE_CONTROL_PUMP)
+        return fail(GPE_ERR_INVALID, "control must be GPE_CONTROL_X_LATTICE or GPE_CONTROL_PUMP");
+    const bool pump = control == GPE_CONTROL_PUMP;
     if (!b || !psi0 || !loss || !grad || nsteps < 1 || !knots)
         return fail(GPE_ERR_INVALID, "null argument or nsteps < 1");
     if (loss_kind != GPE_LOSS_FIDELITY) return fail(GPE_ERR_UNSUPPORTED, "only the fidelity loss runs on the GPU");
@@ -618,8 +621,9 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     for (int i = 0; i < nb; ++i) {
         gpe_plan *p = b->plans[i];
         if (p->nx != nx || p->ny != ny) return fail(GPE_ERR_INVALID, "adjoint members must share the grid size");
-        if (p->pot.sx.kind != GPE_SCHED_KNOTS || p->pot.sx.nknots != nknots)
-            return fail(GPE_ERR_INVALID, "members need an x-lattice knot schedule with nknots values");
+        const Sched &ctl = pump ? p->pot.sy : p->pot.sx;
+        if (ctl.kind != GPE_SCHED_KNOTS || ctl.nknots != nknots)
+            return fail(GPE_ERR_INVALID, "members need a knot schedule with nknots values on the controlled lattice");
         if (p->pot.cavity) return fail(GPE_ERR_UNSUPPORTED, "adjoint with the cavity on");
         if (!psi0[i] || !target[i]) return fail(GPE_ERR_INVALID, "null member state");
     }
@@ -641,16 +645,16 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     const size_t npts = (size_t)nx * ny;
     HIP_OK(hipEventRecord(b->ev_in, b->user));
     HIP_OK(hipStreamWaitEvent(b->work, b->ev_in, 0));
-    // controls: the members' x-lattice knot values
+    // controls: the members' knot values of the controlled lattice
     for (int i = 0; i < nb; ++i)
-        HIP_OK(hipMemcpyAsync(b->plans[i]->knots_x, knots + (size_t)i * nknots, sizeof(double) * nknots,
-                              hipMemcpyHostToDevice, b->work));
+        HIP_OK(hipMemcpyAsync(pump ? b->plans[i]->knots_y : b->plans[i]->knots_x, knots + (size_t)i * nknots,
+                              sizeof(double) * nknots, hipMemcpyHostToDevice, b->work));
     std::vector<InstDesc> fwd(nb);
     std::vector<AdjInst> adj(nb);
     for (int i = 0; i < nb; ++i) {
         gpe_plan *p = b->plans[i];
         fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st};
-        adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i]};
+        adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i], pump ? 1 : 0};
     }
     HIP_OK(hipMemcpyAsync(w->d_fwd, fwd.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice, b->work));
     HIP_OK(hipMemcpyAsync(w->d_adj, adj.data(), sizeof(AdjInst) * nb, hipMemcpyHostToDevice, b->work));
@@ -735,7 +739,7 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         HIP_OK(hipMemcpyAsync(kg.data(), w->kick_grad[i], sizeof(double) * kg.size(), hipMemcpyDeviceToHost, b->work));
         HIP_OK(hipStreamSynchronize(b->work));
         gpe_schedule s{};
-        const Sched &d = b->plans[i]->pot.sx;
+        const Sched &d = pump ? b->plans[i]->pot.sy : b->plans[i]->pot.sx;
         s.nknots = d.nknots;
         s.t0 = d.t0;
         s.t1 = d.t1;

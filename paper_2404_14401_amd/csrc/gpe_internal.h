@@ -144,6 +144,7 @@ struct AdjInst {
     DevState *st;
     double *partials;   // [row work-groups] per-row-block sums of the current kick
     double *kick_grad;  // [nsteps + 1] dL/dV0 at t0 + k dt
+    int control_axis;   // controlled lattice: 0 x, 1 y (the pump)
 };
 
 enum AdjRowMode : int {

@@ -203,7 +203,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                     part[1] += (double)tx.z * cy * d2;
                     part[2] += (double)tx.w * d2;
                     part[3] += yv * d2;
-                    part[4] += (double)tx.z * tx.z * d2;
+                    if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d2;
                 }
             } else {
                 // |psi| is the same before and after a phase kick
@@ -211,13 +211,17 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                 part[1] += (double)tx.z * cy * d;
                 part[2] += (double)tx.w * d;
                 part[3] += yv * d;
-                part[4] += (double)tx.z * tx.z * d;
+                if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d;
                 v[m] = kick_real(v[m], th);
             }
         }
     }
     if (partials) {
-        block_sum<NPART>(part, red);
+        // the C overlap is only needed by the adiabatic field: skip its shuffles otherwise
+        if (pot.cavity == 2)
+            block_sum<NPART>(part, red);
+        else
+            block_sum<NPART - 1>(*reinterpret_cast<double(*)[NPART - 1]>(part), red);
         if (threadIdx.x == 0)
 #pragma unroll
             for (int k = 0; k < NPART; ++k) partials[k] = part[k];
@@ -1018,6 +1022,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     const double tau = (MODE == ADJ_MID) ? gd.dt : 0.5 * gd.dt;
     const VLine vl = vline_cav(I.pot, row, tk, 0.0, 0.0);
     const float *vu = I.pot.vuser ? I.pot.vuser + (size_t)row * N : nullptr;
+    const double wy = I.control_axis ? (double)I.pot.ty[row].y : 0.0;  // cos^2(ky_lat y) of this row
     double part[1] = {0.0};
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -1033,7 +1038,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
         const double k2 = 2.0 * gd.g * tau * s;
         w[m] = {w[m].x * cs - w[m].y * sn + k2 * vin.x, w[m].x * sn + w[m].y * cs + k2 * vin.y};
         v[m] = vin;
-        part[0] += tau * s * (double)tx.y;  // d V / d V0 = cos^2(kx_lat x)
+        part[0] += tau * s * (I.control_axis ? wy : (double)tx.y);  // dV/dV0 = cos^2 of the controlled lattice
     }
     block_sum<1>(part, red);
     if (threadIdx.x == 0) I.partials[lb] = part[0];

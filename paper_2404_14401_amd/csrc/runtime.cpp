@@ -58,7 +58,8 @@ static int env_int(const char *name, int dflt)
 }
 
 // Launch shape: threads per line T = n / R.  Rows: lines per work-group so that a
-// work-group has about 256 threads.  Columns: tiles of W adjacent columns, W chosen
+// work-group has about 128 threads (one 1024-point line at radix 8; measured best at
+// 1024^2, where more work-groups spread the pass's latency over more CUs).  Columns: tiles of W adjacent columns, W chosen
 // so that there are at least 256 tiles (one per CU) when the grid allows it.
 Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles)
 {
@@ -86,11 +87,11 @@ Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_co
 
 static Shape make_shape(int nx, int ny)
 {
-    Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 256),
+    Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128),
                            env_int("GPE_MIN_COL_TILES", 256));
     const int w = env_int("GPE_COL_W", 0);
     if (w > 0 && w <= nx && (w & (w - 1)) == 0 && w * s.col_threads / s.col_cols <= 1024) {
-        Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 256), nx / w);
+        Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128), nx / w);
         s = t;
     }
     return s;

@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("GPE_LIB_PATH") or os.path.join(_HERE, "libgpe.so")
 OK = 0
 ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONFINITE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 NOBS = 6
+CONTROL = {"x": 0, "pump": 1}
 SCHED = {"const": 0, "ramp": 1, "knots": 2, "pulse": 3}
 LOSS = {"fidelity": 0, "energy": 1}
 ADJ_MODE = {"auto": 0, "reconstruct": 1, "checkpoint": 2}
@@ -99,7 +100,7 @@ def lib():
         L.gpe_batch_tune.argtypes = [P, C.c_char_p]
         L.gpe_batch_info.argtypes = [P, I, P]
         L.gpe_batch_get_cavity.argtypes = [P, I, P]
-        L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, D, P, P, P, P]
+        L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, I, D, P, P, P, P]
         for name in EXPORTS:
             if name != "gpe_last_error":
                 getattr(L, name).restype = C.c_int
@@ -306,9 +307,10 @@ class Batch:
 
 
 def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, mode: str = "auto",
-            drift_tol: float = 1e-4, psi_finals=None):
-    """Loss 1 - |<target|psi(T)>|^2 and its gradient w.r.t. the x-lattice knot values of
-    every batch member (discrete adjoint on the GPU).  knots: array (n, M).
+            drift_tol: float = 1e-4, psi_finals=None, control: str = "x"):
+    """Loss 1 - |<target|psi(T)>|^2 and its gradient w.r.t. the knot values of the
+    x-lattice (control "x") or pump, y-lattice (control "pump"), depth of every batch
+    member (discrete adjoint on the GPU).  knots: array (n, M).
     Returns (loss[n], grad[n, M], info dict)."""
     k = np.ascontiguousarray(knots, dtype=np.float64)
     n, m = k.shape
@@ -319,7 +321,7 @@ def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, m
     info = np.zeros(4)
     fin = batch._ptrs(psi_finals) if psi_finals is not None else None
     check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), batch._ptrs(targets), int(nsteps), float(t0),
-                            k.ctypes.data, m, LOSS["fidelity"], ADJ_MODE[mode], float(drift_tol),
+                            k.ctypes.data, m, CONTROL[control], LOSS["fidelity"], ADJ_MODE[mode], float(drift_tol),
                             loss.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
     return loss, grad, {"mode": {1: "reconstruct", 2: "checkpoint"}[int(info[0])], "drift": info[1],
                         "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}

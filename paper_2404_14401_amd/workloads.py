@@ -158,6 +158,14 @@ def cavity_1024(seed: int = 0) -> Setup:
 CAVITY_1024_STEPS = 20000
 
 
+def cavity_1024_adiabatic(seed: int = 0) -> Setup:
+    """The cavity run with the adiabatic field of Sec. 5.3 (Eqs. 17-18) in place of the
+    field ODE: N = eta / sqrt(Vp Vc), so that N sqrt(Vp Vc) is the ODE's coupling, and
+    the dispersive shift N Vc C that the ODE leaves out."""
+    s = cavity_1024(seed)
+    return s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+
+
 def cavity_scaled(n: int, seed: int = 0) -> Setup:
     """The cavity workload's physics on an n x n grid with the same spacing
     dx = 1/16 (box n/16), for parity at sizes the oracle finishes in seconds."""

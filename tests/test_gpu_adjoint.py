@@ -92,3 +92,37 @@ def test_auto_falls_back_to_checkpoints_when_drift_tolerance_is_zero():
     assert a[2]["mode"] == "checkpoint" and a[2]["forward_steps"] == 2 * nsteps
     r = gpe.adjoint(batch, [to_dev(p0)], [to_dev(tg)], nsteps, s.sx.knots[None, :], mode="reconstruct")
     assert np.linalg.norm(a[1] - r[1]) / np.linalg.norm(r[1]) < 1e-4
+
+
+def pump_setup(b, n=64, nknots=8, nsteps=60, dt=0.005):
+    """The pump (y lattice) as the control, with a static x lattice present."""
+    knots = np.random.Generator(np.random.PCG64(200 + b)).uniform(0.0, 15.0, size=nknots)
+    return W.Setup(nx=n, ny=n, lx=16.0, ly=16.0, dt=dt, g=300.0, kx_lat=1.5, ky_lat=2.0,
+                   sx=W.Schedule("const", 3.0), sy=W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots))
+
+
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+def test_pump_control_adjoint_matches_oracle_and_autograd(mode):
+    torch = torch_cuda()
+    from paper_2404_14401_amd import autograd as A
+    from paper_2404_14401_amd import gpe
+
+    nsteps, nb = 60, 2
+    setups = [pump_setup(b, nsteps=nsteps) for b in range(nb)]
+    batch = gpe.Batch(setups)
+    p0, tg = zip(*[states(s, b) for b, s in enumerate(setups)])
+    d0, dtg = [to_dev(p) for p in p0], [to_dev(t) for t in tg]
+    knots = np.stack([s.sy.knots for s in setups])
+    loss, grad, info = gpe.adjoint(batch, d0, dtg, nsteps, knots, mode=mode, control="pump")
+    assert info["mode"] == mode
+    for b, s in enumerate(setups):
+        l_ref, g_ref, _ = O.adjoint(problem(s), 0.0, p0[b], tg[b], nsteps, control="y")
+        assert abs(loss[b] - l_ref) < 1e-5
+        assert np.linalg.norm(grad[b] - g_ref) / np.linalg.norm(g_ref) < 1e-3
+    kt = torch.tensor(knots, dtype=torch.float64, requires_grad=True)
+    A.control_loss(kt, batch, d0, dtg, nsteps, mode=mode, control="pump").sum().backward()
+    assert np.abs(kt.grad.numpy() - grad).max() <= 1e-12 * np.abs(grad).max()
+    # the x lattice has no knots here: asking for it is an argument error
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.adjoint(batch, d0, dtg, nsteps, knots)
+    assert e.value.code == gpe.ERR_INVALID

@@ -378,6 +378,34 @@ def test_adjoint_matches_central_differences(loss):
     assert np.abs(grad - fd).max() / np.abs(fd).max() < 1e-6
 
 
+@pytest.mark.parametrize("loss", ["fidelity", "energy"])
+def test_pump_control_adjoint_matches_central_differences_and_transposition(loss):
+    """Control of the y (pump) lattice depth with a static x lattice present: central
+    differences, and the x-control gradient of the transposed problem (axes swapped,
+    states transposed) equals it."""
+    nsteps = 30
+    knots = np.random.Generator(np.random.PCG64(8)).uniform(0.0, 6.0, size=5)
+    s = W.Setup(nx=32, ny=16, lx=12.0, ly=8.0, dt=0.01, g=20.0, kx_lat=1.2, ky_lat=1.7,
+                sx=W.Schedule("const", 2.0), sy=W.Schedule("knots", t0=0.0, t1=nsteps * 0.01, knots=knots))
+    psi0 = W.gaussian(s, 1.0, 0.3, 0.1)
+    target = W.gaussian(s, 0.9, -0.2, 0.2)
+    val, grad, _ = O.adjoint(problem(s), 0.0, psi0, target, nsteps, 0, loss, control="y")
+    h = 1e-4
+    fd = np.zeros_like(grad)
+    for m in range(grad.size):
+        for sgn in (1, -1):
+            k2 = knots.copy()
+            k2[m] += sgn * h
+            s2 = s.with_(sy=W.Schedule("knots", t0=0.0, t1=s.sy.t1, knots=k2))
+            v2, _, _ = O.adjoint(problem(s2), 0.0, psi0, target, nsteps, 0, loss, control="y")
+            fd[m] += sgn * v2 / (2 * h)
+    assert np.abs(grad - fd).max() / np.abs(fd).max() < 1e-6
+    st = W.Setup(nx=16, ny=32, lx=8.0, ly=12.0, dt=0.01, g=20.0, kx_lat=1.7, ky_lat=1.2,
+                 sx=s.sy, sy=W.Schedule("const", 2.0))
+    vt, gt, _ = O.adjoint(problem(st), 0.0, psi0.T, target.T, nsteps, 0, loss, control="x")
+    assert abs(vt - val) < 1e-12 and np.abs(gt - grad).max() < 1e-10 * np.abs(grad).max()
+
+
 def test_adjoint_is_independent_of_checkpoint_spacing_and_returns_forward_state():
     nsteps = 30
     s = _control_problem(nsteps)
