@@ -73,3 +73,36 @@ def test_checkpoint_resume_of_cavity_state_is_bitwise():
     b.step_real(saved_psi, 40, 40 * s.dt)
     assert (da == saved_psi).all()
     assert b.cavity()["alpha"] == a.cavity()["alpha"]
+
+
+def test_widened_entry_points_validate_arguments():
+    """Argument errors of the Fourier-space stepping, the momentum orders, the cavity
+    and probe settings and the adjoint control: reported before anything launches."""
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.imag_ground_64(0.0)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(W.gaussian(s, 1.0))
+    for call in (lambda: plan.step_real_k(d, -1, 0.0), lambda: plan.step_real_k(d, 1, float("nan")),
+                 lambda: plan.momentum_orders(d, 2, 8, 1), lambda: plan.momentum_orders(d, 0, 0, 1),
+                 lambda: plan.momentum_orders(d, 1, 8, 4), lambda: plan.momentum_orders(d, 0, 8, -1)):
+        with pytest.raises(gpe.GpeError) as e:
+            call()
+        assert e.value.code == gpe.ERR_INVALID
+    pops, nrm = plan.momentum_orders(d, 0, 8, 3)   # (2*3+1)*8 = 56 <= 64 bins: valid
+    assert pops.shape == (7,) and nrm > 0
+    adia = W.self_organisation_128(5.0, -10.0).with_(nx=64, ny=64, lx=8.0, ly=8.0)
+    for bad in (adia.with_(vc=0.01),                                  # pump < 0, U0 > 0
+                adia.with_(n_atoms=-1.0),
+                adia.with_(cavity_mode="ode", probe_omega=1.0),        # probe needs the adiabatic field
+                adia.with_(probe_detuning=float("inf"))):
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.Plan.from_setup(bad)
+        assert e.value.code == gpe.ERR_INVALID
+    knots = np.linspace(0.0, 1.0, 4)
+    ctl = s.with_(kx_lat=1.0, sx=W.Schedule("knots", t0=0.0, t1=0.1, knots=knots))
+    b = gpe.Batch([ctl])
+    with pytest.raises(gpe.GpeError) as e:   # the y lattice has no knots
+        gpe.adjoint(b, [d], [d], 10, knots[None, :], control="pump")
+    assert e.value.code == gpe.ERR_INVALID

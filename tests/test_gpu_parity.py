@@ -47,6 +47,39 @@ def test_free_flow_single_steps_match_spectral_propagation(path, shape, monkeypa
     assert rel_l2(to_host(d), ref) < 2e-6
 
 
+@pytest.mark.parametrize("shape", [(4096, 16), (16, 4096), (2048, 64)])
+def test_free_flow_extreme_aspect_ratios(shape, monkeypatch):
+    """The largest line lengths the plan takes (4096) in either pass, against the
+    oracle's spectral propagation."""
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=nx * 0.05, ly=ny * 0.15, dt=0.01, g=0.0, wx=0.0, wy=0.0)
+    psi0 = W.to_c64(W.gaussian(s, 0.8, 0.3, -0.2) * np.exp(1j * 0.7 * s.xs()[None, :]))
+    ref, _ = O.step_real(problem(s), state(s), psi0, 3)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    plan.step_real(d, 3, 0.0)
+    assert rel_l2(to_host(d), ref) < 2e-6
+
+
+def test_largest_grid_steps_with_every_potential_term(monkeypatch):
+    """4096^2, the plan's largest grid: two real steps and one imaginary step with the
+    trap, both lattices, g and the cavity field ODE, against the oracle."""
+    s = W.Setup(nx=4096, ny=4096, lx=64.0, ly=64.0, dt=0.002, g=200.0, wx=0.1, wy=0.12, x0=0.5,
+                kx_lat=1.1, ky_lat=0.9, sx=W.Schedule("ramp", 0.0, 4.0, 0.0, 0.01), sy=W.Schedule("const", 1.0),
+                cavity=True, vc=1.0, kc=0.9, delta_c=-5.0, kappa=2.0, eta=2.0, alpha0=0.1 + 0.05j)
+    psi0 = W.to_c64(W.gaussian(s, 6.0, 0.5, -0.3) * np.exp(1j * 0.2 * s.ys()[:, None]))
+    for mode, n in (("real", 2), ("imag", 1)):
+        st = state(s)
+        fn = O.step_real if mode == "real" else O.step_imag
+        ref, _ = fn(problem(s), st, psi0, n)
+        plan = make_plan(s, "multipass", monkeypatch)
+        d = to_dev(psi0)
+        (plan.step_real if mode == "real" else plan.step_imag)(d, n, 0.0)
+        assert rel_l2(to_host(d), ref) < 2e-6, mode
+        if mode == "real":
+            assert abs(plan.cavity()["alpha"] - st.alpha) < 1e-7
+
+
 @pytest.mark.parametrize("path", ["lds", "multipass"])
 def test_one_step_with_every_potential_term(path, monkeypatch):
     """Trap (displaced, anisotropic), both lattices (ramp and const), cavity terms
