@@ -149,6 +149,13 @@ int gpe_step_real(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t0, doubl
  * The cavity must be off (GPE_ERR_UNSUPPORTED otherwise). */
 int gpe_step_real_k(gpe_plan *plan, gpe_c64 *psik, int64_t nsteps, double t0, double *obs);
 
+/* nsteps imaginary-time steps (Sec. 3.3) in the same Fourier-space ordering, potential
+ * frozen at time t: psi_k <- e^{-T/2} F[e^{-V} F^{-1}[e^{-T/2} psi_k]], then psi_k is
+ * renormalised to unit norm (the norm by Parseval, sum |psi_k|^2 dx dy / (nx ny)).
+ * obs (nullable): per step the norm before renormalisation in [0] (the other fields
+ * are zero).  The cavity must be off (GPE_ERR_UNSUPPORTED otherwise). */
+int gpe_step_imag_k(gpe_plan *plan, gpe_c64 *psik, int64_t nsteps, double t, double *obs);
+
 /* nsteps imaginary-time steps (Sec. 3.3) with the potential frozen at time t; the ODE
  * cavity field is held fixed, the adiabatic one follows the state (its value for the
  * returned state is left in the plan); psi ends with unit norm.  obs as for

@@ -51,6 +51,7 @@ struct GridDev {
     // kinetic half steps of the Fourier-space ordering: e^{-i kx^2 dt/4}, and
     // e^{-i ky^2 dt/4} with (entry) and without (exit) the 1/(nx ny) of the round trip
     const double2 *kh_x, *kh_yin, *kh_yout;
+    const double *khi_x, *khi_yin, *khi_yout;  // the same in imaginary time: e^{-k^2 dt/4}
 };
 
 // Per-work-group partials: norm, Theta, x moment, y moment, C = cos^2(kc x) overlap.
@@ -74,6 +75,8 @@ enum ColMode : int {
     COL_EKIN = 2,      // FFT_y -> partials of sum k^2/2 |psi_k|^2 (no store)
     COL_KHALF_INV = 3, // (Fourier-space state) kinetic half step -> IFFT_y
     COL_FWD_KHALF = 4, // FFT_y -> kinetic half step (Fourier-space state out)
+    COL_KHALF_INV_IM = 5,  // imaginary time: pending scale and kinetic half step -> IFFT_y
+    COL_FWD_KHALF_IM = 6,  // imaginary time: FFT_y -> kinetic half step, partials of sum |psi_k|^2
 };
 
 struct RowArgs {

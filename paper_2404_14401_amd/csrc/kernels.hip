@@ -257,7 +257,8 @@ __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
 // ------------------------------------------------------------------ column pass
 template <int N, int R, int MODE>
 __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 *dst, const GridDev &gd,
-                                         double *partials, int tile, int w, XchgT *smem, double *red)
+                                         double *partials, int tile, int w, XchgT *smem, double *red,
+                                         double scale = 1.0)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -289,11 +290,21 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
 #if GPE_TW_LDS
     __syncthreads();
 #endif
-    if constexpr (MODE == COL_KHALF_INV) {
-        // Fourier-space state: kinetic half step, then back to real space along y
-        const C kx = gd.kh_x[col];
+    if constexpr (MODE == COL_KHALF_INV || MODE == COL_KHALF_INV_IM) {
+        // Fourier-space state: kinetic half step (imaginary time: with the pending
+        // renormalisation), then back to real space along y
+        if constexpr (MODE == COL_KHALF_INV) {
+            const C kx = gd.kh_x[col];
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kh_yin[t + m * T]));
+            for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kh_yin[t + m * T]));
+        } else {
+            const double kx = gd.khi_x[col] * scale;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const double f = kx * gd.khi_yin[t + m * T];
+                v[m] = {v[m].x * f, v[m].y * f};
+            }
+        }
         fft_line<N, R, true>(v, lds, t, twy);
 #pragma unroll
         for (int m = 0; m < R; ++m) store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
@@ -307,6 +318,24 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
             v[m] = cmul(v[m], cmul(kx, gd.kh_yout[t + m * T]));
             store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
         }
+        return;
+    }
+    if constexpr (MODE == COL_FWD_KHALF_IM) {
+        // kinetic half step, then the norm by Parseval: sum |psi_k|^2 / (nx ny) per work-group
+        const double kx = gd.khi_x[col];
+        double part[NPART] = {};
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const double f = kx * gd.khi_yout[t + m * T];
+            v[m] = {v[m].x * f, v[m].y * f};
+            part[0] += v[m].x * v[m].x + v[m].y * v[m].y;
+            store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
+        }
+        part[0] *= 1.0 / ((double)gd.nx * gd.ny);
+        block_sum<1>(*reinterpret_cast<double(*)[1]>(part), red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) partials[k] = part[k];
         return;
     }
     if constexpr (MODE == COL_EKIN) {
@@ -356,8 +385,9 @@ __global__ void __launch_bounds__(1024) col_pass(ColArgs a)
     extern __shared__ XchgT smem[];
     __shared__ double red[16 * NPART];
     if (a.do_tail && blockIdx.x == 0) run_tail(a.tail, a.grid, a.pot, a.st, red);
+    const double sc = MODE == COL_KHALF_INV_IM ? a.st->scale : 1.0;
     col_body<N, kRadix, MODE>(a.src, a.dst, a.grid, a.partials + blockIdx.x * NPART, xcd_tile(a.xcd_swizzle),
-                              a.cols_per_wg, smem, red);
+                              a.cols_per_wg, smem, red, sc);
 }
 
 template <int N, int R>
@@ -697,6 +727,7 @@ template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowAr
     if (imag) {
         if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, true);
         else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, true);
+        else if (mode == ROW_MID) GPE_ROW(ROW_MID, true);
         else return hipErrorInvalidValue;
     } else {
         if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, false);
@@ -750,6 +781,8 @@ template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int 
     else if (mode == COL_EKIN) GPE_COL(COL_EKIN);
     else if (mode == COL_KHALF_INV) GPE_COL(COL_KHALF_INV);
     else if (mode == COL_FWD_KHALF) GPE_COL(COL_FWD_KHALF);
+    else if (mode == COL_KHALF_INV_IM) GPE_COL(COL_KHALF_INV_IM);
+    else if (mode == COL_FWD_KHALF_IM) GPE_COL(COL_FWD_KHALF_IM);
     else return hipErrorInvalidValue;
 #undef GPE_COL
     return hipGetLastError();

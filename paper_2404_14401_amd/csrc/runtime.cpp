@@ -243,13 +243,14 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     if ((rc = dalloc(p, (void **)&p->tx, sizeof(float4) * nx))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->ty, sizeof(float4) * ny))) return cleanup(rc);
     std::vector<double2> kx(nx), ky(ny), twx(nx), twy(ny), khx(nx), khyi(ny), khyo(ny);
-    std::vector<double> kmx(nx), kmy(ny);
+    std::vector<double> kmx(nx), kmy(ny), khix(nx), khiyi(ny), khiyo(ny);
     const double inv = 1.0 / ((double)nx * ny);
     for (int i = 0; i < nx; ++i) {
         const double k = kval(i, nx, d->lx), ph = 0.5 * k * k * d->dt;
         kx[i] = make_double2(std::cos(ph), -std::sin(ph));
         khx[i] = make_double2(std::cos(0.5 * ph), -std::sin(0.5 * ph));
         kmx[i] = std::exp(-ph);
+        khix[i] = std::exp(-0.5 * ph);
         const double a = -2.0 * M_PI * i / nx;
         twx[i] = make_double2(std::cos(a), std::sin(a));
     }
@@ -259,12 +260,15 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
         khyi[j] = make_double2(std::cos(0.5 * ph) * inv, -std::sin(0.5 * ph) * inv);
         khyo[j] = make_double2(std::cos(0.5 * ph), -std::sin(0.5 * ph));
         kmy[j] = std::exp(-ph) * inv;
+        khiyi[j] = std::exp(-0.5 * ph) * inv;
+        khiyo[j] = std::exp(-0.5 * ph);
         const double a = -2.0 * M_PI * j / ny;
         twy[j] = make_double2(std::cos(a), std::sin(a));
     }
     if ((rc = upload(p, &p->kin_x, kx)) || (rc = upload(p, &p->kin_y, ky)) || (rc = upload(p, &p->kim_x, kmx)) ||
         (rc = upload(p, &p->kim_y, kmy)) || (rc = upload(p, &p->tw_x, twx)) || (rc = upload(p, &p->tw_y, twy)) ||
-        (rc = upload(p, &p->kh_x, khx)) || (rc = upload(p, &p->kh_yin, khyi)) || (rc = upload(p, &p->kh_yout, khyo)))
+        (rc = upload(p, &p->kh_x, khx)) || (rc = upload(p, &p->kh_yin, khyi)) || (rc = upload(p, &p->kh_yout, khyo)) ||
+        (rc = upload(p, &p->khi_x, khix)) || (rc = upload(p, &p->khi_yin, khiyi)) || (rc = upload(p, &p->khi_yout, khiyo)))
         return cleanup(rc);
     p->npart_max = std::max(std::max(p->shape.row_blocks, p->shape.col_blocks), 256);
     if ((rc = dalloc(p, (void **)&p->partials, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
@@ -292,6 +296,9 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     gd.kh_x = p->kh_x;
     gd.kh_yin = p->kh_yin;
     gd.kh_yout = p->kh_yout;
+    gd.khi_x = p->khi_x;
+    gd.khi_yin = p->khi_yin;
+    gd.khi_yout = p->khi_yout;
     gpe_potential_desc pot{};
     pot.wx = pot.wy = 1.0;
     if ((rc = gpe_set_potential(p, &pot))) return cleanup(rc);
@@ -490,6 +497,35 @@ int gpe_step_real_k(gpe_plan *p, gpe_c64 *psik, int64_t nsteps, double t0, doubl
         LAUNCH_OK(launch_col(p->ny, n + 1 < nsteps ? COL_KIN_REAL : COL_FWD_KHALF, cb, sh.col_blocks, sh.col_threads,
                              sh.col_shmem, p->stream));
     }
+    return GPE_OK;
+}
+
+int gpe_step_imag_k(gpe_plan *p, gpe_c64 *psik, int64_t nsteps, double t, double *obs)
+{
+    if (!p || !psik || nsteps < 0) return fail(GPE_ERR_INVALID, "null plan/psi or negative nsteps");
+    if (!std::isfinite(t)) return fail(GPE_ERR_INVALID, "t must be finite");
+    if (p->pot.cavity) return fail(GPE_ERR_UNSUPPORTED, "the Fourier-space ordering runs without the cavity");
+    if (nsteps == 0) return GPE_OK;
+    const Shape &sh = p->shape;
+    float2 *f = (float2 *)psik;
+    LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
+    RowArgs ra = row_args(p, f);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        ColArgs ca = col_args(p, f);
+        ca.do_tail = 0;
+        LAUNCH_OK(launch_col(p->ny, COL_KHALF_INV_IM, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        ra.n = (int)n;
+        LAUNCH_OK(launch_row(p->nx, ROW_MID, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        LAUNCH_OK(launch_col(p->ny, COL_FWD_KHALF_IM, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        TailArgs ta{};
+        ta.partials = p->partials2;
+        ta.npartials = sh.col_blocks;
+        ta.imag = 1;
+        ta.obs = obs ? obs + n * NOBS : nullptr;
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+    }
+    LAUNCH_OK(launch_scale(f, (size_t)p->nx * p->ny, p->st, p->stream));
+    LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
     return GPE_OK;
 }
 

@@ -83,6 +83,7 @@ struct gpe_plan {
     float4 *tx = nullptr, *ty = nullptr;
     double2 *kin_x = nullptr, *kin_y = nullptr, *tw_x = nullptr, *tw_y = nullptr;
     double2 *kh_x = nullptr, *kh_yin = nullptr, *kh_yout = nullptr;
+    double *khi_x = nullptr, *khi_yin = nullptr, *khi_yout = nullptr;
     double *kim_x = nullptr, *kim_y = nullptr;
     double *partials = nullptr, *partials2 = nullptr, *hpart = nullptr;
     double *probe = nullptr;  // partials of the density about to be kicked (adiabatic field)

@@ -29,7 +29,7 @@ ADJ_MODE = {"auto": 0, "reconstruct": 1, "checkpoint": 2}
 # Every entry point the header declares (checked by the CPU tests against include/gpe.h).
 EXPORTS = (
     "gpe_plan_create", "gpe_plan_destroy", "gpe_set_potential", "gpe_step_real", "gpe_step_real_k",
-    "gpe_step_imag", "gpe_momentum_orders",
+    "gpe_step_imag", "gpe_step_imag_k", "gpe_momentum_orders",
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
     "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
@@ -85,6 +85,7 @@ def lib():
         L.gpe_step_real.argtypes = [P, P, I64, D, P]
         L.gpe_step_imag.argtypes = [P, P, I64, D, P]
         L.gpe_step_real_k.argtypes = [P, P, I64, D, P]
+        L.gpe_step_imag_k.argtypes = [P, P, I64, D, P]
         L.gpe_momentum_orders.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P]
         L.gpe_energy.argtypes = [P, P, D, P]
         L.gpe_norm.argtypes = [P, P, P]
@@ -201,6 +202,11 @@ class Plan:
     def step_real_k(self, psik, nsteps: int, t0: float = 0.0, obs=None):
         """Real-time steps in the T/2-V-T/2 ordering on the Fourier-space state FFT2(psi)."""
         check(lib().gpe_step_real_k(self._h, _ptr(psik), int(nsteps), float(t0),
+                                    _ptr(obs, "float64") if obs is not None else None))
+
+    def step_imag_k(self, psik, nsteps: int, t: float = 0.0, obs=None):
+        """Imaginary-time steps in the T/2-V-T/2 ordering on the Fourier-space state; unit norm after each."""
+        check(lib().gpe_step_imag_k(self._h, _ptr(psik), int(nsteps), float(t),
                                     _ptr(obs, "float64") if obs is not None else None))
 
     def momentum_orders(self, psik, axis: int, order_step: int, nmax: int):

@@ -148,3 +148,53 @@ def test_pulse_schedule_in_both_orderings(path, monkeypatch):
     d = to_dev(psik0)
     plan2.step_real_k(d, 100, 0.0)
     assert rel_l2(to_host(d), ref) < 1e-5
+
+
+# ------------------------------------------------ imaginary time, Fourier-space state
+
+@pytest.mark.parametrize("shape", [(64, 32), (256, 128)])
+def test_kspace_imaginary_steps_with_every_potential_term(shape):
+    torch = torch_cuda()
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=12.0 * nx / 64, ly=12.0 * ny / 64, dt=0.02, g=30.0, wx=1.1, wy=0.8,
+                x0=0.3, y0=-0.2, kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("ramp", 1.0, 3.0, 0.0, 0.1),
+                sy=W.Schedule("const", 2.0))
+    psik0 = W.to_c64(O.fft2d(W.random_state(s, 4)))
+    ref, robs = O.step_imag_k(problem(s), state(s, 0.05), psik0, 3, want_obs=True)
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    obs = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+    plan.step_imag_k(d, 3, 0.05, obs)
+    assert rel_l2(to_host(d), ref) < 2e-6
+    assert np.abs(obs.cpu().numpy()[:, 0] - robs).max() < 1e-6 * np.abs(robs).max()
+
+
+def test_kspace_imaginary_fixed_point_is_the_printed_orderings_gaussian():
+    """Harmonic trap, g = 0: the Fourier-space ordering's imaginary-time fixed point is
+    exp(-a r^2 / 2) with a = 1/sqrt(1 + dtau^2/4) (the value the oracle is pinned to)."""
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=0.1, g=0.0)
+    plan = plan_for(s)
+    d = to_dev(O.fft2d(W.gaussian(s, 1.3, 0.2, -0.1)))
+    plan.step_imag_k(d, 400, 0.0)
+    out = O.fft2d(to_host(d), inverse=True)
+    a = 1.0 / np.sqrt(1 + s.dt**2 / 4)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    want = W.normalise(s, np.exp(-a * (x**2 + y**2) / 2).astype(complex))
+    assert rel_l2(out * np.exp(-1j * np.angle(np.vdot(want, out))), want) < 1e-5
+
+
+def test_kspace_imaginary_ground_state_64():
+    """64^2 interacting ground state from a noisy start, 2000 steps: psi_k and the energy
+    against the oracle's Fourier-space imaginary time."""
+    s = W.imag_ground_64(100.0)
+    psik0 = W.to_c64(O.fft2d(W.noisy_gaussian(s, 0)))
+    n = W.IMAG_64_STEPS
+    ref, _ = O.step_imag_k(problem(s), state(s), psik0, n)
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    plan.step_imag_k(d, n, 0.0)
+    out = to_host(d)
+    assert rel_l2(out, ref) < 1e-4
+    e_g = O.energy(problem(s), O.fft2d(out, inverse=True))["e"]
+    e_r = O.energy(problem(s), O.fft2d(ref, inverse=True))["e"]
+    assert abs(e_g - e_r) / abs(e_r) < 1e-5
