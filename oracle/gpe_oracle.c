@@ -564,8 +564,9 @@ int orc_set_threads(int n)
  * recomputed forward before it is swept backward, so the gradient is the exact
  * adjoint of this file's own forward map.
  * The controlled lattice is the x lattice (axis 0) or the y lattice (axis 1), the
- * pump of the cavity set-up (Sec. 5.3) run here with the cavity off; dV/dc_m is
- * w_m(t) cos^2(k_lat u) along that axis.
+ * pump of the cavity set-up (Sec. 5.3); dV/dc_m is w_m(t) cos^2(k_lat u) along that
+ * axis, plus, with the adiabatic cavity field, the pump's share in the interference
+ * lattice and in alpha (see kick_adjoint_cavity; fidelity loss only there).
  */
 
 /* cos^2 of the controlled lattice at grid point (i, j) */
@@ -591,9 +592,74 @@ static void hat_weights(const orc_sched *s, double t, int *i0, double *w0, doubl
 /* Backward through one kick at time t.  zout is the kick's output; on return z holds
  * its input (reconstructed exactly as zout e^{+i theta}, |z| = |zout|) and G the
  * gradient with respect to it.  Accumulates dL/dc into grad. */
+/* Backward through one kick with the adiabatic cavity field (cavity 2).  The field
+ * alpha(rho, t) of Eqs. 17-18 depends on the density through Theta^ = Theta/Nrm and
+ * C^ = C/Nrm, so besides the local terms the kick has a global one:
+ *   A = sum_x s dV/dalpha = 2 U0 alpha S_c + 2 sqrt(Vp U0) S_x    (S_c = sum s cos^2 kx,
+ *       S_x = sum s cos kx cos ky, s = Im(conj(G') psi')),
+ *   b_T = Re(conj(A) dalpha/dTheta^), b_C = Re(conj(A) dalpha/dC^),
+ *   dalpha/dTheta^ = N sqrt(Vp U0)/(D~ + i kappa), dalpha/dC^ = alpha N U0/(D~ + i kappa),
+ *   G = G' e^{i theta} + 2 w psi,
+ *   w = h [g s + (b_T (cos kx cos ky - Theta^) + b_C (cos^2 kx - C^)) dA / Nrm].
+ * Control: the x lattice enters only through h sum s cos^2(kx_lat x); the pump through
+ *   h [sum s cos^2(ky_lat y) + (U0/sqrt(Vp U0)) Re(alpha) S_x + Re(conj(A) dalpha/dVp)],
+ *   dalpha/dVp = N U0 Theta^ / (2 sqrt(Vp U0) (D~ + i kappa))  (finite for Vp U0 > 0). */
+static void kick_adjoint_cavity(const orc_problem *p, int axis, const cplx *zout, cplx *z, cplx *G, double t,
+                                double h, double *grad)
+{
+    double da = (p->lx / p->nx) * (p->ly / p->ny);
+    double nrm = orc_norm(p, zout);
+    double thn = orc_theta(p, zout) / nrm, c2n = orc_cos2(p, zout) / nrm;
+    cplx alpha = alpha_adiabatic(p, zout, t);
+    double vp = sched_eval(&p->sy, t), sq = sqrt(vp * p->vc);
+    cplx dplus = (p->delta_c - p->n_atoms * p->vc * c2n) + I * p->kappa;
+    double s_c = 0, s_x = 0, s_ctl = 0;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double s = cimag(conj(G[q]) * zout[q]);
+            double cx = cos(p->kc * xcoord(p, i)), cy = cos(p->kc * ycoord(p, j));
+            s_c += s * cx * cx;
+            s_x += s * cx * cy;
+            s_ctl += s * control_weight(p, axis, i, j);
+        }
+    cplx A = 2.0 * p->vc * alpha * s_c + 2.0 * sq * s_x;
+    cplx a_th = p->n_atoms * sq / dplus, a_c = alpha * p->n_atoms * p->vc / dplus;
+    double b_th = creal(conj(A) * a_th), b_c = creal(conj(A) * a_c);
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t q = (size_t)j * p->nx + i;
+            double dens = creal(zout[q]) * creal(zout[q]) + cimag(zout[q]) * cimag(zout[q]);
+            double th = (potential(p, i, j, t, alpha) + p->g * dens) * h;
+            cplx e = cos(th) + I * sin(th);
+            cplx zin = zout[q] * e;
+            double s = cimag(conj(G[q]) * zout[q]);
+            double cx = cos(p->kc * xcoord(p, i)), cy = cos(p->kc * ycoord(p, j));
+            double w = h * (p->g * s + (b_th * (cx * cy - thn) + b_c * (cx * cx - c2n)) * da / nrm);
+            G[q] = G[q] * e + 2.0 * w * zin;
+            z[q] = zin;
+        }
+    double lat_sum = h * s_ctl;
+    if (axis == 1) {
+        cplx a_v = p->n_atoms * p->vc * thn / (2.0 * sq * dplus);
+        lat_sum += h * ((p->vc / sq) * creal(alpha) * s_x + creal(conj(A) * a_v));
+    }
+    const orc_sched *ctl = axis == 0 ? &p->sx : &p->sy;
+    if (grad && ctl->kind == 2) {
+        int i0; double w0, w1;
+        hat_weights(ctl, t, &i0, &w0, &w1);
+        grad[i0] += w0 * lat_sum;
+        grad[i0 + 1] += w1 * lat_sum;
+    }
+}
+
 static void kick_adjoint(const orc_problem *p, int axis, const cplx *zout, cplx *z, cplx *G, double t, double h,
                          double *grad)
 {
+    if (p->cavity == 2) {
+        kick_adjoint_cavity(p, axis, zout, z, G, t, h, grad);
+        return;
+    }
     double lat_sum = 0;
     for (int j = 0; j < p->ny; j++)
         for (int i = 0; i < p->nx; i++) {
@@ -635,7 +701,9 @@ int orc_adjoint_axis(const orc_problem *p, int axis, double t0, const cplx *psi0
                      int64_t nsteps, int64_t ckpt, int loss_kind, double *loss, double *grad, cplx *psi_final)
 {
     const orc_sched *ctl = axis == 0 ? &p->sx : &p->sy;
-    if (p->cavity || (axis != 0 && axis != 1) || ctl->kind != 2 || nsteps < 1) return -1;
+    if ((axis != 0 && axis != 1) || ctl->kind != 2 || nsteps < 1) return -1;
+    /* the cavity: only the adiabatic field, with the fidelity loss */
+    if (p->cavity == 1 || (p->cavity == 2 && loss_kind != 0)) return -1;
     if (ckpt < 1) ckpt = 1;
     size_t npts = (size_t)p->nx * p->ny;
     double da = (p->lx / p->nx) * (p->ly / p->ny), h = 0.5 * p->dt;

@@ -333,7 +333,8 @@ def dft2d(a, inverse: bool = False) -> np.ndarray:
 def adjoint(prob: Problem, t0: float, psi0, target, nsteps: int, ckpt: int = 0, loss: str = "fidelity",
             control: str = "x"):
     """Loss and its gradient w.r.t. the knot values of the x-lattice (control "x") or the
-    y-lattice, i.e. pump (control "y"), depth schedule (discrete adjoint).
+    y-lattice, i.e. pump (control "y"), depth schedule (discrete adjoint); cavity off, or
+    the adiabatic field with the fidelity loss.
 
     Returns (loss, grad[M], psi_final)."""
     p, keep = prob.cstruct()

@@ -406,6 +406,40 @@ def test_pump_control_adjoint_matches_central_differences_and_transposition(loss
     assert abs(vt - val) < 1e-12 and np.abs(gt - grad).max() < 1e-10 * np.abs(grad).max()
 
 
+@pytest.mark.parametrize("control", ["y", "x"])
+def test_adjoint_through_the_adiabatic_cavity_matches_central_differences(control):
+    """With the adiabatic field on (Eqs. 17-18, probe included) the kick's phase depends
+    on the whole density through alpha; the adjoint's global term must reproduce
+    central differences for pump (y) and x-lattice knots.  The cavity moves the
+    gradient by ~10%, so a missing or wrong global term fails."""
+    nsteps, dt = 30, 0.01
+    kn = np.random.Generator(np.random.PCG64(11)).uniform(-6.0, -2.0, size=5)   # red-detuned pump
+    kx = np.random.Generator(np.random.PCG64(12)).uniform(0.0, 3.0, size=4)
+    ax = control == "x"
+    knots = kx if ax else kn
+    sched = W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots)
+    s = W.Setup(nx=32, ny=32, lx=8.0, ly=8.0, dt=dt, g=15.0, kx_lat=1.3, ky_lat=2.0,
+                sx=sched if ax else W.Schedule("const", 1.0), sy=W.Schedule("const", -4.0) if ax else sched,
+                cavity=True, cavity_mode="adiabatic", vc=-0.4, kc=2.0, delta_c=-6.0, kappa=3.0, n_atoms=40.0,
+                probe_omega=1.5, probe_detuning=2.0, probe_phase=0.3)
+    psi0, tg = W.gaussian(s, 1.0, 0.3, 0.1), W.gaussian(s, 0.9, -0.2, 0.2)
+    _, grad, _ = O.adjoint(problem(s), 0.0, psi0, tg, nsteps, 0, "fidelity", control=control)
+    h = 1e-5
+    fd = np.zeros_like(grad)
+    for m in range(grad.size):
+        for sgn in (1, -1):
+            k2 = knots.copy()
+            k2[m] += sgn * h
+            sc = W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=k2)
+            v2, _, _ = O.adjoint(problem(s.with_(sx=sc) if ax else s.with_(sy=sc)), 0.0, psi0, tg, nsteps, 0,
+                                 "fidelity", control=control)
+            fd[m] += sgn * v2 / (2 * h)
+    assert np.abs(grad - fd).max() / np.abs(fd).max() < 1e-6
+    _, g0, _ = O.adjoint(problem(s.with_(cavity=False, probe_omega=0.0)), 0.0, psi0, tg, nsteps, 0, "fidelity",
+                         control=control)
+    assert np.abs(g0 - grad).max() > 0.03 * np.abs(grad).max()
+
+
 def test_adjoint_is_independent_of_checkpoint_spacing_and_returns_forward_state():
     nsteps = 30
     s = _control_problem(nsteps)
