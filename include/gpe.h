@@ -224,15 +224,18 @@ int gpe_batch_info(gpe_batch *b, int group, int out[8]);
 
 /* Cavity state of batch member m after the batch's last call, as gpe_get_cavity
  * (synchronous; the adiabatic field of Sec. 5.3, Eqs. 17-18, is the only cavity model a
- * batch runs, on members up to 128^2). */
+ * batch runs: members with the field ODE are rejected at creation). */
 int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 
 /* ------------------------------------------------------------------ adjoint
  * Gradient of a loss of psi(T), T = t0 + nsteps dt, with respect to the knot values
  * of a lattice-depth schedule (GPE_SCHED_KNOTS) of every member of a batch of
- * real-time problems of one grid size (no cavity): control GPE_CONTROL_X_LATTICE
- * differentiates the x lattice Vx(t) cos^2(kx_lat x), GPE_CONTROL_PUMP the y lattice
- * Vy(t) cos^2(ky_lat y), the pump of the cavity set-up (Sec. 5.3) with the cavity off.
+ * real-time problems of one grid size: control GPE_CONTROL_X_LATTICE differentiates the
+ * x lattice Vx(t) cos^2(kx_lat x), GPE_CONTROL_PUMP the y lattice Vy(t) cos^2(ky_lat y),
+ * the pump of the cavity set-up (Sec. 5.3).  Members run without the cavity or with the
+ * adiabatic field (GPE_CAVITY_ADIABATIC, probe included): then the gradient also carries
+ * alpha's dependence on the density and, for the pump, on Vy (sqrt(Vy Vc) coupling; the
+ * pump knots must keep Vy Vc > 0).  The field ODE is rejected (GPE_ERR_UNSUPPORTED).
  * Losses:
  *   GPE_LOSS_FIDELITY: L = 1 - |<target|psi(T)>|^2, <a|b> = sum conj(a) b dx dy;
  *   GPE_LOSS_ENERGY:   L = E_kin + E_pot + E_int of psi(T) at time T.

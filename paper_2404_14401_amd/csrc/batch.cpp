@@ -27,6 +27,7 @@ struct Tuning {
 struct BGroup {
     int nx = 0, ny = 0;
     bool lds = false;
+    bool adia = false;  // some member has the adiabatic field: probe passes before its kicks
     std::vector<int> members;
     Tuning tune;
     Shape shape{};
@@ -41,6 +42,8 @@ struct AdjWork {
     int64_t cap_steps = 0;
     std::vector<float2 *> psi, lam;
     std::vector<double *> kick_grad, partials;
+    std::vector<double *> probe, aprobe;  // adiabatic field: forward and adjoint probe partials
+    bool any_adia = false;                // some member has the adiabatic field
     std::vector<float2 *> ckpt;  // [slot * nb + member]
     int ckpt_slots = 0;
     AdjInst *d_adj = nullptr;
@@ -128,8 +131,24 @@ static int mid_steps(gpe_batch *b, int n0, int count, hipStream_t s)
             if (g.lds) continue;
             int rc = group_col(b, g, s);
             if (rc) return rc;
+            if (g.adia && (rc = group_row(b, g, ROW_PROBE_MID, n0 + k, s))) return rc;
             if ((rc = group_row(b, g, ROW_MID, n0 + k, s))) return rc;
         }
+    return GPE_OK;
+}
+
+// The last step of a call for every multi-pass group: column pass, probe (adiabatic
+// field), exit row pass.
+static int exit_step(gpe_batch *b, int n)
+{
+    int rc;
+    for (auto &g : b->groups)
+        if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
+    for (auto &g : b->groups) {
+        if (g.lds) continue;
+        if (g.adia && (rc = group_row(b, g, ROW_PROBE_MID, n, b->work))) return rc;
+        if ((rc = group_row(b, g, ROW_EXIT, n, b->work))) return rc;
+    }
     return GPE_OK;
 }
 
@@ -161,9 +180,8 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
         if (descs[i].dt != descs[0].dt) return fail(GPE_ERR_INVALID, "batch members must share dt");
-        if (pots[i].cavity == GPE_CAVITY_ODE ||
-            (pots[i].cavity == GPE_CAVITY_ADIABATIC && !lds_supported(descs[i].nx, descs[i].ny)))
-            return fail(GPE_ERR_UNSUPPORTED, "batched cavity members: adiabatic field on grids up to 128^2 only");
+        if (pots[i].cavity == GPE_CAVITY_ODE)
+            return fail(GPE_ERR_UNSUPPORTED, "batched cavity members: only the adiabatic field");
     }
     gpe_batch *b = new gpe_batch();
     b->n = n;
@@ -237,6 +255,11 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
                 d.grid = p->grid;
                 d.pot = p->pot;
                 d.st = p->st;
+                if (p->pot.cavity == GPE_CAVITY_ADIABATIC) {
+                    // one partial record per row work-group, for any row shape the tuner picks
+                    if ((rc = balloc(b, (void **)&d.probe, sizeof(double) * NPART * g.ny))) return cleanup(rc);
+                    g.adia = true;
+                }
                 g.h_inst[k] = d;
             }
             if ((rc = balloc(b, (void **)&g.d_inst, sizeof(InstDesc) * m))) return cleanup(rc);
@@ -309,8 +332,11 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
     if (side_used) HIP_OK(hipEventRecord(b->ev_side, b->side));
     // multi-pass groups
     if (has_multipass(b)) {
-        for (auto &g : b->groups)
-            if (!g.lds && (rc = group_row(b, g, ROW_ENTRY, 0, b->work))) return rc;
+        for (auto &g : b->groups) {
+            if (g.lds) continue;
+            if (g.adia && (rc = group_row(b, g, ROW_PROBE_REAL, 0, b->work))) return rc;
+            if ((rc = group_row(b, g, ROW_ENTRY, 0, b->work))) return rc;
+        }
         int64_t mids = nsteps - 1, done = 0;
         if (!b->warmed && mids > 0) {
             const int k = (int)std::min<int64_t>(mids, 1);
@@ -328,16 +354,10 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
                 done += b->chunk;
             }
             if ((rc = mid_steps(b, 0, (int)(mids - done), b->work))) return rc;
-            for (auto &g : b->groups)
-                if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
-            for (auto &g : b->groups)
-                if (!g.lds && (rc = group_row(b, g, ROW_EXIT, (int)(mids - done), b->work))) return rc;
+            if ((rc = exit_step(b, (int)(mids - done)))) return rc;
         } else {
             if ((rc = mid_steps(b, (int)done, (int)(mids - done), b->work))) return rc;
-            for (auto &g : b->groups)
-                if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
-            for (auto &g : b->groups)
-                if (!g.lds && (rc = group_row(b, g, ROW_EXIT, (int)mids, b->work))) return rc;
+            if ((rc = exit_step(b, (int)mids))) return rc;
         }
     }
     if (side_used) HIP_OK(hipStreamWaitEvent(b->work, b->ev_side, 0));
@@ -357,7 +377,9 @@ static double time_group(gpe_batch *b, BGroup &g, int steps)
     for (int it = 0; it < 2; ++it) {
         auto t = std::chrono::steady_clock::now();
         for (int k = 0; k < steps; ++k) {
-            if (group_col(b, g, b->work) || group_row(b, g, ROW_MID, k, b->work)) return 1e30;
+            if (group_col(b, g, b->work) || (g.adia && group_row(b, g, ROW_PROBE_MID, k, b->work)) ||
+                group_row(b, g, ROW_MID, k, b->work))
+                return 1e30;
         }
         if (hipStreamSynchronize(b->work) != hipSuccess) return 1e30;
         double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count();
@@ -490,11 +512,15 @@ static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t n
         w->lam.resize(nb);
         w->kick_grad.resize(nb);
         w->partials.resize(nb);
+        w->probe.resize(nb);
+        w->aprobe.resize(nb);
         for (int i = 0; i < nb; ++i) {
             int rc;
             if ((rc = balloc(b, (void **)&w->psi[i], sizeof(float2) * npts))) return rc;
             if ((rc = balloc(b, (void **)&w->lam[i], sizeof(float2) * npts))) return rc;
             if ((rc = balloc(b, (void **)&w->partials[i], sizeof(double) * 4096))) return rc;
+            if ((rc = balloc(b, (void **)&w->probe[i], sizeof(double) * NPART * 4096))) return rc;
+            if ((rc = balloc(b, (void **)&w->aprobe[i], sizeof(double) * NPART * 4096))) return rc;
             w->bytes += 2 * sizeof(float2) * npts;
         }
         int rc;
@@ -561,10 +587,14 @@ static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     ca.xcd_swizzle = (cblocks % 8 == 0 && cblocks >= 64) ? 1 : 0;
     const int64_t k = n1 - n0;
     ra.n = 0;
+    if (w->any_adia)
+        LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_PROBE_REAL, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
     LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_ENTRY, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
     for (int64_t j = 0; j < k; ++j) {
         LAUNCH_OK(launch_col_batched(w->ny, 8, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
         ra.n = (int)j;
+        if (w->any_adia)
+            LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_PROBE_MID, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
         LAUNCH_OK(launch_row_batched(w->nx, 8, j + 1 < k ? ROW_MID : ROW_EXIT, ra, rblocks, sh.row_threads,
                                      sh.row_shmem, b->work));
     }
@@ -590,12 +620,16 @@ static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     // rows need 2 arrays' worth of registers: at most 256 threads per work-group
     const size_t rsh = adj_row_shmem(w->nx, sh.row_lines, 8), csh = adj_col_shmem(w->ny, sh.col_cols, 8);
     ra.kick = (int)n1;
+    if (w->any_adia)
+        LAUNCH_OK(launch_row_adj(w->nx, ADJ_PROBE_FIRST, ra, rblocks, sh.row_threads, rsh, b->work));
     LAUNCH_OK(launch_row_adj(w->nx, ADJ_FIRST, ra, rblocks, sh.row_threads, rsh, b->work));
     int pending = (int)n1;
     for (int64_t n = n1 - 1; n >= n0; --n) {
         ca.tail_kick = pending;
         LAUNCH_OK(launch_col_adj(w->ny, ca, cblocks, sh.col_threads, csh, b->work));
         ra.kick = (int)n;
+        if (w->any_adia)
+            LAUNCH_OK(launch_row_adj(w->nx, ADJ_PROBE_MID, ra, rblocks, sh.row_threads, rsh, b->work));
         LAUNCH_OK(launch_row_adj(w->nx, n > n0 ? ADJ_MID : ADJ_LAST, ra, rblocks, sh.row_threads, rsh, b->work));
         pending = (int)n;
     }
@@ -624,7 +658,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         const Sched &ctl = pump ? p->pot.sy : p->pot.sx;
         if (ctl.kind != GPE_SCHED_KNOTS || ctl.nknots != nknots)
             return fail(GPE_ERR_INVALID, "members need a knot schedule with nknots values on the controlled lattice");
-        if (p->pot.cavity) return fail(GPE_ERR_UNSUPPORTED, "adjoint with the cavity on");
+        if (p->pot.cavity == GPE_CAVITY_ODE)
+            return fail(GPE_ERR_UNSUPPORTED, "adjoint with the field-ODE cavity (the adiabatic field is supported)");
         if (!psi0[i] || !target[i]) return fail(GPE_ERR_INVALID, "null member state");
     }
     if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
@@ -651,10 +686,14 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
                               sizeof(double) * nknots, hipMemcpyHostToDevice, b->work));
     std::vector<InstDesc> fwd(nb);
     std::vector<AdjInst> adj(nb);
+    w->any_adia = false;
     for (int i = 0; i < nb; ++i) {
         gpe_plan *p = b->plans[i];
-        fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st};
-        adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i], pump ? 1 : 0};
+        const bool adia = p->pot.cavity == GPE_CAVITY_ADIABATIC;
+        fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st, adia ? w->probe[i] : nullptr};
+        adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i], pump ? 1 : 0,
+                         adia ? w->aprobe[i] : nullptr};
+        if (adia) w->any_adia = true;
     }
     HIP_OK(hipMemcpyAsync(w->d_fwd, fwd.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice, b->work));
     HIP_OK(hipMemcpyAsync(w->d_adj, adj.data(), sizeof(AdjInst) * nb, hipMemcpyHostToDevice, b->work));

@@ -126,6 +126,7 @@ struct InstDesc {
     GridDev grid;
     PotDev pot;
     DevState *st;
+    double *probe;  // adiabatic field: [row work-groups][NPART] partials of the probe pass (else null)
 };
 
 // A batched row or column pass over all members of one grid size.
@@ -148,12 +149,16 @@ struct AdjInst {
     double *partials;   // [row work-groups] per-row-block sums of the current kick
     double *kick_grad;  // [nsteps + 1] dL/dV0 at t0 + k dt
     int control_axis;   // controlled lattice: 0 x, 1 y (the pump)
+    double *aprobe;     // adiabatic field: [row work-groups][NPART] sums of rho, rho cos kx cos ky,
+                        // rho cos^2 kx, s cos^2 kx, s cos kx cos ky over (psi', G') (else null)
 };
 
 enum AdjRowMode : int {
     ADJ_FIRST = 0,  // real-space (psi_K, lam_K) -> adjoint half kick at t_K -> FFT_x
     ADJ_MID = 1,    // IFFT_x -> adjoint merged kick at t_n -> FFT_x
     ADJ_LAST = 2,   // IFFT_x -> adjoint half kick at t_0 -> real space
+    ADJ_PROBE_FIRST = 3,  // (adiabatic field) real-space (psi, G) -> field and adjoint sums
+    ADJ_PROBE_MID = 4,    // (adiabatic field) IFFT_x of both -> field and adjoint sums
 };
 
 struct AdjPassArgs {

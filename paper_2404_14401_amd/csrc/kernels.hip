@@ -244,14 +244,23 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 }
 
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
+// A member with the adiabatic field carries probe partials: the probe modes write them,
+// the kick modes turn them into alpha; other members skip the probe modes.
 template <int N, int R, int MODE>
 __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
 {
     extern __shared__ XchgT smem[];
     __shared__ double red[8 * NPART];
     const InstDesc &I = a.inst[blockIdx.x / a.blocks_per_inst];
-    row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, blockIdx.x % a.blocks_per_inst,
-                                a.per_wg, smem, red);
+    const int lb = blockIdx.x % a.blocks_per_inst;
+    if constexpr (MODE == ROW_PROBE_REAL || MODE == ROW_PROBE_MID) {
+        if (!I.probe) return;
+        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, I.probe + lb * NPART, a.n, lb, a.per_wg, smem,
+                                    red);
+    } else {
+        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
+                                    I.probe, a.blocks_per_inst);
+    }
 }
 
 // ------------------------------------------------------------------ column pass
@@ -898,6 +907,8 @@ template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPas
     if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY);
     else if (mode == ROW_MID) GPE_ROWB(ROW_MID);
     else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT);
+    else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL);
+    else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID);
     else return hipErrorInvalidValue;
 #undef GPE_ROWB
     return hipGetLastError();
@@ -1023,7 +1034,8 @@ hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStr
 // The kinetic propagation U = IFFT2 M FFT2 is unitary, so both the state and G go
 // back through U^H = IFFT2 conj(M) FFT2: the same passes with the conjugate factor.
 template <int N, int R, int MODE>
-__device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines, int kick, XchgT *smem, double *red)
+__device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines, int kick, XchgT *smem, double *red,
+                                             int nprobe)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -1050,10 +1062,71 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
         w[m] = {(double)b.x, (double)b.y};
     }
     __syncthreads();
-    if constexpr (MODE != ADJ_FIRST) fft_line2<N, R, true>(v, w, la, lb2, t, s_tw);
+    if constexpr (MODE != ADJ_FIRST && MODE != ADJ_PROBE_FIRST) fft_line2<N, R, true>(v, w, la, lb2, t, s_tw);
+    const double cyc = I.pot.ty[row].z;  // cos(kc y) of this row
+    if constexpr (MODE == ADJ_PROBE_FIRST || MODE == ADJ_PROBE_MID) {
+        // sums for the adiabatic field and its adjoint: rho, rho cxcy, rho cc2, s cc2, s cxcy
+        double part[NPART] = {};
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const double cx = s_tx[t + m * T].z;
+            const double d = v[m].x * v[m].x + v[m].y * v[m].y;
+            const double s = w[m].x * v[m].y - w[m].y * v[m].x;
+            part[0] += d;
+            part[1] += cx * cyc * d;
+            part[2] += cx * cx * d;
+            part[3] += cx * cx * s;
+            part[4] += cx * cyc * s;
+        }
+        block_sum<NPART>(part, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) I.aprobe[lb * NPART + k] = part[k];
+        return;
+    }
     const double tk = I.st->t0 + kick * gd.dt;
     const double tau = (MODE == ADJ_MID) ? gd.dt : 0.5 * gd.dt;
-    const VLine vl = vline_cav(I.pot, row, tk, 0.0, 0.0);
+    // adiabatic field (Sec. 5.3, Eqs. 17-18): alpha of the kicked density and the global
+    // adjoint term of its density dependence, from the probe sums of this member
+    double are = 0.0, aim = 0.0, bth = 0.0, bc = 0.0, thn = 0.0, c2n = 0.0, inv0 = 0.0, extra = 0.0;
+    if (I.aprobe) {
+        double sm[NPART] = {};
+        for (int i = threadIdx.x; i < nprobe; i += blockDim.x)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) sm[k] += I.aprobe[i * NPART + k];
+        block_sum<NPART>(sm, red);
+        if (threadIdx.x == 0) {
+            const PotDev &p = I.pot;
+            double ar, ai;
+            alpha_adiabatic(p, tk, sm[0], sm[1], sm[2], &ar, &ai);
+            const double tn = sm[1] / sm[0], cn = sm[2] / sm[0];
+            const double sq = sqrt(fmax(sched_eval(p.sy, tk) * p.vc, 0.0));
+            const double dr = p.delta_c - p.n_atoms * p.vc * cn, di = p.kappa, dd = dr * dr + di * di;
+            // A = sum s dV/dalpha = 2 U0 alpha S_c + 2 sqrt(Vp U0) S_x
+            const double Ar = 2.0 * p.vc * ar * sm[3] + 2.0 * sq * sm[4], Ai = 2.0 * p.vc * ai * sm[3];
+            // dalpha/dTheta^ = N sq / (D + i kappa); dalpha/dC^ = alpha N U0 / (D + i kappa)
+            const double tr = p.n_atoms * sq * dr / dd, ti = -p.n_atoms * sq * di / dd;
+            const double cr = p.n_atoms * p.vc * (ar * dr + ai * di) / dd, ci = p.n_atoms * p.vc * (ai * dr - ar * di) / dd;
+            red[0] = ar;
+            red[1] = ai;
+            red[2] = Ar * tr + Ai * ti;  // Re(conj(A) dalpha/dTheta^)
+            red[3] = Ar * cr + Ai * ci;  // Re(conj(A) dalpha/dC^)
+            red[4] = tn;
+            red[5] = cn;
+            red[6] = 1.0 / sm[0];
+            // pump control: (U0 / sq) Re(alpha) S_x + Re(conj(A) dalpha/dVp), dalpha/dVp = N U0 Theta^ / (2 sq (D + i kappa))
+            double ex = 0.0;
+            if (I.control_axis && sq > 0.0) {
+                const double f = p.n_atoms * p.vc * tn / (2.0 * sq);
+                ex = (p.vc / sq) * ar * sm[4] + f * (Ar * dr - Ai * di) / dd;
+            }
+            red[7] = ex;
+        }
+        __syncthreads();
+        are = red[0]; aim = red[1]; bth = red[2]; bc = red[3]; thn = red[4]; c2n = red[5]; inv0 = red[6]; extra = red[7];
+        __syncthreads();
+    }
+    const VLine vl = vline_cav(I.pot, row, tk, are, aim);
     const float *vu = I.pot.vuser ? I.pot.vuser + (size_t)row * N : nullptr;
     const double wy = I.control_axis ? (double)I.pot.ty[row].y : 0.0;  // cos^2(ky_lat y) of this row
     double part[1] = {0.0};
@@ -1068,11 +1141,17 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
         sincos_d(th, &sn, &cs);
         const double s = w[m].x * v[m].y - w[m].y * v[m].x;  // Im(conj(G') psi')
         const C vin = {v[m].x * cs - v[m].y * sn, v[m].x * sn + v[m].y * cs};
-        const double k2 = 2.0 * gd.g * tau * s;
+        double wt = gd.g * s;
+        if (I.aprobe) {
+            const double cx = tx.z;
+            wt += (bth * (cx * cyc - thn) + bc * (cx * cx - c2n)) * inv0;
+        }
+        const double k2 = 2.0 * tau * wt;
         w[m] = {w[m].x * cs - w[m].y * sn + k2 * vin.x, w[m].x * sn + w[m].y * cs + k2 * vin.y};
         v[m] = vin;
         part[0] += tau * s * (I.control_axis ? wy : (double)tx.y);  // dV/dV0 = cos^2 of the controlled lattice
     }
+    if (lb == 0 && threadIdx.x == 0) part[0] += tau * extra;  // global pump term, once per kick
     block_sum<1>(part, red);
     if (threadIdx.x == 0) I.partials[lb] = part[0];
     if constexpr (MODE != ADJ_LAST) fft_line2<N, R, false>(v, w, la, lb2, t, s_tw);
@@ -1087,9 +1166,11 @@ template <int N, int R, int MODE>
 __global__ void __launch_bounds__(512) row_adj_b(AdjPassArgs a)
 {
     extern __shared__ XchgT smem[];
-    __shared__ double red[8];
+    __shared__ double red[8 * NPART];
     const AdjInst &I = a.inst[blockIdx.x / a.blocks_per_inst];
-    row_adj_body<N, R, MODE>(I, blockIdx.x % a.blocks_per_inst, a.per_wg, a.kick, smem, red);
+    if constexpr (MODE == ADJ_PROBE_FIRST || MODE == ADJ_PROBE_MID)
+        if (!I.aprobe) return;
+    row_adj_body<N, R, MODE>(I, blockIdx.x % a.blocks_per_inst, a.per_wg, a.kick, smem, red, a.blocks_per_inst);
 }
 
 // Sum one member's row partials (fixed order) into kick_grad[k]; one work-group.
@@ -1211,6 +1292,8 @@ template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPas
     if (mode == ADJ_FIRST) GPE_RADJ(ADJ_FIRST);
     else if (mode == ADJ_MID) GPE_RADJ(ADJ_MID);
     else if (mode == ADJ_LAST) GPE_RADJ(ADJ_LAST);
+    else if (mode == ADJ_PROBE_FIRST) GPE_RADJ(ADJ_PROBE_FIRST);
+    else if (mode == ADJ_PROBE_MID) GPE_RADJ(ADJ_PROBE_MID);
     else return hipErrorInvalidValue;
 #undef GPE_RADJ
     return hipGetLastError();

@@ -140,16 +140,44 @@ def test_adiabatic_batched_sweep_matches_plain_solver_and_oracle():
             assert close_alpha(b.cavity(i), st.alpha, 1e-4), i
 
 
-def test_batch_rejects_unsupported_cavity_members():
+def test_batch_rejects_field_ode_members():
     torch_cuda()
     from paper_2404_14401_amd import gpe
 
     with pytest.raises(gpe.GpeError) as e:
-        gpe.Batch([W.self_organisation_128(5.0, -10.0).with_(nx=256, ny=256, lx=32.0, ly=32.0)])
-    assert e.value.code == gpe.ERR_UNSUPPORTED
-    with pytest.raises(gpe.GpeError) as e:
         gpe.Batch([W.cavity_scaled(64, 0)])
     assert e.value.code == gpe.ERR_UNSUPPORTED
+
+
+def test_adiabatic_batch_with_multipass_groups():
+    """Adiabatic members on 256^2 and 512^2 grids (multi-pass groups with probe passes,
+    graph-replayed) next to 128^2 LDS members and a member without the cavity: each
+    equals the plain solver; the 256^2 ones equal the oracle."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    big = [W.self_organisation_128(v, -10.0).with_(nx=256, ny=256, lx=32.0, ly=32.0) for v in (6.0, 14.0)]
+    setups = big + [W.self_organisation_128(10.0, -5.0),
+                    W.self_organisation_128(12.0, -10.0).with_(nx=512, ny=512, lx=32.0, ly=32.0),
+                    big[0].with_(cavity=False)]
+    psi0 = [W.self_organisation_start(s) for s in setups]
+    b = gpe.Batch(setups)
+    assert sorted((g["nx"], g["lds"]) for g in b.groups()) == [(128, True), (256, False), (512, False)]
+    devs = [to_dev(p) for p in psi0]
+    n = 160   # more than one 50-step graph chunk
+    b.step(devs, n, 0.0)
+    for i, s in enumerate(setups):
+        plain = gpe.Plan.from_setup(s)
+        d = to_dev(psi0[i])
+        plain.step_real(d, n, 0.0)
+        assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-5, i
+        if s.cavity:
+            assert close_alpha(b.cavity(i), plain.cavity()["alpha"], 1e-5), i
+        if s.nx == 256 and s.cavity:
+            st = state(s)
+            ref, _ = O.step_real(problem(s), st, psi0[i], n)
+            assert rel_l2(to_host(devs[i]), ref) < 1e-4, i
+            assert close_alpha(b.cavity(i), st.alpha, 1e-4), i
 
 
 # ------------------------------------------------------ Bragg probe (Sec. 5.4)
