@@ -103,6 +103,7 @@ static int group_row(gpe_batch *b, BGroup &g, int mode, int n, hipStream_t s)
     a.blocks_per_inst = g.shape.row_blocks;
     a.per_wg = g.shape.row_lines;
     a.n = n;
+    a.adia = g.adia ? 1 : 0;
     const int blocks = g.shape.row_blocks * (int)g.members.size();
     LAUNCH_OK(launch_row_batched(g.nx, g.tune.radix, mode, a, blocks, g.shape.row_threads, g.shape.row_shmem, s));
     (void)b;
@@ -578,6 +579,7 @@ static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0 + n0 * b->dt, b->work));
     BatchPassArgs ra{}, ca{};
     ra.inst = w->d_fwd;
+    ra.adia = w->any_adia ? 1 : 0;
     ra.blocks_per_inst = sh.row_blocks;
     ra.per_wg = sh.row_lines;
     ca.inst = w->d_fwd;

@@ -136,6 +136,7 @@ struct BatchPassArgs {
     int per_wg;           // rows or columns per work-group
     int n;                // step index within the call
     int xcd_swizzle;
+    int adia;             // some member has the adiabatic field (kick kernels read probe partials)
 };
 
 // One member of an adjoint sweep (device memory): the state being reconstructed

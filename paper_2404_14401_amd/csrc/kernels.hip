@@ -246,7 +246,8 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
 // A member with the adiabatic field carries probe partials: the probe modes write them,
 // the kick modes turn them into alpha; other members skip the probe modes.
-template <int N, int R, int MODE>
+// (ADIA is a template flag so that groups without the field keep the probe-free kernel.)
+template <int N, int R, int MODE, bool ADIA>
 __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
 {
     extern __shared__ XchgT smem[];
@@ -257,9 +258,11 @@ __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
         if (!I.probe) return;
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, I.probe + lb * NPART, a.n, lb, a.per_wg, smem,
                                     red);
-    } else {
+    } else if constexpr (ADIA) {
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
                                     I.probe, a.blocks_per_inst);
+    } else {
+        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red);
     }
 }
 
@@ -893,23 +896,30 @@ hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s)
 template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPassArgs &a, int blocks, int threads,
                                                         size_t shmem, hipStream_t s)
 {
-#define GPE_ROWB(M)                                                                                \
+#define GPE_ROWB(M, A)                                                                             \
     do {                                                                                           \
         static bool attr_ = false;                                                                 \
         if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M>,                 \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M, A>,              \
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
             if (e_ != hipSuccess) return e_;                                                       \
             attr_ = true;                                                                          \
         }                                                                                          \
-        hipLaunchKernelGGL((row_pass_b<N, R, M>), dim3(blocks), dim3(threads), shmem, s, a);       \
+        hipLaunchKernelGGL((row_pass_b<N, R, M, A>), dim3(blocks), dim3(threads), shmem, s, a);    \
     } while (0)
-    if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY);
-    else if (mode == ROW_MID) GPE_ROWB(ROW_MID);
-    else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT);
-    else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL);
-    else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID);
-    else return hipErrorInvalidValue;
+    if (a.adia) {
+        if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, true);
+        else if (mode == ROW_MID) GPE_ROWB(ROW_MID, true);
+        else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
+        else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL, true);
+        else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID, true);
+        else return hipErrorInvalidValue;
+    } else {
+        if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, false);
+        else if (mode == ROW_MID) GPE_ROWB(ROW_MID, false);
+        else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, false);
+        else return hipErrorInvalidValue;
+    }
 #undef GPE_ROWB
     return hipGetLastError();
 }
