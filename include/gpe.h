@@ -56,7 +56,7 @@ extern "C" {
 #define GPE_ERR_NOMEM (-2)       /* device allocation failed or exceeds max_bytes */
 #define GPE_ERR_DEVICE (-3)      /* HIP runtime error */
 #define GPE_ERR_NONFINITE (-4)   /* NaN/Inf detected in psi by a fused reduction */
-#define GPE_ERR_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define GPE_ERR_UNSUPPORTED (-5) /* valid request the library does not implement */
 
 typedef struct gpe_plan gpe_plan;
 typedef struct gpe_batch gpe_batch;
