@@ -87,7 +87,7 @@ struct RowArgs {
     DevState *st;
     double *partials;  // [gridDim.x][NPART]
     int n;             // step index within the call; kick time = st->t0 + (n or n+1) dt + t_shift
-    int reduce;        // write partials
+    int reduce;        // write partials: 1 all of them, 2 Theta only (the field ODE without observables)
     int lines_per_wg;
     double t_shift;    // -dt/2 for the midpoint kick of the Fourier-space ordering
     const double *probe;  // adiabatic field: partials of the density about to be kicked

@@ -88,7 +88,7 @@ template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
                                          const PotDev &pot, DevState *st, double *partials, int n, int lb,
                                          int lines, XchgT *smem, double *red, double t_shift = 0.0,
-                                         const double *probe = nullptr, int nprobe = 0)
+                                         const double *probe = nullptr, int nprobe = 0, bool theta_only = false)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -207,18 +207,23 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                 }
             } else {
                 // |psi| is the same before and after a phase kick
-                part[0] += d;
                 part[1] += (double)tx.z * cy * d;
-                part[2] += (double)tx.w * d;
-                part[3] += yv * d;
-                if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d;
+                if (!theta_only) {
+                    part[0] += d;
+                    part[2] += (double)tx.w * d;
+                    part[3] += yv * d;
+                    if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d;
+                }
                 v[m] = kick_real(v[m], th);
             }
         }
     }
     if (partials) {
-        // the C overlap is only needed by the adiabatic field: skip its shuffles otherwise
-        if (pot.cavity == 2)
+        // the C overlap is only needed by the adiabatic field, and the field ODE alone
+        // needs only Theta: skip the other sums' shuffles
+        if (theta_only)
+            block_sum<1>(*reinterpret_cast<double(*)[1]>(part + 1), red);
+        else if (pot.cavity == 2)
             block_sum<NPART>(part, red);
         else
             block_sum<NPART - 1>(*reinterpret_cast<double(*)[NPART - 1]>(part), red);
@@ -240,7 +245,7 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
     __shared__ double red[8 * NPART];
     row_body<N, kRadix, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
                                      a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
-                                     a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe);
+                                     a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe, a.reduce == 2);
 }
 
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).

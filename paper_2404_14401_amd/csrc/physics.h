@@ -171,7 +171,8 @@ __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, 
     if (threadIdx.x == 0) {
         if (ta.npartials > 0) {
             const double norm = s[0] * gd.dA, th = s[1] * gd.dA, mx = s[2] * gd.dA, my = s[3] * gd.dA;
-            if (!isfinite(norm)) st->nonfinite = 1;
+            // (Theta-only partials leave the norm at zero; a non-finite psi reaches Theta too)
+            if (!isfinite(norm) || !isfinite(th)) st->nonfinite = 1;
             st->norm = norm;
             if (ta.imag) {
                 const double inv = 1.0 / norm;

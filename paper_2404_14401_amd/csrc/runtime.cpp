@@ -437,7 +437,7 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
     LAUNCH_OK(launch_set_call(p->st, t0, 0, 0, p->stream));
     RowArgs ra = row_args(p, f);
     ra.n = 0;
-    ra.reduce = first_theta ? 1 : 0;
+    ra.reduce = first_theta ? 2 : 0;
     LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
     for (int64_t n = 0; n < nsteps; ++n) {
         ColArgs ca = col_args(p, f);
@@ -454,7 +454,7 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream,
                              ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
         ra.n = (int)n;
-        ra.reduce = red ? 1 : 0;
+        ra.reduce = red ? (obs ? 1 : 2) : 0;
         hipEvent_t *er = timed ? timing_pair(p, 1) : nullptr;
         LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, ra, sh.row_blocks, sh.row_threads,
                              sh.row_shmem, p->stream, er ? er[0] : nullptr, er ? er[1] : nullptr));
