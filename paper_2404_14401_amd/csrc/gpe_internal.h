@@ -104,6 +104,7 @@ struct TailArgs {
     int imag;          // imaginary-time bookkeeping (scale, pre-normalisation norm)
     int advance_alpha; // compute alpha_{n+1} after the reduction
     int alpha_from_partials;  // adiabatic field of the reduced density (imaginary time)
+    int theta_only;           // the partials hold Theta alone (slot 1)
 };
 
 struct ColArgs {

@@ -162,7 +162,10 @@ __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, 
                                          DevState *st, double *red)
 {
     double s[NPART] = {};
-    if (ta.npartials > 0) {
+    if (ta.npartials > 0 && ta.theta_only) {
+        for (int i = threadIdx.x; i < ta.npartials; i += blockDim.x) s[1] += ta.partials[i * NPART + 1];
+        block_sum<1>(*reinterpret_cast<double(*)[1]>(s + 1), red);
+    } else if (ta.npartials > 0) {
         for (int i = threadIdx.x; i < ta.npartials; i += blockDim.x)
 #pragma unroll
             for (int k = 0; k < NPART; ++k) s[k] += ta.partials[i * NPART + k];

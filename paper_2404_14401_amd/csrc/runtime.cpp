@@ -446,6 +446,7 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         ta.npartials = (n == 0) ? (first_theta ? sh.row_blocks : 0) : (red ? sh.row_blocks : 0);
         ta.first_theta = (n == 0 && first_theta) ? 1 : 0;
         ta.obs = (n >= 1 && obs) ? obs + (n - 1) * NOBS : nullptr;
+        ta.theta_only = (n == 0 || !obs) ? 1 : 0;  // matches the row pass's reduce mode 2
         ta.imag = 0;
         ta.advance_alpha = cav ? 1 : 0;
         ca.do_tail = (ta.npartials > 0 || ta.advance_alpha) ? 1 : 0;
@@ -464,6 +465,7 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         ta.partials = p->partials;
         ta.npartials = sh.row_blocks;
         ta.obs = obs ? obs + (nsteps - 1) * NOBS : nullptr;
+        ta.theta_only = obs ? 0 : 1;
         LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
     }
     if (cav) p->have_theta = true;
