@@ -238,14 +238,16 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
  * pump knots must keep Vy Vc > 0).  The field ODE is rejected (GPE_ERR_UNSUPPORTED).
  * Losses:
  *   GPE_LOSS_FIDELITY: L = 1 - |<target|psi(T)>|^2, <a|b> = sum conj(a) b dx dy;
- *   GPE_LOSS_ENERGY:   L = E_kin + E_pot + E_int of psi(T) at time T.
+ *   GPE_LOSS_ENERGY:   L = E_kin + E_pot + E_int of psi(T) at time T (as gpe_energy's
+ *                      terms times the norm; members without a cavity only, else
+ *                      GPE_ERR_UNSUPPORTED).
  * The reverse sweep rebuilds the forward states by running each step backwards
  * (exact in real time) -- GPE_ADJ_RECONSTRUCT -- or from stored states every
  * ~sqrt(nsteps) steps -- GPE_ADJ_CHECKPOINT; GPE_ADJ_AUTO reconstructs and falls
  * back to checkpoints if the rebuilt psi(0) drifts from the input by more than
  * drift_tol (relative L2).
- * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each, target
- * ignored for the energy loss); knots: host, nb * nknots values (they replace the
+ * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each; target may
+ * be null for the energy loss and is ignored there); knots: host, nb * nknots values (they replace the
  * members' knots of the controlled lattice); loss: host, nb values; grad: host,
  * nb * nknots values;
  * psi_final (nullable): host array of nb device pointers receiving psi(T).

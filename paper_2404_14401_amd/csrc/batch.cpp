@@ -648,8 +648,9 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     const bool pump = control == GPE_CONTROL_PUMP;
     if (!b || !psi0 || !loss || !grad || nsteps < 1 || !knots)
         return fail(GPE_ERR_INVALID, "null argument or nsteps < 1");
-    if (loss_kind != GPE_LOSS_FIDELITY) return fail(GPE_ERR_UNSUPPORTED, "only the fidelity loss runs on the GPU");
-    if (!target) return fail(GPE_ERR_INVALID, "fidelity loss needs target states");
+    if (loss_kind != GPE_LOSS_FIDELITY && loss_kind != GPE_LOSS_ENERGY) return fail(GPE_ERR_INVALID, "bad loss kind");
+    const bool energy = loss_kind == GPE_LOSS_ENERGY;
+    if (!energy && !target) return fail(GPE_ERR_INVALID, "fidelity loss needs target states");
     if (mode < GPE_ADJ_AUTO || mode > GPE_ADJ_CHECKPOINT) return fail(GPE_ERR_INVALID, "bad adjoint mode");
     if (nsteps > (1 << 28)) return fail(GPE_ERR_INVALID, "nsteps too large");
     const int nb = b->n;
@@ -662,7 +663,9 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
             return fail(GPE_ERR_INVALID, "members need a knot schedule with nknots values on the controlled lattice");
         if (p->pot.cavity == GPE_CAVITY_ODE)
             return fail(GPE_ERR_UNSUPPORTED, "adjoint with the field-ODE cavity (the adiabatic field is supported)");
-        if (!psi0[i] || !target[i]) return fail(GPE_ERR_INVALID, "null member state");
+        if (energy && p->pot.cavity != GPE_CAVITY_OFF)
+            return fail(GPE_ERR_UNSUPPORTED, "the energy loss with a cavity (fidelity only there)");
+        if (!psi0[i] || (!energy && !target[i])) return fail(GPE_ERR_INVALID, "null member state");
     }
     if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
     Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, 256);
@@ -700,6 +703,7 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     HIP_OK(hipMemcpyAsync(w->d_fwd, fwd.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice, b->work));
     HIP_OK(hipMemcpyAsync(w->d_adj, adj.data(), sizeof(AdjInst) * nb, hipMemcpyHostToDevice, b->work));
 
+    std::vector<double> terminal(nb, 0.0);  // energy loss: dL/dV0 at T
     auto run = [&](bool checkpoint, double *drift) -> int {
         for (int i = 0; i < nb; ++i) {
             HIP_OK(hipMemcpyAsync(w->psi[i], psi0[i], sizeof(float2) * npts, hipMemcpyDeviceToDevice, b->work));
@@ -721,26 +725,35 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
                 if (psi_final[i])
                     HIP_OK(hipMemcpyAsync(psi_final[i], w->psi[i], sizeof(float2) * npts, hipMemcpyDeviceToDevice,
                                           b->work));
-        // terminal adjoint: L = 1 - |c|^2, c = <target|psi(T)>, G = -2 c target dA
         std::vector<const float2 *> pa(nb), pb(nb);
-        for (int i = 0; i < nb; ++i) {
-            pa[i] = (const float2 *)target[i];
-            pb[i] = w->psi[i];
-        }
         std::vector<std::array<double, 4>> sums;
-        if ((r = pair_sums(b, w, pa, pb, sums))) return r;
-        std::vector<double2> coef(nb);
-        for (int i = 0; i < nb; ++i) {
-            const double dA = b->plans[i]->grid.dA;
-            const double cr = sums[i][0] * dA, ci = sums[i][1] * dA;
-            loss[i] = 1.0 - (cr * cr + ci * ci);
-            coef[i] = make_double2(-2.0 * cr * dA, -2.0 * ci * dA);
+        if (energy) {
+            // terminal adjoint of L = E(psi(T)): G = 2 dA H psi(T), plus dL/dV0 at T
+            const double T = t0 + nsteps * b->dt;
+            for (int i = 0; i < nb; ++i)
+                if ((r = energy_terminal(b->plans[i], w->psi[i], w->lam[i], T, pump ? 1 : 0, w->partials[i], b->work,
+                                         &loss[i], &terminal[i])))
+                    return r;
+        } else {
+            // terminal adjoint: L = 1 - |c|^2, c = <target|psi(T)>, G = -2 c target dA
+            for (int i = 0; i < nb; ++i) {
+                pa[i] = (const float2 *)target[i];
+                pb[i] = w->psi[i];
+            }
+            if ((r = pair_sums(b, w, pa, pb, sums))) return r;
+            std::vector<double2> coef(nb);
+            for (int i = 0; i < nb; ++i) {
+                const double dA = b->plans[i]->grid.dA;
+                const double cr = sums[i][0] * dA, ci = sums[i][1] * dA;
+                loss[i] = 1.0 - (cr * cr + ci * ci);
+                coef[i] = make_double2(-2.0 * cr * dA, -2.0 * ci * dA);
+            }
+            HIP_OK(hipMemcpyAsync(w->d_coef, coef.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, b->work));
+            std::vector<float2 *> dst(w->lam.begin(), w->lam.end());
+            HIP_OK(hipMemcpyAsync(w->d_dst, dst.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+            HIP_OK(hipMemcpyAsync(w->d_pa, pa.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
+            LAUNCH_OK(launch_scaled_copy(w->d_dst, w->d_pa, w->d_coef, npts, nb, 64, b->work));
         }
-        HIP_OK(hipMemcpyAsync(w->d_coef, coef.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, b->work));
-        std::vector<float2 *> dst(w->lam.begin(), w->lam.end());
-        HIP_OK(hipMemcpyAsync(w->d_dst, dst.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
-        HIP_OK(hipMemcpyAsync(w->d_pa, pa.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
-        LAUNCH_OK(launch_scaled_copy(w->d_dst, w->d_pa, w->d_coef, npts, nb, 64, b->work));
         if (checkpoint) {
             for (int64_t s = nseg - 1; s >= 0; --s) {
                 const int64_t e = std::min(nsteps, (s + 1) * seg);
@@ -790,8 +803,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
             int i0;
             double w0, w1;
             hat(s, t0 + k * b->dt, &i0, &w0, &w1);
-            g[i0] += w0 * kg[k];
-            g[i0 + 1] += w1 * kg[k];
+            g[i0] += w0 * (kg[k] + (k == nsteps ? terminal[i] : 0.0));
+            g[i0 + 1] += w1 * (kg[k] + (k == nsteps ? terminal[i] : 0.0));
         }
     }
     if (info) {

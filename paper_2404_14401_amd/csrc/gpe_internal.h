@@ -66,6 +66,7 @@ enum RowMode : int {
     ROW_FWD = 3,    // real-space psi -> FFT_x, energy partials (E_pot, E_int, norm)
     ROW_PROBE_REAL = 4,  // real-space psi -> partials of norm, Theta, C (no store)
     ROW_PROBE_MID = 5,   // IFFT_x -> partials of norm, Theta, C (no store)
+    ROW_INV = 6,         // IFFT_x only (back to real space)
 };
 
 // Column-pass modes.
@@ -77,6 +78,7 @@ enum ColMode : int {
     COL_FWD_KHALF = 4, // FFT_y -> kinetic half step (Fourier-space state out)
     COL_KHALF_INV_IM = 5,  // imaginary time: pending scale and kinetic half step -> IFFT_y
     COL_FWD_KHALF_IM = 6,  // imaginary time: FFT_y -> kinetic half step, partials of sum |psi_k|^2
+    COL_KIN_APPLY = 7,     // FFT_y -> times |k|^2/2 /(nx ny), partials of sum |k|^2/2 |psi_k|^2 -> IFFT_y
 };
 
 struct RowArgs {

@@ -145,6 +145,12 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
         return;
     }
 
+    if constexpr (MODE == ROW_INV) {
+        fft_line<N, R, true>(v, lds, t, twx);
+#pragma unroll
+        for (int m = 0; m < R; ++m) store_c64(dst + t + m * T, v[m]);
+        return;
+    }
     // kick time: t_n for the entry kick, t_{n+1} for the others; imaginary time freezes
     // V; the energy pass evaluates V at the call's own time
     double tk = st->t0;
@@ -355,6 +361,31 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
             for (int k = 0; k < NPART; ++k) partials[k] = part[k];
         return;
     }
+    if constexpr (MODE == COL_KIN_APPLY) {
+        // the kinetic operator |k|^2/2 applied in Fourier space (its expectation reduced on
+        // the way), then back along y; the 1/(nx ny) of the round trip is folded in
+        const int ix = col >= nx / 2 ? col - nx : col;
+        const double kx = 2.0 * M_PI * ix / gd.lx;
+        const double inv = 1.0 / ((double)gd.nx * gd.ny);
+        double part[NPART] = {};
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int j = t + m * T;
+            const int iy = j >= N / 2 ? j - N : j;
+            const double ky = 2.0 * M_PI * iy / gd.ly;
+            const double e = 0.5 * (kx * kx + ky * ky);
+            part[0] += e * (v[m].x * v[m].x + v[m].y * v[m].y);
+            v[m] = {v[m].x * e * inv, v[m].y * e * inv};
+        }
+        block_sum<1>(*reinterpret_cast<double(*)[1]>(part), red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) partials[k] = part[k];
+        fft_line<N, R, true>(v, lds, t, twy);
+#pragma unroll
+        for (int m = 0; m < R; ++m) store_c64(dst + (size_t)(t + m * T) * nx + col, v[m]);
+        return;
+    }
     if constexpr (MODE == COL_EKIN) {
         const int ix = col >= nx / 2 ? col - nx : col;
         const double kx = 2.0 * M_PI * ix / gd.lx;
@@ -482,6 +513,34 @@ __global__ void __launch_bounds__(256) marginal_kernel(const float2 *psi, int nx
     red[q * 64 + lane] = s;
     __syncthreads();
     if (q == 0 && col < nx) out[col] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+}
+
+// Terminal adjoint of the energy loss (one work-group per row): with lam = T psi on
+// entry, lam <- 2 dA (T psi + (V(t) + g|psi|^2) psi), the gradient of E_kin + E_pot +
+// E_int; partials[row] = dA sum_x w(x) |psi|^2, the loss's derivative by the depth of
+// the controlled lattice (w = cos^2 along x, or along y for axis 1).
+__global__ void __launch_bounds__(256) energy_grad_kernel(const float2 *psi, float2 *lam, GridDev gd, PotDev pot,
+                                                          const DevState *st, int axis, double *partials)
+{
+    __shared__ double red[4];
+    const int row = blockIdx.x, nx = gd.nx;
+    const VLine vl = vline_cav(pot, row, st->t0, st->alpha_re, st->alpha_im);
+    const float4 ty = pot.ty[row];
+    const float *vu = pot.vuser ? pot.vuser + (size_t)row * nx : nullptr;
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        const size_t q = (size_t)row * nx + i;
+        const float4 tx = pot.tx[i];
+        const float2 p = psi[q], l = lam[q];
+        const double d = (double)p.x * p.x + (double)p.y * p.y;
+        double V = vpoint(vl, tx);
+        if (vu) V += (double)vu[i];
+        const double f = V + gd.g * d;
+        lam[q] = make_float2((float)(2.0 * gd.dA * ((double)l.x + f * p.x)), (float)(2.0 * gd.dA * ((double)l.y + f * p.y)));
+        s[0] += (axis ? (double)ty.y : (double)tx.y) * d;
+    }
+    block_sum<1>(s, red);
+    if (threadIdx.x == 0) partials[row] = s[0] * gd.dA;
 }
 
 // ------------------------------------------------------------- whole grid in LDS
@@ -753,6 +812,7 @@ template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowAr
         else if (mode == ROW_FWD) GPE_ROW(ROW_FWD, false);
         else if (mode == ROW_PROBE_REAL) GPE_ROW(ROW_PROBE_REAL, false);
         else if (mode == ROW_PROBE_MID) GPE_ROW(ROW_PROBE_MID, false);
+        else if (mode == ROW_INV) GPE_ROW(ROW_INV, false);
         else return hipErrorInvalidValue;
     }
 #undef GPE_ROW
@@ -800,6 +860,7 @@ template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int 
     else if (mode == COL_FWD_KHALF) GPE_COL(COL_FWD_KHALF);
     else if (mode == COL_KHALF_INV_IM) GPE_COL(COL_KHALF_INV_IM);
     else if (mode == COL_FWD_KHALF_IM) GPE_COL(COL_FWD_KHALF_IM);
+    else if (mode == COL_KIN_APPLY) GPE_COL(COL_KIN_APPLY);
     else return hipErrorInvalidValue;
 #undef GPE_COL
     return hipGetLastError();
@@ -845,6 +906,13 @@ hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_h
 hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(norm_kernel, dim3(blocks), dim3(256), 0, s, psi, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_grad(const float2 *psi, float2 *lam, const GridDev &gd, const PotDev &pot,
+                              const DevState *st, int axis, double *partials, hipStream_t s)
+{
+    hipLaunchKernelGGL(energy_grad_kernel, dim3(gd.ny), dim3(256), 0, s, psi, lam, gd, pot, st, axis, partials);
     return hipGetLastError();
 }
 

@@ -420,6 +420,44 @@ static int step_real_adiabatic(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double
     return GPE_OK;
 }
 
+// Terminal adjoint of the energy loss L = E_kin + E_pot + E_int (the energy functional
+// of Sec. 5.1, not divided by the norm): G = 2 dA (T + V + g|psi|^2) psi in the
+// real-gradient convention, T psi formed spectrally (FFT_x, FFT_y, |k|^2/2, IFFT_y,
+// IFFT_x).
+int energy_terminal(gpe_plan *p, const float2 *psi, float2 *lam, double t, int axis, double *rpart, hipStream_t s,
+                    double *loss, double *lat)
+{
+    const Shape &sh = p->shape;
+    LAUNCH_OK(launch_set_call(p->st, t, 0, 0, s));
+    RowArgs ra = row_args(p, lam);
+    ra.src = psi;
+    ra.reduce = 1;
+    LAUNCH_OK(launch_row(p->nx, ROW_FWD, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
+    ColArgs ca = col_args(p, lam);
+    ca.do_tail = 0;
+    LAUNCH_OK(launch_col(p->ny, COL_KIN_APPLY, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s));
+    RowArgs ri = row_args(p, lam);
+    ri.partials = nullptr;
+    LAUNCH_OK(launch_row(p->nx, ROW_INV, false, ri, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
+    LAUNCH_OK(launch_energy_grad(psi, lam, p->grid, p->pot, p->st, axis, rpart, s));
+    std::vector<double> rp((size_t)sh.row_blocks * NPART), cp((size_t)sh.col_blocks * NPART), lp((size_t)p->ny);
+    HIP_OK(hipMemcpyAsync(rp.data(), p->partials, rp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(cp.data(), p->partials2, cp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(lp.data(), rpart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double ep = 0, ei = 0, ek = 0, l = 0;
+    for (int b = 0; b < sh.row_blocks; ++b) {
+        ep += rp[b * NPART + 1];
+        ei += rp[b * NPART + 2];
+    }
+    for (int b = 0; b < sh.col_blocks; ++b) ek += cp[b * NPART + 0];
+    for (int j = 0; j < p->ny; ++j) l += lp[j];
+    const double dA = p->grid.dA;
+    *loss = ek * dA / ((double)p->nx * p->ny) + ep * dA + 0.5 * p->g * ei * dA;
+    *lat = l;
+    return GPE_OK;
+}
+
 extern "C" {
 
 int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *obs)

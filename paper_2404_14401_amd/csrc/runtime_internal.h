@@ -18,6 +18,8 @@ hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads
 hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
 hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
 hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
+hipError_t launch_energy_grad(const float2 *psi, float2 *lam, const GridDev &gd, const PotDev &pot,
+                              const DevState *st, int axis, double *partials, hipStream_t s);
 hipError_t launch_marginal(const float2 *psi, int nx, int ny, int axis, double *out, hipStream_t s);
 hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s);
 hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s);
@@ -104,5 +106,10 @@ struct gpe_plan {
 
 hipEvent_t *timing_pair(gpe_plan *p, int kind);
 int dalloc(gpe_plan *p, void **ptr, size_t bytes);
+// Energy loss of psi at time t and its terminal adjoint (lam <- 2 dA H psi); *lat gets
+// the loss's derivative by the controlled lattice depth (axis 0: x, 1: y).  Runs on s
+// with the plan's own partial buffers and rpart (ny doubles); returns after a sync.
+int energy_terminal(gpe_plan *p, const float2 *psi, float2 *lam, double t, int axis, double *rpart, hipStream_t s,
+                    double *loss, double *lat);
 Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles);
 

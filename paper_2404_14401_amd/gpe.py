@@ -313,8 +313,9 @@ class Batch:
 
 
 def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, mode: str = "auto",
-            drift_tol: float = 1e-4, psi_finals=None, control: str = "x"):
-    """Loss 1 - |<target|psi(T)>|^2 and its gradient w.r.t. the knot values of the
+            drift_tol: float = 1e-4, psi_finals=None, control: str = "x", loss: str = "fidelity"):
+    """Loss 1 - |<target|psi(T)>|^2 (loss "fidelity") or E_kin + E_pot + E_int of psi(T)
+    (loss "energy", targets None) and its gradient w.r.t. the knot values of the
     x-lattice (control "x") or pump, y-lattice (control "pump"), depth of every batch
     member (discrete adjoint on the GPU).  knots: array (n, M).
     Returns (loss[n], grad[n, M], info dict)."""
@@ -322,12 +323,13 @@ def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, m
     n, m = k.shape
     if n != batch.n:
         raise ValueError("one row of knots per batch member")
-    loss = np.zeros(n)
+    out = np.zeros(n)
     grad = np.zeros((n, m))
     info = np.zeros(4)
     fin = batch._ptrs(psi_finals) if psi_finals is not None else None
-    check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), batch._ptrs(targets), int(nsteps), float(t0),
-                            k.ctypes.data, m, CONTROL[control], LOSS["fidelity"], ADJ_MODE[mode], float(drift_tol),
-                            loss.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
-    return loss, grad, {"mode": {1: "reconstruct", 2: "checkpoint"}[int(info[0])], "drift": info[1],
+    tg = batch._ptrs(targets) if targets is not None else None
+    check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), tg, int(nsteps), float(t0),
+                            k.ctypes.data, m, CONTROL[control], LOSS[loss], ADJ_MODE[mode], float(drift_tol),
+                            out.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
+    return out, grad, {"mode": {1: "reconstruct", 2: "checkpoint"}[int(info[0])], "drift": info[1],
                         "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}

@@ -169,3 +169,55 @@ def test_adjoint_through_the_adiabatic_cavity_matches_oracle(control, mode):
     lp, _, _ = gpe.adjoint(batch, d0, dtg, nsteps, kp, control=control)
     lm, _, _ = gpe.adjoint(batch, d0, dtg, nsteps, km, control=control)
     assert abs(grad[0, 2] - (lp[0] - lm[0]) / (2 * h)) <= 1e-2 * np.abs(grad[0]).max()
+
+
+@pytest.mark.parametrize("control", ["x", "pump"])
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+def test_energy_loss_adjoint_matches_oracle_and_finite_differences(control, mode):
+    """L = E_kin + E_pot + E_int of psi(T): the terminal adjoint 2 dA H psi(T) formed on
+    the GPU (spectral kinetic term), plus the loss's own dependence on the final depth."""
+    torch = torch_cuda()
+    from paper_2404_14401_amd import autograd as A
+    from paper_2404_14401_amd import gpe
+
+    nsteps, nb = 60, 2
+    pump = control == "pump"
+    setups = [(pump_setup if pump else control_setup)(b, nsteps=nsteps) for b in range(nb)]
+    batch = gpe.Batch(setups)
+    p0 = [states(s, b)[0] for b, s in enumerate(setups)]
+    d0 = [to_dev(p) for p in p0]
+    knots = np.stack([(s.sy if pump else s.sx).knots for s in setups])
+    loss, grad, info = gpe.adjoint(batch, d0, None, nsteps, knots, mode=mode, control=control, loss="energy")
+    assert info["mode"] == mode and info["drift"] < 1e-4
+    for b, s in enumerate(setups):
+        l_ref, g_ref, _ = O.adjoint(problem(s), 0.0, p0[b], p0[b], nsteps, loss="energy",
+                                    control="y" if pump else "x")
+        assert abs(loss[b] - l_ref) <= 1e-5 * abs(l_ref)
+        assert np.linalg.norm(grad[b] - g_ref) / np.linalg.norm(g_ref) < 1e-3
+    kt = torch.tensor(knots, dtype=torch.float64, requires_grad=True)
+    A.control_loss(kt, batch, d0, None, nsteps, mode=mode, control=control, loss="energy").sum().backward()
+    assert np.abs(kt.grad.numpy() - grad).max() <= 1e-12 * np.abs(grad).max()
+    # central differences of the GPU loss on the last knot (it also carries the terminal
+    # term); the complex64 energy carries ~1e-7 relative rounding noise
+    h = 1e-2
+    kp, km = knots.copy(), knots.copy()
+    kp[0, -1] += h
+    km[0, -1] -= h
+    lp, _, _ = gpe.adjoint(batch, d0, None, nsteps, kp, control=control, loss="energy")
+    lm, _, _ = gpe.adjoint(batch, d0, None, nsteps, km, control=control, loss="energy")
+    assert abs(grad[0, -1] - (lp[0] - lm[0]) / (2 * h)) <= 1e-2 * np.abs(grad[0]).max()
+
+
+def test_energy_loss_with_the_cavity_is_rejected():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = cavity_control_setup(0, "x", nsteps=10)
+    batch = gpe.Batch([s])
+    p0, _ = states(s, 0)
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.adjoint(batch, [to_dev(p0)], None, 10, s.sx.knots[None, :], loss="energy")
+    assert e.value.code == gpe.ERR_UNSUPPORTED
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.adjoint(batch, [to_dev(p0)], None, 10, s.sx.knots[None, :])
+    assert e.value.code == gpe.ERR_INVALID
