@@ -127,7 +127,10 @@ def bench_batched(steps: int, tune_cache: str | None):
 def bench_adjoint(steps: int, nb: int):
     """Optimal-control gradient: nb members at 512^2, `steps` real-time steps, lattice
     depth over 200 knots from PCG64(member), g = 300; loss = 1 - |<target|psi(T)>|^2 with
-    the target the ground state at V0 = 15.  Forward alone vs forward + reverse."""
+    the target the ground state at V0 = 15.  Forward alone vs forward + reverse, in each
+    way of getting the forward states back: reconstruction, segment restarts, and the
+    stored trajectory (every kick's output kept in HBM; its first call also allocates it,
+    later calls reuse it, as an optimiser's repeated gradients would)."""
     import numpy as np
     import torch
 
@@ -158,15 +161,32 @@ def bench_adjoint(steps: int, nb: int):
     t_fwd = time.perf_counter() - t
     out = {"workload": f"{nb} x 512^2 real-time control problems, {steps} steps, dt=5e-4, 200 knots, g=300",
            "steps": steps, "forward_s": t_fwd}
-    for mode in ("reconstruct", "checkpoint"):
+    def run(bb, mode, fwd, kn, **kw):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        loss, grad, info = gpe.adjoint(b, psi0, tgts, steps, knots, mode=mode)
+        loss, grad, info = gpe.adjoint(bb, psi0, tgts, steps, kn, mode=mode, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        out[mode] = {"forward_plus_reverse_s": dt, "ratio_to_forward": dt / t_fwd, "drift": info["drift"],
-                     "workspace_bytes": info["workspace_bytes"], "mean_loss": float(np.mean(loss)),
-                     "grad_norm": float(np.linalg.norm(grad))}
+        return {"forward_plus_reverse_s": dt, "ratio_to_forward": dt / fwd, "drift": info["drift"],
+                "workspace_bytes": info["workspace_bytes"], "mean_loss": float(np.mean(loss)),
+                "grad_norm": float(np.linalg.norm(grad)), "grad": grad}
+
+    ref = None
+    for mode in ("reconstruct", "checkpoint", "store"):
+        try:
+            first = run(b, mode, t_fwd, knots)
+            out[mode] = run(b, mode, t_fwd, knots) if mode == "store" else first
+        except gpe.GpeError as e:  # the stored trajectory may not fit the device
+            out[mode] = {"error": str(e)}
+            continue
+        if mode == "store":
+            out[mode]["first_call_s"] = first["forward_plus_reverse_s"]
+        g = out[mode].pop("grad")
+        if ref is None:
+            ref = g
+        else:
+            out[mode]["grad_rel_diff_vs_reconstruct"] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    b.close()
     # pump-amplitude control through the adiabatic cavity field (probe passes in both sweeps)
     ca = [W.control_512(b, nsteps=steps).with_(
         kx_lat=0.0, sx=W.Schedule("const", 0.0), ky_lat=2.0, cavity=True, cavity_mode="adiabatic", vc=-0.05, kc=2.0,
@@ -181,14 +201,19 @@ def bench_adjoint(steps: int, nb: int):
     bc.step(work, steps, 0.0)
     torch.cuda.synchronize()
     t_fc = time.perf_counter() - t
-    t = time.perf_counter()
-    loss, grad, info = gpe.adjoint(bc, psi0, tgts, steps, kc, mode="reconstruct", control="pump")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    out["adiabatic_cavity_pump"] = {"workload": f"{nb} x 512^2, adiabatic cavity field, pump depth over 200 knots",
-                                    "forward_s": t_fc, "forward_plus_reverse_s": dt, "ratio_to_forward": dt / t_fc,
-                                    "drift": info["drift"], "mean_loss": float(np.mean(loss)),
-                                    "grad_norm": float(np.linalg.norm(grad))}
+    cav = {"workload": f"{nb} x 512^2, adiabatic cavity field, pump depth over 200 knots", "forward_s": t_fc}
+    for mode in ("reconstruct", "store"):
+        try:
+            r = run(bc, mode, t_fc, kc, control="pump")
+            if mode == "store":
+                r = run(bc, mode, t_fc, kc, control="pump")
+        except gpe.GpeError as e:
+            cav[mode] = {"error": str(e)}
+            continue
+        r.pop("grad")
+        cav[mode] = r
+    bc.close()
+    out["adiabatic_cavity_pump"] = cav
     return out
 
 

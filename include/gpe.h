@@ -245,19 +245,23 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
  * (exact in real time) -- GPE_ADJ_RECONSTRUCT -- or from stored states every
  * ~sqrt(nsteps) steps -- GPE_ADJ_CHECKPOINT; GPE_ADJ_AUTO reconstructs and falls
  * back to checkpoints if the rebuilt psi(0) drifts from the input by more than
- * drift_tol (relative L2).
+ * drift_tol (relative L2).  GPE_ADJ_STORE keeps every kick's output state from the
+ * forward sweep (nsteps * nx * ny * 8 bytes per member, kept by the batch for later
+ * calls, GPE_ERR_NOMEM if the device cannot hold it), so the reverse sweep transforms
+ * the adjoint alone: the fastest mode where HBM allows it.
  * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each; target may
  * be null for the energy loss and is ignored there); knots: host, nb * nknots values (they replace the
  * members' knots of the controlled lattice); loss: host, nb values; grad: host,
  * nb * nknots values;
  * psi_final (nullable): host array of nb device pointers receiving psi(T).
- * info (nullable): host, 4 doubles {mode used (1 reconstruct, 2 checkpoint),
+ * info (nullable): host, 4 doubles {mode used (1 reconstruct, 2 checkpoint, 3 store),
  * reconstruction drift, peak scratch bytes, number of forward steps run}. */
 #define GPE_LOSS_FIDELITY 0
 #define GPE_LOSS_ENERGY 1
 #define GPE_ADJ_AUTO 0
 #define GPE_ADJ_RECONSTRUCT 1
 #define GPE_ADJ_CHECKPOINT 2
+#define GPE_ADJ_STORE 3
 #define GPE_CONTROL_X_LATTICE 0
 #define GPE_CONTROL_PUMP 1
 int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *target, int64_t nsteps,

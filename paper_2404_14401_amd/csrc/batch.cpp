@@ -46,6 +46,8 @@ struct AdjWork {
     bool any_adia = false;                // some member has the adiabatic field
     std::vector<float2 *> ckpt;  // [slot * nb + member]
     int ckpt_slots = 0;
+    std::vector<float2 *> traj;  // per member: post-kick states [kick][ny][nx] (stored mode)
+    int64_t traj_steps = 0;
     AdjInst *d_adj = nullptr;
     InstDesc *d_fwd = nullptr;
     const float2 **d_pa = nullptr, **d_pb = nullptr;
@@ -80,6 +82,13 @@ static int balloc(gpe_batch *b, void **p, size_t bytes)
     if (e != hipSuccess) return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     b->allocs.push_back(*p);
     return GPE_OK;
+}
+
+static void bfree(gpe_batch *b, void *p)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    b->allocs.erase(std::remove(b->allocs.begin(), b->allocs.end(), p), b->allocs.end());
 }
 
 static Shape group_shape(const BGroup &g)
@@ -501,7 +510,8 @@ static void hat(const gpe_schedule &s, double t, int *i0, double *w0, double *w1
     *w0 = 1.0 - *w1;
 }
 
-static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t nsteps, int slots)
+static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t nsteps, int slots,
+                     int64_t traj_steps = 0)
 {
     const size_t npts = (size_t)nx * ny;
     if (w->nx != nx || w->ny != ny || w->nb != nb) {
@@ -550,6 +560,25 @@ static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t n
         }
         w->ckpt_slots++;
     }
+    if (traj_steps > w->traj_steps) {
+        // one buffer per member, replaced (not kept alongside) when a longer run needs more
+        for (float2 *p : w->traj) bfree(b, p);
+        w->bytes -= std::min(w->bytes, (size_t)w->traj_steps * nb * sizeof(float2) * npts);
+        w->traj.assign(nb, nullptr);
+        w->traj_steps = 0;
+        for (int i = 0; i < nb; ++i) {
+            int rc;
+            if ((rc = balloc(b, (void **)&w->traj[i], sizeof(float2) * npts * (size_t)traj_steps))) {
+                for (float2 *&p : w->traj) {
+                    bfree(b, p);
+                    p = nullptr;
+                }
+                return rc;
+            }
+        }
+        w->traj_steps = traj_steps;
+        w->bytes += (size_t)traj_steps * nb * sizeof(float2) * npts;
+    }
     return GPE_OK;
 }
 
@@ -573,13 +602,15 @@ static int pair_sums(gpe_batch *b, AdjWork *w, const std::vector<const float2 *>
 
 // Forward real-time steps [n0, n1) of every member on the adjoint workspace (batched
 // multi-pass kernels, time base st->t0 = t0 + n0 dt).
-static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1)
+static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1,
+                       bool record = false)
 {
     const int nb = w->nb;
     LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0 + n0 * b->dt, b->work));
     BatchPassArgs ra{}, ca{};
     ra.inst = w->d_fwd;
     ra.adia = w->any_adia ? 1 : 0;
+    ra.traj = record ? 1 : 0;
     ra.blocks_per_inst = sh.row_blocks;
     ra.per_wg = sh.row_lines;
     ca.inst = w->d_fwd;
@@ -605,7 +636,9 @@ static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
 
 // Reverse sweep over steps [n0, n1) (from n1 down to n0): on entry psi holds psi_{n1}
 // and lam the adjoint at n1 (real space); on exit psi_{n0} (reconstructed) and lam_{n0}.
-static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1)
+// stored: the kick outputs come from the members' trajectories, psi stays psi_{n1}.
+static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1,
+                       bool stored = false)
 {
     const int nb = w->nb;
     LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0, b->work));
@@ -619,8 +652,9 @@ static int adj_reverse(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     ca.row_blocks = sh.row_blocks;
     const int rblocks = sh.row_blocks * nb, cblocks = sh.col_blocks * nb;
     ca.xcd_swizzle = (cblocks % 8 == 0 && cblocks >= 64) ? 1 : 0;
-    // rows need 2 arrays' worth of registers: at most 256 threads per work-group
-    const size_t rsh = adj_row_shmem(w->nx, sh.row_lines, 8), csh = adj_col_shmem(w->ny, sh.col_cols, 8);
+    ra.traj = ca.traj = stored ? 1 : 0;
+    const int arrays = stored ? 1 : 2;
+    const size_t rsh = adj_row_shmem(w->nx, sh.row_lines, 8, arrays), csh = adj_col_shmem(w->ny, sh.col_cols, 8, arrays);
     ra.kick = (int)n1;
     if (w->any_adia)
         LAUNCH_OK(launch_row_adj(w->nx, ADJ_PROBE_FIRST, ra, rblocks, sh.row_threads, rsh, b->work));
@@ -651,7 +685,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     if (loss_kind != GPE_LOSS_FIDELITY && loss_kind != GPE_LOSS_ENERGY) return fail(GPE_ERR_INVALID, "bad loss kind");
     const bool energy = loss_kind == GPE_LOSS_ENERGY;
     if (!energy && !target) return fail(GPE_ERR_INVALID, "fidelity loss needs target states");
-    if (mode < GPE_ADJ_AUTO || mode > GPE_ADJ_CHECKPOINT) return fail(GPE_ERR_INVALID, "bad adjoint mode");
+    if (mode < GPE_ADJ_AUTO || mode > GPE_ADJ_STORE) return fail(GPE_ERR_INVALID, "bad adjoint mode");
+    const bool store = mode == GPE_ADJ_STORE;
     if (nsteps > (1 << 28)) return fail(GPE_ERR_INVALID, "nsteps too large");
     const int nb = b->n;
     const int nx = b->plans[0]->nx, ny = b->plans[0]->ny;
@@ -672,15 +707,16 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, nx / std::max(1, 512 / (ny / 8)));
     if (sh.col_threads > 512) return fail(GPE_ERR_UNSUPPORTED, "column shape");
     // the adjoint column pass holds two exchange areas: narrow the tiles until they fit LDS
-    for (int tiles = nx / sh.col_cols * 2; adj_col_shmem(ny, sh.col_cols, 8) > 158 * 1024 && sh.col_cols > 1;
+    for (int tiles = nx / sh.col_cols * 2; adj_col_shmem(ny, sh.col_cols, 8, 2) > 158 * 1024 && sh.col_cols > 1;
          tiles *= 2)
         sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, tiles);
-    if (adj_col_shmem(ny, sh.col_cols, 8) > 158 * 1024 || adj_row_shmem(nx, sh.row_lines, 8) > 158 * 1024)
+    if (adj_col_shmem(ny, sh.col_cols, 8, 2) > 158 * 1024 || adj_row_shmem(nx, sh.row_lines, 8, 2) > 158 * 1024)
         return fail(GPE_ERR_UNSUPPORTED, "adjoint passes exceed the LDS of a work-group");
     AdjWork *w = adj_work(b);
     const int64_t seg = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
     const int64_t nseg = (nsteps + seg - 1) / seg;
-    int rc = adj_alloc(b, w, nx, ny, nb, nsteps, mode == GPE_ADJ_RECONSTRUCT ? 0 : (int)nseg);
+    int rc = adj_alloc(b, w, nx, ny, nb, nsteps, (mode == GPE_ADJ_AUTO || mode == GPE_ADJ_CHECKPOINT) ? (int)nseg : 0,
+                       store ? nsteps : 0);
     if (rc) return rc;
     const size_t npts = (size_t)nx * ny;
     HIP_OK(hipEventRecord(b->ev_in, b->user));
@@ -695,9 +731,10 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     for (int i = 0; i < nb; ++i) {
         gpe_plan *p = b->plans[i];
         const bool adia = p->pot.cavity == GPE_CAVITY_ADIABATIC;
-        fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st, adia ? w->probe[i] : nullptr};
+        float2 *traj = store ? w->traj[i] : nullptr;
+        fwd[i] = InstDesc{w->psi[i], p->grid, p->pot, p->st, adia ? w->probe[i] : nullptr, traj};
         adj[i] = AdjInst{w->psi[i], w->lam[i], p->grid, p->pot, p->st, w->partials[i], w->kick_grad[i], pump ? 1 : 0,
-                         adia ? w->aprobe[i] : nullptr};
+                         adia ? w->aprobe[i] : nullptr, traj};
         if (adia) w->any_adia = true;
     }
     HIP_OK(hipMemcpyAsync(w->d_fwd, fwd.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice, b->work));
@@ -717,7 +754,7 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
                                           hipMemcpyDeviceToDevice, b->work));
                 if ((r = adj_forward(b, w, sh, t0, s * seg, std::min(nsteps, (s + 1) * seg)))) return r;
             }
-        } else if ((r = adj_forward(b, w, sh, t0, 0, nsteps))) {
+        } else if ((r = adj_forward(b, w, sh, t0, 0, nsteps, store))) {
             return r;
         }
         if (psi_final)
@@ -763,9 +800,11 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
                                               hipMemcpyDeviceToDevice, b->work));
                 if ((r = adj_reverse(b, w, sh, t0, s * seg, e))) return r;
             }
-        } else if ((r = adj_reverse(b, w, sh, t0, 0, nsteps))) {
+        } else if ((r = adj_reverse(b, w, sh, t0, 0, nsteps, store))) {
             return r;
         }
+        *drift = 0;
+        if (store) return GPE_OK;  // the state was read back, not rebuilt
         // drift of the state rebuilt at t0 against the input
         for (int i = 0; i < nb; ++i) {
             pa[i] = w->psi[i];
@@ -808,7 +847,7 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         }
     }
     if (info) {
-        info[0] = ckpt ? 2 : 1;
+        info[0] = store ? 3 : ckpt ? 2 : 1;
         info[1] = drift;
         info[2] = (double)w->bytes;
         info[3] = (double)fwd_steps;

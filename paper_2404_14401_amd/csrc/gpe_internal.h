@@ -130,6 +130,8 @@ struct InstDesc {
     PotDev pot;
     DevState *st;
     double *probe;  // adiabatic field: [row work-groups][NPART] partials of the probe pass (else null)
+    float2 *traj;   // adjoint forward sweep: post-kick real-space state of every kick but the
+                    // last, [kick][ny][nx] (else null)
 };
 
 // A batched row or column pass over all members of one grid size.
@@ -140,6 +142,7 @@ struct BatchPassArgs {
     int n;                // step index within the call
     int xcd_swizzle;
     int adia;             // some member has the adiabatic field (kick kernels read probe partials)
+    int traj;             // entry and merged kicks record their output in InstDesc::traj
 };
 
 // One member of an adjoint sweep (device memory): the state being reconstructed
@@ -155,6 +158,7 @@ struct AdjInst {
     int control_axis;   // controlled lattice: 0 x, 1 y (the pump)
     double *aprobe;     // adiabatic field: [row work-groups][NPART] sums of rho, rho cos kx cos ky,
                         // rho cos^2 kx, s cos^2 kx, s cos kx cos ky over (psi', G') (else null)
+    const float2 *traj; // stored post-kick states [kick][ny][nx] (the passes then carry lam alone)
 };
 
 enum AdjRowMode : int {
@@ -173,6 +177,7 @@ struct AdjPassArgs {
     int xcd_swizzle;
     int tail_kick;      // column pass: add the previous row pass's sums to kick_grad[tail_kick] (-1: none)
     int row_blocks;     // number of row work-groups per member (partials to reduce)
+    int traj;           // 1: states come from AdjInst::traj, the passes transform lam alone
 };
 
 // Whole grid resident in one work-group's LDS (small grids).

@@ -69,16 +69,17 @@ int kernel_radix() { return kRadix; }
 size_t xchg_bytes() { return sizeof(XchgT); }
 // extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
 size_t staged_table_bytes(int n) { return GPE_TW_LDS ? (size_t)n * (sizeof(double2) + sizeof(float4)) : 0; }
-// LDS of the adjoint passes: two exchange areas (state and adjoint) plus the tables
-size_t adj_row_shmem(int n, int lines, int r)
+// LDS of the adjoint passes: exchange areas for `arrays` lines (state and adjoint, or the
+// adjoint alone) plus the tables
+size_t adj_row_shmem(int n, int lines, int r, int arrays)
 {
     const size_t words = (size_t)n + (n >> ilog2(r));
-    return align16(2 * lines * words * sizeof(XchgT)) + (size_t)n * (sizeof(double2) + sizeof(float4));
+    return align16(arrays * lines * words * sizeof(XchgT)) + (size_t)n * (sizeof(double2) + sizeof(float4));
 }
-size_t adj_col_shmem(int n, int w, int r)
+size_t adj_col_shmem(int n, int w, int r, int arrays)
 {
     const size_t words = (size_t)n * w + (n >> ilog2(r)) + w;
-    return align16(2 * words * sizeof(XchgT)) + (size_t)n * 2 * sizeof(double2);
+    return align16(arrays * words * sizeof(XchgT)) + (size_t)n * 2 * sizeof(double2);
 }
 
 // --------------------------------------------------------------------- row pass
@@ -88,7 +89,8 @@ template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
                                          const PotDev &pot, DevState *st, double *partials, int n, int lb,
                                          int lines, XchgT *smem, double *red, double t_shift = 0.0,
-                                         const double *probe = nullptr, int nprobe = 0, bool theta_only = false)
+                                         const double *probe = nullptr, int nprobe = 0, bool theta_only = false,
+                                         float2 *traj = nullptr)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -224,6 +226,12 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
             }
         }
     }
+    if constexpr (!IMAG && (MODE == ROW_ENTRY || MODE == ROW_MID)) {
+        // the adjoint's stored trajectory: this kick's output in real space
+        if (traj)
+#pragma unroll
+            for (int m = 0; m < R; ++m) store_c64(traj + (size_t)row * N + t + m * T, v[m]);
+    }
     if (partials) {
         // the C overlap is only needed by the adiabatic field, and the field ODE alone
         // needs only Theta: skip the other sums' shuffles
@@ -257,23 +265,29 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
 // A member with the adiabatic field carries probe partials: the probe modes write them,
 // the kick modes turn them into alpha; other members skip the probe modes.
-// (ADIA is a template flag so that groups without the field keep the probe-free kernel.)
-template <int N, int R, int MODE, bool ADIA>
+// (ADIA is a template flag so that groups without the field keep the probe-free kernel;
+// TRAJ likewise for the adjoint's forward sweep that records every kick's output.)
+template <int N, int R, int MODE, bool ADIA, bool TRAJ>
 __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
 {
     extern __shared__ XchgT smem[];
     __shared__ double red[8 * NPART];
     const InstDesc &I = a.inst[blockIdx.x / a.blocks_per_inst];
     const int lb = blockIdx.x % a.blocks_per_inst;
+    // kick k's output goes to trajectory slot k (entry kick k = 0, merged kick of step n: n + 1)
+    float2 *tj = nullptr;
+    if constexpr (TRAJ && (MODE == ROW_ENTRY || MODE == ROW_MID))
+        tj = I.traj + (size_t)(MODE == ROW_ENTRY ? 0 : a.n + 1) * ((size_t)I.grid.nx * I.grid.ny);
     if constexpr (MODE == ROW_PROBE_REAL || MODE == ROW_PROBE_MID) {
         if (!I.probe) return;
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, I.probe + lb * NPART, a.n, lb, a.per_wg, smem,
                                     red);
     } else if constexpr (ADIA) {
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
-                                    I.probe, a.blocks_per_inst);
+                                    I.probe, a.blocks_per_inst, false, tj);
     } else {
-        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red);
+        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
+                                    nullptr, 0, false, tj);
     }
 }
 
@@ -969,18 +983,38 @@ hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s)
 template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPassArgs &a, int blocks, int threads,
                                                         size_t shmem, hipStream_t s)
 {
-#define GPE_ROWB(M, A)                                                                             \
+#define GPE_ROWB_T(M, A, TJ)                                                                       \
     do {                                                                                           \
         static bool attr_ = false;                                                                 \
         if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M, A>,              \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M, A, TJ>,          \
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
             if (e_ != hipSuccess) return e_;                                                       \
             attr_ = true;                                                                          \
         }                                                                                          \
-        hipLaunchKernelGGL((row_pass_b<N, R, M, A>), dim3(blocks), dim3(threads), shmem, s, a);    \
+        hipLaunchKernelGGL((row_pass_b<N, R, M, A, TJ>), dim3(blocks), dim3(threads), shmem, s, a); \
     } while (0)
-    if (a.adia) {
+#define GPE_ROWB(M, A) GPE_ROWB_T(M, A, false)
+    if (a.traj) {
+        // the adjoint's recording forward sweep (radix 8 only): entry and merged kicks
+        if constexpr (R == 8) {
+            if (a.adia) {
+                if (mode == ROW_ENTRY) GPE_ROWB_T(ROW_ENTRY, true, true);
+                else if (mode == ROW_MID) GPE_ROWB_T(ROW_MID, true, true);
+                else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
+                else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL, true);
+                else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID, true);
+                else return hipErrorInvalidValue;
+            } else {
+                if (mode == ROW_ENTRY) GPE_ROWB_T(ROW_ENTRY, false, true);
+                else if (mode == ROW_MID) GPE_ROWB_T(ROW_MID, false, true);
+                else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, false);
+                else return hipErrorInvalidValue;
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (a.adia) {
         if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, true);
         else if (mode == ROW_MID) GPE_ROWB(ROW_MID, true);
         else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
@@ -994,6 +1028,7 @@ template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPas
         else return hipErrorInvalidValue;
     }
 #undef GPE_ROWB
+#undef GPE_ROWB_T
     return hipGetLastError();
 }
 
@@ -1116,20 +1151,25 @@ hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStr
 //   s = Im(conj(G') psi'),  G = G' e^{+i theta} + 2 g tau s psi,  dL/dV(x) = tau s(x).
 // The kinetic propagation U = IFFT2 M FFT2 is unitary, so both the state and G go
 // back through U^H = IFFT2 conj(M) FFT2: the same passes with the conjugate factor.
-template <int N, int R, int MODE>
+// TRAJ: the kick outputs psi' were stored by the forward sweep (slot k for kick k, the
+// last kick's output is psi(T) itself), so the passes transform lam alone.
+template <int N, int R, int MODE, bool TRAJ>
 __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines, int kick, XchgT *smem, double *red,
                                              int nprobe)
 {
     using C = double2;
     constexpr int T = N / R;
+    constexpr bool FIRST = MODE == ADJ_FIRST || MODE == ADJ_PROBE_FIRST;
     using View = LinePad<XchgT, ilog2(R)>;
     const GridDev &gd = I.grid;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int row = lb * lines + line;
-    // exchange lines: [state lines][adjoint lines], then the staged tables
+    // exchange lines: [state lines][adjoint lines] (TRAJ: adjoint lines only), then the
+    // staged tables
+    constexpr int AREAS = TRAJ ? 1 : 2;
     View la{smem + line * View::words(N)};
-    View lb2{smem + (lines + line) * View::words(N)};
-    double2 *s_tw = (double2 *)((char *)smem + align16(2 * lines * View::words(N) * sizeof(XchgT)));
+    View lb2{smem + ((AREAS - 1) * lines + line) * View::words(N)};
+    double2 *s_tw = (double2 *)((char *)smem + align16(AREAS * lines * View::words(N) * sizeof(XchgT)));
     float4 *s_tx = (float4 *)(s_tw + N);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         s_tw[i] = gd.tw_x[i];
@@ -1137,15 +1177,27 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     }
     float2 *pp = I.psi + (size_t)row * N;
     float2 *pl = I.lam + (size_t)row * N;
+    const float2 *ps = pp;
+    if constexpr (TRAJ && !FIRST) ps = I.traj + (size_t)kick * ((size_t)N * gd.ny) + (size_t)row * N;
     C v[R], w[R];
+    float2 vs[R];  // TRAJ: the stored state stays complex64 through lam's transform
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        float2 a = pp[t + m * T], b = pl[t + m * T];
-        v[m] = {(double)a.x, (double)a.y};
+        float2 a = ps[t + m * T], b = pl[t + m * T];
+        if constexpr (TRAJ) vs[m] = a;
+        else v[m] = {(double)a.x, (double)a.y};
         w[m] = {(double)b.x, (double)b.y};
     }
     __syncthreads();
-    if constexpr (MODE != ADJ_FIRST && MODE != ADJ_PROBE_FIRST) fft_line2<N, R, true>(v, w, la, lb2, t, s_tw);
+    if constexpr (!FIRST) {
+        if constexpr (TRAJ)
+            fft_line<N, R, true>(w, lb2, t, s_tw);
+        else
+            fft_line2<N, R, true>(v, w, la, lb2, t, s_tw);
+    }
+    if constexpr (TRAJ)
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = {(double)vs[m].x, (double)vs[m].y};
     const double cyc = I.pot.ty[row].z;  // cos(kc y) of this row
     if constexpr (MODE == ADJ_PROBE_FIRST || MODE == ADJ_PROBE_MID) {
         // sums for the adiabatic field and its adjoint: rho, rho cxcy, rho cc2, s cc2, s cxcy
@@ -1237,15 +1289,20 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     if (lb == 0 && threadIdx.x == 0) part[0] += tau * extra;  // global pump term, once per kick
     block_sum<1>(part, red);
     if (threadIdx.x == 0) I.partials[lb] = part[0];
-    if constexpr (MODE != ADJ_LAST) fft_line2<N, R, false>(v, w, la, lb2, t, s_tw);
+    if constexpr (MODE != ADJ_LAST) {
+        if constexpr (TRAJ)
+            fft_line<N, R, false>(w, lb2, t, s_tw);
+        else
+            fft_line2<N, R, false>(v, w, la, lb2, t, s_tw);
+    }
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        store_c64(pp + t + m * T, v[m]);
+        if constexpr (!TRAJ) store_c64(pp + t + m * T, v[m]);
         store_c64(pl + t + m * T, w[m]);
     }
 }
 
-template <int N, int R, int MODE>
+template <int N, int R, int MODE, bool TRAJ>
 __global__ void __launch_bounds__(512) row_adj_b(AdjPassArgs a)
 {
     extern __shared__ XchgT smem[];
@@ -1253,7 +1310,8 @@ __global__ void __launch_bounds__(512) row_adj_b(AdjPassArgs a)
     const AdjInst &I = a.inst[blockIdx.x / a.blocks_per_inst];
     if constexpr (MODE == ADJ_PROBE_FIRST || MODE == ADJ_PROBE_MID)
         if (!I.aprobe) return;
-    row_adj_body<N, R, MODE>(I, blockIdx.x % a.blocks_per_inst, a.per_wg, a.kick, smem, red, a.blocks_per_inst);
+    row_adj_body<N, R, MODE, TRAJ>(I, blockIdx.x % a.blocks_per_inst, a.per_wg, a.kick, smem, red,
+                                   a.blocks_per_inst);
 }
 
 // Sum one member's row partials (fixed order) into kick_grad[k]; one work-group.
@@ -1265,7 +1323,7 @@ __device__ __forceinline__ void adj_tail(const AdjInst &I, int nrow, int k, doub
     if (threadIdx.x == 0) I.kick_grad[k] += s[0];
 }
 
-template <int N, int R>
+template <int N, int R, bool TRAJ>
 __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
 {
     using C = double2;
@@ -1283,9 +1341,10 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
     const int col = lt * w + c;
     const int nx = gd.nx;
     const size_t words = View::words(N, w);
+    constexpr int AREAS = TRAJ ? 1 : 2;  // TRAJ: lam alone
     View la{smem + c, w};
-    View lb{smem + words + c, w};
-    double2 *s_tw = (double2 *)((char *)smem + align16(2 * words * sizeof(XchgT)));
+    View lb{smem + (AREAS - 1) * words + c, w};
+    double2 *s_tw = (double2 *)((char *)smem + align16(AREAS * words * sizeof(XchgT)));
     double2 *s_ky = s_tw + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         s_tw[i] = gd.tw_y[i];
@@ -1294,23 +1353,32 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
     C v[R], u[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        float2 f = I.psi[(size_t)(t + m * T) * nx + col], h = I.lam[(size_t)(t + m * T) * nx + col];
-        v[m] = {(double)f.x, (double)f.y};
+        if constexpr (!TRAJ) {
+            float2 f = I.psi[(size_t)(t + m * T) * nx + col];
+            v[m] = {(double)f.x, (double)f.y};
+        }
+        float2 h = I.lam[(size_t)(t + m * T) * nx + col];
         u[m] = {(double)h.x, (double)h.y};
     }
     __syncthreads();
-    fft_line2<N, R, false>(v, u, la, lb, t, s_tw);
+    if constexpr (TRAJ)
+        fft_line<N, R, false>(u, lb, t, s_tw);
+    else
+        fft_line2<N, R, false>(v, u, la, lb, t, s_tw);
     const C kx = gd.kin_x[col];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const C f = cmul(kx, s_ky[t + m * T]);
-        v[m] = cmulc(v[m], f);
+        if constexpr (!TRAJ) v[m] = cmulc(v[m], f);
         u[m] = cmulc(u[m], f);
     }
-    fft_line2<N, R, true>(v, u, la, lb, t, s_tw);
+    if constexpr (TRAJ)
+        fft_line<N, R, true>(u, lb, t, s_tw);
+    else
+        fft_line2<N, R, true>(v, u, la, lb, t, s_tw);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        store_c64(I.psi + (size_t)(t + m * T) * nx + col, v[m]);
+        if constexpr (!TRAJ) store_c64(I.psi + (size_t)(t + m * T) * nx + col, v[m]);
         store_c64(I.lam + (size_t)(t + m * T) * nx + col, u[m]);
     }
 }
@@ -1358,19 +1426,19 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(float2 *const *dst, co
     }
 }
 
-template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPassArgs &a, int blocks, int threads,
-                                                          size_t shmem, hipStream_t s)
+template <int N, int R, bool TRAJ> static hipError_t rowadj_mode(int mode, const AdjPassArgs &a, int blocks,
+                                                                 int threads, size_t shmem, hipStream_t s)
 {
 #define GPE_RADJ(M)                                                                                \
     do {                                                                                           \
         static bool attr_ = false;                                                                 \
         if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_adj_b<N, R, M>,                  \
+            hipError_t e_ = hipFuncSetAttribute((const void *)row_adj_b<N, R, M, TRAJ>,            \
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
             if (e_ != hipSuccess) return e_;                                                       \
             attr_ = true;                                                                          \
         }                                                                                          \
-        hipLaunchKernelGGL((row_adj_b<N, R, M>), dim3(blocks), dim3(threads), shmem, s, a);        \
+        hipLaunchKernelGGL((row_adj_b<N, R, M, TRAJ>), dim3(blocks), dim3(threads), shmem, s, a);  \
     } while (0)
     if (mode == ADJ_FIRST) GPE_RADJ(ADJ_FIRST);
     else if (mode == ADJ_MID) GPE_RADJ(ADJ_MID);
@@ -1382,18 +1450,32 @@ template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPas
     return hipGetLastError();
 }
 
-template <int N, int R> static hipError_t coladj_dispatch(const AdjPassArgs &a, int blocks, int threads, size_t shmem,
-                                                          hipStream_t s)
+template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPassArgs &a, int blocks, int threads,
+                                                          size_t shmem, hipStream_t s)
+{
+    return a.traj ? rowadj_mode<N, R, true>(mode, a, blocks, threads, shmem, s)
+                  : rowadj_mode<N, R, false>(mode, a, blocks, threads, shmem, s);
+}
+
+template <int N, int R, bool TRAJ> static hipError_t coladj_launch(const AdjPassArgs &a, int blocks, int threads,
+                                                                   size_t shmem, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)col_adj_b<N, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024 - 1024);
+        hipError_t e = hipFuncSetAttribute((const void *)col_adj_b<N, R, TRAJ>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((col_adj_b<N, R>), dim3(blocks), dim3(threads), shmem, s, a);
+    hipLaunchKernelGGL((col_adj_b<N, R, TRAJ>), dim3(blocks), dim3(threads), shmem, s, a);
     return hipGetLastError();
+}
+
+template <int N, int R> static hipError_t coladj_dispatch(const AdjPassArgs &a, int blocks, int threads, size_t shmem,
+                                                          hipStream_t s)
+{
+    return a.traj ? coladj_launch<N, R, true>(a, blocks, threads, shmem, s)
+                  : coladj_launch<N, R, false>(a, blocks, threads, shmem, s);
 }
 
 #define GPE_ADJ_SIZES(F, ...)                                                                      \

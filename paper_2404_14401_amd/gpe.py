@@ -24,7 +24,7 @@ NOBS = 6
 CONTROL = {"x": 0, "pump": 1}
 SCHED = {"const": 0, "ramp": 1, "knots": 2, "pulse": 3}
 LOSS = {"fidelity": 0, "energy": 1}
-ADJ_MODE = {"auto": 0, "reconstruct": 1, "checkpoint": 2}
+ADJ_MODE = {"auto": 0, "reconstruct": 1, "checkpoint": 2, "store": 3}
 
 # Every entry point the header declares (checked by the CPU tests against include/gpe.h).
 EXPORTS = (
@@ -331,5 +331,5 @@ def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, m
     check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), tg, int(nsteps), float(t0),
                             k.ctypes.data, m, CONTROL[control], LOSS[loss], ADJ_MODE[mode], float(drift_tol),
                             out.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
-    return out, grad, {"mode": {1: "reconstruct", 2: "checkpoint"}[int(info[0])], "drift": info[1],
+    return out, grad, {"mode": {1: "reconstruct", 2: "checkpoint", 3: "store"}[int(info[0])], "drift": info[1],
                         "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}

@@ -23,7 +23,7 @@ def states(s, b):
     return psi0, tgt
 
 
-@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint", "store"])
 def test_adjoint_matches_oracle(mode):
     torch_cuda()
     from paper_2404_14401_amd import gpe
@@ -101,7 +101,7 @@ def pump_setup(b, n=64, nknots=8, nsteps=60, dt=0.005):
                    sx=W.Schedule("const", 3.0), sy=W.Schedule("knots", t0=0.0, t1=nsteps * dt, knots=knots))
 
 
-@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint", "store"])
 def test_pump_control_adjoint_matches_oracle_and_autograd(mode):
     torch = torch_cuda()
     from paper_2404_14401_amd import autograd as A
@@ -142,7 +142,7 @@ def cavity_control_setup(b, control, n=64, nknots=6, nsteps=60, dt=0.005):
 
 
 @pytest.mark.parametrize("control", ["pump", "x"])
-@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint", "store"])
 def test_adjoint_through_the_adiabatic_cavity_matches_oracle(control, mode):
     torch = torch_cuda()
     from paper_2404_14401_amd import gpe
@@ -172,7 +172,7 @@ def test_adjoint_through_the_adiabatic_cavity_matches_oracle(control, mode):
 
 
 @pytest.mark.parametrize("control", ["x", "pump"])
-@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint"])
+@pytest.mark.parametrize("mode", ["reconstruct", "checkpoint", "store"])
 def test_energy_loss_adjoint_matches_oracle_and_finite_differences(control, mode):
     """L = E_kin + E_pot + E_int of psi(T): the terminal adjoint 2 dA H psi(T) formed on
     the GPU (spectral kinetic term), plus the loss's own dependence on the final depth."""
@@ -221,3 +221,25 @@ def test_energy_loss_with_the_cavity_is_rejected():
     with pytest.raises(gpe.GpeError) as e:
         gpe.adjoint(batch, [to_dev(p0)], None, 10, s.sx.knots[None, :])
     assert e.value.code == gpe.ERR_INVALID
+
+
+def test_stored_trajectory_is_regrown_and_reused_across_calls():
+    """The stored mode keeps its trajectory in the batch: a longer run replaces it, a
+    shorter one reuses it; each call equals reconstruction and reports the memory."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nb = 2
+    setups = [control_setup(b, nsteps=50) for b in range(nb)]
+    p0, tg = zip(*[states(s, b) for b, s in enumerate(setups)])
+    d0, dtg = [to_dev(p) for p in p0], [to_dev(t) for t in tg]
+    knots = np.stack([s.sx.knots for s in setups])
+    bs, br = gpe.Batch(setups), gpe.Batch(setups)
+    npts = setups[0].nx * setups[0].ny
+    for n in (20, 50, 30):
+        ls, gs, info = gpe.adjoint(bs, d0, dtg, n, knots, mode="store")
+        lr, gr, _ = gpe.adjoint(br, d0, dtg, n, knots, mode="reconstruct")
+        assert info["mode"] == "store" and info["forward_steps"] == n
+        assert info["workspace_bytes"] >= max(n, 50 if n != 20 else 20) * nb * npts * 8
+        assert np.abs(ls - lr).max() < 1e-6
+        assert np.linalg.norm(gs - gr) / np.linalg.norm(gr) < 1e-4
