@@ -229,6 +229,56 @@ def _timed(fn) -> float:
     return ev0.elapsed_time(ev1) / 1e3
 
 
+def bench_library_fft(steps: int, us_per_step: float):
+    """Side comparison, not the product path: the cavity workload's split step at 1024^2
+    written with torch's FFT (hipFFT on ROCm) and elementwise complex64 ops -- V/2 kick,
+    fft2, kinetic factor, ifft2, V/2 kick and the per-step overlap sum Theta, with the
+    field held at zero.  Also the fft2 + ifft2 pair alone, the library route's floor."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import workloads as W
+
+    s = W.cavity_1024(0)
+    dev = "cuda"
+    y, x = np.meshgrid(s.ys(), s.xs(), indexing="ij")
+    v = (0.5 * s.wx ** 2 * (x - s.x0) ** 2 + 0.5 * s.wy ** 2 * (y - s.y0) ** 2
+         + s.sy.v0 * np.cos(s.ky_lat * y) ** 2)
+    V = torch.from_numpy(v.astype(np.float32)).to(dev)
+    cxcy = torch.from_numpy((np.cos(s.kc * x) * np.cos(s.kc * y)).astype(np.float32)).to(dev)
+    kx = 2 * np.pi * np.fft.fftfreq(s.nx, d=s.lx / s.nx)
+    ky = 2 * np.pi * np.fft.fftfreq(s.ny, d=s.ly / s.ny)
+    k2 = ky[:, None] ** 2 + kx[None, :] ** 2
+    K = torch.from_numpy(np.exp(-0.5j * k2 * s.dt).astype(np.complex64)).to(dev)
+    one = torch.ones_like(V)
+    psi = torch.from_numpy(W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx)))).to(dev)
+    h, g = 0.5 * s.dt, s.g
+
+    def step(p):
+        d = p.real * p.real + p.imag * p.imag
+        p = p * torch.polar(one, -(V + g * d) * h)
+        p = torch.fft.ifft2(torch.fft.fft2(p) * K)
+        d = p.real * p.real + p.imag * p.imag
+        p = p * torch.polar(one, -(V + g * d) * h)
+        return p, (d * cxcy).sum()
+
+    def run(n):
+        nonlocal psi
+        for _ in range(n):
+            psi, _ = step(psi)
+
+    run(20)
+    t = _timed(lambda: run(steps))
+    q = psi.clone()
+    tf = _timed(lambda: [torch.fft.ifft2(torch.fft.fft2(q)) for _ in range(steps)])
+    n = s.nx * s.ny
+    return {"what": "torch.fft (hipFFT) + elementwise complex64 split step, cavity workload at 1024^2, "
+                    "field held at 0, Theta summed each step",
+            "steps": steps, "us_per_step": 1e6 * t / steps, "value": n * steps / t, "unit": "grid-point-steps/s",
+            "fft2_ifft2_pair_us": 1e6 * tf / steps,
+            "this_library_speedup": (1e6 * t / steps) / us_per_step}
+
+
 def bench_widened(steps: int):
     """The paths beyond the main step: the Fourier-space ordering with momentum-order
     populations (Kapitza-Dirac, 512^2, and the 1024^2 grid without the cavity), the
@@ -314,6 +364,8 @@ def main() -> int:
     ap.add_argument("--adjoint-batch", type=int, default=16)
     ap.add_argument("--widened-steps", type=int, default=2000,
                     help="steps of the Fourier-space, adiabatic-field and sweep legs (0: skip)")
+    ap.add_argument("--side-steps", type=int, default=200,
+                    help="steps of the torch.fft side comparison (0: skip)")
     ap.add_argument("--tune-cache", default=os.path.join(HERE, "profiles", "tune_cache.txt"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (scale for rocprofv3 byte counters)")
@@ -419,6 +471,9 @@ def main() -> int:
     if args.adjoint_steps > 0:
         log("adjoint ...")
         out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
+    if args.side_steps > 0:
+        log("torch.fft side comparison ...")
+        out["library_fft_side"] = bench_library_fft(args.side_steps, 1e3 * out["ms_per_step"])
     if args.cpu_budget > 0:
         log(f"timing the oracle for ~{args.cpu_budget:.0f} s ...")
         out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget)
