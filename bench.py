@@ -10,7 +10,13 @@ The state is synthetic (a Thomas-Fermi-shaped start), already resident on the GP
 
 Prints ONE JSON line: grid-point-steps/s, the roofline of the dominant kernel (HIP
 events around sampled launches inside the timed region), and the FP64 oracle timed on
-a bounded sample on the host cores.
+a bounded sample on the host cores (all threads and one).  Further legs, each
+skippable: the 208-member batched sweep, the control adjoint (three ways of getting the
+forward states back), the widened rows (Fourier-space ordering, Kapitza-Dirac,
+adiabatic field, self-organisation sweep), the paper-shaped imaginary-time grid sweep
+64^2..4096^2, a 64 x 1024^2 batch whose state does not fit the Infinity Cache, the
+device-copy bandwidth, and the same step written with torch.fft (complex64 and
+complex128) as a side comparison.
 """
 from __future__ import annotations
 
@@ -53,28 +59,51 @@ def load_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(setup, psi0, budget_s: float):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(setup, psi0, budget_s: float, one_core_s: float):
+    """The oracle on all the host's threads (budget_s of work), and on one thread
+    (one_core_s of work, 0: skip)."""
     sys.path.insert(0, HERE)
     from oracle import oracle as O
     from tests.bridge import problem, state
 
-    cores = O.set_threads(0)
-    prob, st = problem(setup), state(setup)
-    t = time.perf_counter()
-    psi, _ = O.step_real(prob, st, psi0, 1)
-    one = time.perf_counter() - t
-    n = max(2, int(budget_s / max(one, 1e-6)))
-    t = time.perf_counter()
-    O.step_real(prob, st, psi, n)
-    dt = time.perf_counter() - t
-    return {
-        "value": setup.nx * setup.ny * n / dt,
+    def timed(threads, budget):
+        cores = O.set_threads(threads)
+        prob, st = problem(setup), state(setup)
+        t = time.perf_counter()
+        psi, _ = O.step_real(prob, st, psi0, 1)
+        one = time.perf_counter() - t
+        n = max(2, int(budget / max(one, 1e-6)))
+        t = time.perf_counter()
+        O.step_real(prob, st, psi, n)
+        return cores, n, setup.nx * setup.ny * n / (time.perf_counter() - t)
+
+    all_threads = O.set_threads(0)
+    cores, n, value = timed(all_threads, budget_s)
+    out = {
+        "value": value,
         "unit": "grid-point-steps/s",
         "cores": cores,
         "kind": "oracle",
         "sample": f"{n} real-time cavity steps at {setup.nx}x{setup.ny}, FP64 C oracle "
                   f"(own radix-2 FFT, OpenMP over rows/columns), after 1 untimed step",
+        "host": {"nproc": os.cpu_count(), "model": _cpu_model()},
     }
+    if one_core_s > 0:
+        c1, n1, v1 = timed(1, one_core_s)
+        out["one_core"] = {"value": v1, "cores": c1, "sample": f"{n1} steps, same workload"}
+        O.set_threads(all_threads)
+    return out
 
 
 def bench_batched(steps: int, tune_cache: str | None):
@@ -272,11 +301,83 @@ def bench_library_fft(steps: int, us_per_step: float):
     q = psi.clone()
     tf = _timed(lambda: [torch.fft.ifft2(torch.fft.fft2(q)) for _ in range(steps)])
     n = s.nx * s.ny
-    return {"what": "torch.fft (hipFFT) + elementwise complex64 split step, cavity workload at 1024^2, "
-                    "field held at 0, Theta summed each step",
-            "steps": steps, "us_per_step": 1e6 * t / steps, "value": n * steps / t, "unit": "grid-point-steps/s",
-            "fft2_ifft2_pair_us": 1e6 * tf / steps,
-            "this_library_speedup": (1e6 * t / steps) / us_per_step}
+    out = {"what": "torch.fft (hipFFT) + elementwise complex64 split step, cavity workload at 1024^2, "
+                   "field held at 0, Theta summed each step",
+           "steps": steps, "us_per_step": 1e6 * t / steps, "value": n * steps / t, "unit": "grid-point-steps/s",
+           "fft2_ifft2_pair_us": 1e6 * tf / steps,
+           "this_library_speedup": (1e6 * t / steps) / us_per_step}
+    # the same in complex128 (the paper's double-precision runs)
+    V, cxcy, K, one = V.double(), cxcy.double(), K.to(torch.complex128), one.double()
+    psi = psi.to(torch.complex128)
+    run(5)
+    t2 = _timed(lambda: run(steps))
+    out["complex128"] = {"us_per_step": 1e6 * t2 / steps, "value": n * steps / t2,
+                         "this_library_speedup": (1e6 * t2 / steps) / us_per_step}
+    return out
+
+
+def bench_grid_sweep(steps: int, runs: int):
+    """The paper's timing experiment reshaped for this library (Sec. 4.1): imaginary time
+    for a non-interacting condensate in a fixed harmonic trap, Nx = Ny = 2^n on
+    [-8, 8)^2, dtau = 1e-3, `steps` steps per run, the mean over `runs` runs; n from 6 to
+    12, the plan's largest grid.  Small grids take the LDS-resident path."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    rows = []
+    for n in range(6, 13):
+        s = W.imag_ground_64(0.0).with_(nx=1 << n, ny=1 << n)
+        p = gpe.Plan.from_setup(s)
+        psi = torch.from_numpy(W.to_c64(W.gaussian(s, 1.5))).to("cuda")
+        p.step_imag(psi, 10, 0.0)
+        ts = [_timed(lambda: p.step_imag(psi, steps, 0.0)) for _ in range(runs)]
+        t = float(np.mean(ts))
+        pts = s.nx * s.ny
+        rows.append({"n": n, "grid": pts, "ms_per_run": 1e3 * t, "ms_runs": [1e3 * x for x in ts],
+                     "value": pts * steps / t, "hbm_frac": 32 * pts * steps / t / (HBM_PEAK_GBS * 1e9)})
+        p.close()
+        del psi
+    return {"workload": f"imaginary time, g=0, harmonic trap w=1, [-8,8)^2, dtau=1e-3, {steps} steps per run, "
+                        f"mean of {runs} runs", "unit": "grid-point-steps/s", "rows": rows}
+
+
+def bench_out_of_cache(steps: int, members: int):
+    """A state larger than the 256 MB Infinity Cache: `members` real-time condensates at
+    1024^2 (trap + pump lattice of the cavity workload, field off) in one batch, so the
+    per-step traffic has to come from HBM."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    s = W.cavity_1024(0).with_(cavity=False)
+    setups = [s] * members
+    psi0 = torch.from_numpy(W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx)))).to("cuda")
+    psis = [psi0.clone() for _ in range(members)]
+    b = gpe.Batch(setups)
+    b.step(psis, 4, 0.0)
+    t = _timed(lambda: b.step(psis, steps, 4 * s.dt))
+    pts = members * s.nx * s.ny
+    b.close()
+    return {"workload": f"{members} x 1024^2 real-time condensates in one batch (state {8 * pts / 2**20:.0f} MiB), "
+                        "trap + pump lattice, field off", "steps": steps, "value": pts * steps / t,
+            "unit": "grid-point-steps/s", "us_per_step": 1e6 * t / steps,
+            "hbm_frac": 32 * pts * steps / t / (HBM_PEAK_GBS * 1e9)}
+
+
+def stream_copy_gbs(mib: int = 1024, reps: int = 20) -> float:
+    """Device-to-device copy bandwidth (read + write bytes) of a `mib` MiB buffer."""
+    import torch
+
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t = _timed(lambda: [b.copy_(a) for _ in range(reps)])
+    return 2 * a.numel() * reps / t / 1e9
 
 
 def bench_widened(steps: int):
@@ -366,6 +467,14 @@ def main() -> int:
                     help="steps of the Fourier-space, adiabatic-field and sweep legs (0: skip)")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="steps of the torch.fft side comparison (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=1000,
+                    help="steps per run of the 64^2..4096^2 imaginary-time grid sweep (0: skip)")
+    ap.add_argument("--sweep-runs", type=int, default=5)
+    ap.add_argument("--ooc-steps", type=int, default=20,
+                    help="steps of the 64 x 1024^2 out-of-cache batch (0: skip)")
+    ap.add_argument("--ooc-members", type=int, default=64)
+    ap.add_argument("--cpu-one-core", type=float, default=5.0,
+                    help="seconds of single-thread oracle work (0: skip)")
     ap.add_argument("--tune-cache", default=os.path.join(HERE, "profiles", "tune_cache.txt"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (scale for rocprofv3 byte counters)")
@@ -462,6 +571,9 @@ def main() -> int:
                           "frac": 2 * B_PASS * value / (HBM_PEAK_GBS * 1e9)},
         "wall_s": wall,
     }
+    copy = stream_copy_gbs()
+    out["stream_copy_gbs"] = copy
+    out["step_roofline"]["frac_of_stream_copy"] = 2 * B_PASS * value / (copy * 1e9)
     if args.batched_steps > 0:
         log("batched sweep ...")
         out["batched"] = bench_batched(args.batched_steps, args.tune_cache)
@@ -471,12 +583,18 @@ def main() -> int:
     if args.adjoint_steps > 0:
         log("adjoint ...")
         out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
+    if args.sweep_steps > 0:
+        log("grid sweep ...")
+        out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs)
+    if args.ooc_steps > 0:
+        log("out-of-cache batch ...")
+        out["out_of_cache"] = bench_out_of_cache(args.ooc_steps, args.ooc_members)
     if args.side_steps > 0:
         log("torch.fft side comparison ...")
         out["library_fft_side"] = bench_library_fft(args.side_steps, 1e3 * out["ms_per_step"])
     if args.cpu_budget > 0:
         log(f"timing the oracle for ~{args.cpu_budget:.0f} s ...")
-        out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget, args.cpu_one_core)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -127,7 +127,10 @@ typedef struct {
 #define GPE_NOBS 6
 
 /* Create a plan: allocates its tables and scratch once (the kernels allocate nothing
- * per step).  The potential starts as a unit isotropic trap with no lattice. */
+ * per step).  The potential starts as a unit isotropic trap with no lattice.  Grids
+ * up to 32^2 (64^2 in imaginary time) run every step of a call in one work-group with
+ * the grid in LDS, larger ones as two FFT passes per step over the chip (environment
+ * GPE_PATH=lds|multipass forces either where it can). */
 int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *desc);
 int gpe_plan_destroy(gpe_plan *plan);
 
@@ -205,8 +208,10 @@ const char *gpe_last_error(void);
 /* ------------------------------------------------------------------ batched
  * n independent condensates, each with its own plan description (sizes may differ;
  * dt must be equal) and potential, advanced together: every step is one launch per
- * FFT pass over all members (instances small enough to fit a work-group's LDS run
- * their whole step in one work-group).  psis: host array of n device pointers.
+ * FFT pass over all members of a size.  Members up to 64^2 -- and 128^2 ones beside
+ * larger sizes or at least 256 of them -- instead run all their steps in one
+ * work-group each, the grid kept in LDS (environment GPE_BATCH_PATH=lds|multipass
+ * forces either where it can).  psis: host array of n device pointers.
  * All members share the stream of desc[0]. */
 int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const gpe_potential_desc *pots);
 int gpe_batch_destroy(gpe_batch *b);

@@ -91,6 +91,29 @@ static void bfree(gpe_batch *b, void *p)
     b->allocs.erase(std::remove(b->allocs.begin(), b->allocs.end(), p), b->allocs.end());
 }
 
+// Which size groups keep each member whole in one work-group's LDS (one work-group per
+// member, all steps in one launch) instead of the batched multi-pass kernels.  Measured
+// on the MI355X: 64^2 and smaller always pay; 128^2 pays only beside multi-pass groups,
+// whose launches it overlaps on the side stream (208-member mixed sweep 8.0e10 vs 6.5e10
+// grid-point-steps/s), or with at least one member per CU, while a batch of fewer
+// 128^2 members alone runs faster multi-pass (80 adiabatic members: 2.7e10 vs 2.2e10).
+// GPE_BATCH_PATH=lds or multipass overrides the choice for every group that can.
+static void choose_group_paths(std::vector<BGroup> &groups)
+{
+    const char *force = getenv("GPE_BATCH_PATH");
+    const bool all_lds = force && !strcmp(force, "lds"), none = force && !strcmp(force, "multipass");
+    bool any_mp = false;
+    for (auto &g : groups) {
+        g.lds = lds_supported(g.nx, g.ny);
+        if (!g.lds) any_mp = true;
+    }
+    for (auto &g : groups) {
+        if (!g.lds) continue;
+        if (none) g.lds = false;
+        else if (!all_lds && g.nx * g.ny > 64 * 64) g.lds = any_mp || g.members.size() >= 256;
+    }
+}
+
 static Shape group_shape(const BGroup &g)
 {
     return make_shape_r(g.nx, g.ny, g.tune.radix, xchg_bytes(), g.tune.row_threads, g.tune.min_col_tiles);
@@ -222,12 +245,12 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
             BGroup g;
             g.nx = p->nx;
             g.ny = p->ny;
-            g.lds = lds_supported(p->nx, p->ny);
             b->groups.push_back(g);
             it = b->groups.end() - 1;
         }
         it->members.push_back(i);
     }
+    choose_group_paths(b->groups);
     std::vector<DevState *> states(n);
     for (int i = 0; i < n; ++i) states[i] = b->plans[i]->st;
     if ((rc = balloc(b, (void **)&b->d_states, sizeof(DevState *) * n))) return cleanup(rc);

@@ -38,3 +38,22 @@ def rel_l2_phase_aligned(a, ref) -> float:
     ov = np.vdot(a, ref)
     ph = ov / abs(ov) if abs(ov) > 0 else 1.0
     return float(np.linalg.norm(a * ph - ref) / np.linalg.norm(ref))
+
+
+def plain_plan_like(batch, setup):
+    """A plain plan on the same kernels as the batch group of `setup`'s grid size
+    (LDS-resident or multi-pass), so that member and plan agree to rounding."""
+    import os
+
+    from paper_2404_14401_amd import gpe
+
+    lds = {(g["nx"], g["ny"]): g["lds"] for g in batch.groups()}[(setup.nx, setup.ny)]
+    old = os.environ.get("GPE_PATH")
+    os.environ["GPE_PATH"] = "lds" if lds else "multipass"
+    try:
+        return gpe.Plan.from_setup(setup)
+    finally:
+        if old is None:
+            del os.environ["GPE_PATH"]
+        else:
+            os.environ["GPE_PATH"] = old

@@ -7,7 +7,7 @@ import pytest
 from oracle import oracle as O
 from paper_2404_14401_amd import workloads as W
 from tests.bridge import problem, state
-from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+from tests.gpu_util import plain_plan_like, rel_l2, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -114,21 +114,25 @@ def test_adiabatic_imaginary_time_ground_state(path, monkeypatch):
     assert np.abs(o[:, 0] - robs[:, 0]).max() < 3e-7
 
 
-def test_adiabatic_batched_sweep_matches_plain_solver_and_oracle():
+@pytest.mark.parametrize("path", ["auto", "lds", "multipass"])
+def test_adiabatic_batched_sweep_matches_plain_solver_and_oracle(path, monkeypatch):
     """A 3 x 4 (detuning x final depth) slice of the Fig. 5-shaped sweep in one batch:
-    every member equals the plain solver (same kernel arithmetic), two equal the oracle."""
+    every member equals the plain solver (same kernel arithmetic), two equal the oracle.
+    A batch of few 128^2 members alone runs multi-pass unless told otherwise."""
     torch_cuda()
     from paper_2404_14401_amd import gpe
 
+    if path != "auto":
+        monkeypatch.setenv("GPE_BATCH_PATH", path)
     setups = W.self_organisation_sweep(n_vp=4, detunings=(-5.0, -10.0, -40.0))
     psi0 = [W.self_organisation_start(s) for s in setups]
     b = gpe.Batch(setups)
-    assert all(g["lds"] for g in b.groups())
+    assert all(g["lds"] == (path == "lds") for g in b.groups())
     devs = [to_dev(p) for p in psi0]
     n = 300
     b.step(devs, n, 0.0)
     for i, s in enumerate(setups):
-        plain = gpe.Plan.from_setup(s)
+        plain = plain_plan_like(b, s)
         d = to_dev(psi0[i])
         plain.step_real(d, n, 0.0)
         assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-6, i
@@ -167,7 +171,7 @@ def test_adiabatic_batch_with_multipass_groups():
     n = 160   # more than one 50-step graph chunk
     b.step(devs, n, 0.0)
     for i, s in enumerate(setups):
-        plain = gpe.Plan.from_setup(s)
+        plain = plain_plan_like(b, s)
         d = to_dev(psi0[i])
         plain.step_real(d, n, 0.0)
         assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-5, i

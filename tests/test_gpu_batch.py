@@ -6,7 +6,7 @@ import pytest
 from oracle import oracle as O
 from paper_2404_14401_amd import workloads as W
 from tests.bridge import problem, state
-from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+from tests.gpu_util import plain_plan_like, rel_l2, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ def test_batch_members_match_plain_solver_and_oracle(nsteps):
     devs = [to_dev(p) for p in psi0]
     b.step(devs, nsteps, 0.0)
     for i, s in enumerate(setups):
-        plain = gpe.Plan.from_setup(s)
+        plain = plain_plan_like(b, s)
         d = to_dev(psi0[i])
         plain.step_real(d, nsteps, 0.0)
         out = to_host(devs[i])

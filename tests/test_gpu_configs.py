@@ -16,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_2404_14401_amd import workloads as W
 from tests.bridge import problem, state
-from tests.gpu_util import rel_l2, to_dev, to_host, torch_cuda
+from tests.gpu_util import plain_plan_like, rel_l2, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -109,7 +109,7 @@ def test_sweep_208_full_length_sampled_members():
     b.step(devs, n, 0.0)
     for i in (0, 127, 128, 191, 192, 207):
         s = setups[i]
-        plain = gpe.Plan.from_setup(s)
+        plain = plain_plan_like(b, s)
         d = to_dev(psi0[i])
         plain.step_real(d, n, 0.0)
         out = to_host(devs[i])
