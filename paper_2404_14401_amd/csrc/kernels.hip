@@ -1136,6 +1136,18 @@ hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStr
     return hipGetLastError();
 }
 
+// One plan's time base moves on by dt_total (after a replayed chunk of steps).
+__global__ void advance_one_kernel(DevState *st, double dt_total)
+{
+    if (threadIdx.x == 0) st->t0 += dt_total;
+}
+
+hipError_t launch_advance_one(DevState *st, double dt_total, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_one_kernel, dim3(1), dim3(64), 0, s, st, dt_total);
+    return hipGetLastError();
+}
+
 hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s)
 {
     hipLaunchKernelGGL(advance_t0_kernel, dim3(1), dim3(256), 0, s, st, n, dt_total);

@@ -110,6 +110,57 @@ static Sched to_sched(const gpe_schedule &s, const double *dev_knots)
     return d;
 }
 
+static void drop_plan_graphs(gpe_plan *p)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (p->graph[k]) (void)hipGraphExecDestroy(p->graph[k]);
+        if (p->graph_def[k]) (void)hipGraphDestroy(p->graph_def[k]);
+        p->graph[k] = nullptr;
+        p->graph_def[k] = nullptr;
+        p->graph_psi[k] = nullptr;
+    }
+}
+
+// Steps per captured chunk.  A call replays chunks when it records no per-step
+// observables, times no passes and is long enough to amortise a capture (a plan
+// created with GPE_PLAN_GRAPH=0 in the environment never does).
+static constexpr int kChunk = 32;
+
+static bool replay_ok(const gpe_plan *p, int64_t nsteps, const double *obs)
+{
+    return p->replay && !obs && p->timing_every == 0 && nsteps >= 2 + 2 * kChunk;
+}
+
+// Capture kChunk steps issued by `issue` (on the capture stream) as graph k, unless the
+// graph for this psi exists.
+template <class F> static int capture_chunk(gpe_plan *p, int k, const void *psi, F issue)
+{
+    if (p->graph[k] && p->graph_psi[k] == psi) return GPE_OK;
+    if (p->graph[k]) (void)hipGraphExecDestroy(p->graph[k]);
+    if (p->graph_def[k]) (void)hipGraphDestroy(p->graph_def[k]);
+    p->graph[k] = nullptr;
+    p->graph_def[k] = nullptr;
+    p->graph_psi[k] = nullptr;
+    if (!p->cap) HIP_OK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = issue(p->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(GPE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&p->graph[k], g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        p->graph[k] = nullptr;
+        return fail(GPE_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    p->graph_def[k] = g;
+    p->graph_psi[k] = psi;
+    return GPE_OK;
+}
+
 static int check_sched(const gpe_schedule &s, const char *name)
 {
     if (s.kind < 0 || s.kind > 3) return fail(GPE_ERR_INVALID, std::string(name) + ": unknown schedule kind");
@@ -158,6 +209,7 @@ int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
     if (v->probe_omega != 0 && v->cavity != 2)
         return fail(GPE_ERR_INVALID, "the cavity probe acts on the adiabatic field only");
     HIP_OK(hipStreamSynchronize(p->stream));
+    drop_plan_graphs(p);  // the potential is baked into captured kernel arguments
     const int nx = p->nx, ny = p->ny;
     std::vector<float4> tx(nx), ty(ny);
     for (int i = 0; i < nx; ++i) {
@@ -232,6 +284,8 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     if (force && !strcmp(force, "lds")) p->path = 2;
     const char *xcd = getenv("GPE_XCD");
     if (xcd && !strcmp(xcd, "0")) p->xcd = 0;
+    const char *rep = getenv("GPE_PLAN_GRAPH");
+    if (rep && !strcmp(rep, "0")) p->replay = false;
     const int nx = d->nx, ny = d->ny;
     p->shape = make_shape(nx, ny);
     int rc = 0;
@@ -311,6 +365,8 @@ int gpe_plan_destroy(gpe_plan *p)
     if (!p) return GPE_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
+    drop_plan_graphs(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     for (void *a : p->allocs) (void)hipFree(a);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->hpart) (void)hipHostFree(p->hpart);
@@ -483,7 +539,9 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
     ra.n = 0;
     ra.reduce = first_theta ? 2 : 0;
     LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, false, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
-    for (int64_t n = 0; n < nsteps; ++n) {
+    // step n of the call: column pass, then the row pass whose kick sits at st->t0 +
+    // (rel + 1) dt (rel = n unless replayed chunks have moved st->t0 on)
+    auto step = [&](int64_t n, int64_t rel, hipStream_t s) -> int {
         ColArgs ca = col_args(p, f);
         TailArgs &ta = ca.tail;
         ta.partials = p->partials;
@@ -496,13 +554,41 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         ca.do_tail = (ta.npartials > 0 || ta.advance_alpha) ? 1 : 0;
         const bool timed = p->timing_every > 0 && n % p->timing_every == 0 && n + 1 < nsteps;
         hipEvent_t *ec = timed ? timing_pair(p, 0) : nullptr;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream,
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s,
                              ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
-        ra.n = (int)n;
-        ra.reduce = red ? (obs ? 1 : 2) : 0;
+        RowArgs rb = ra;
+        rb.n = (int)rel;
+        rb.reduce = red ? (obs ? 1 : 2) : 0;
         hipEvent_t *er = timed ? timing_pair(p, 1) : nullptr;
-        LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, ra, sh.row_blocks, sh.row_threads,
-                             sh.row_shmem, p->stream, er ? er[0] : nullptr, er ? er[1] : nullptr));
+        LAUNCH_OK(launch_row(p->nx, n + 1 < nsteps ? ROW_MID : ROW_EXIT, false, rb, sh.row_blocks, sh.row_threads,
+                             sh.row_shmem, s, er ? er[0] : nullptr, er ? er[1] : nullptr));
+        return GPE_OK;
+    };
+    int rc;
+    if (!replay_ok(p, nsteps, obs)) {
+        for (int64_t n = 0; n < nsteps; ++n)
+            if ((rc = step(n, n, p->stream))) return rc;
+    } else {
+        // step 0 (it may start the overlap history), then the middle steps 1 .. nsteps-2
+        // from replayed chunks of kChunk steps counted from st->t0 = t0 + dt, which each
+        // chunk moves on by kChunk dt, then the rest and the exit step directly
+        if ((rc = step(0, 0, p->stream))) return rc;
+        LAUNCH_OK(launch_advance_one(p->st, p->dt, p->stream));
+        if ((rc = capture_chunk(p, 0, f, [&](hipStream_t s) -> int {
+                 for (int j = 0; j < kChunk; ++j) {
+                     int r = step(1, j, s);
+                     if (r) return r;
+                 }
+                 LAUNCH_OK(launch_advance_one(p->st, kChunk * p->dt, s));
+                 return GPE_OK;
+             })))
+            return rc;
+        const int64_t mids = nsteps - 2;
+        int64_t done = 0;
+        for (; mids - done >= kChunk; done += kChunk) HIP_OK(hipGraphLaunch(p->graph[0], p->stream));
+        for (int64_t r = 0; r < mids - done; ++r)
+            if ((rc = step(1 + done + r, r, p->stream))) return rc;
+        if ((rc = step(nsteps - 1, mids - done, p->stream))) return rc;
     }
     if (red) {
         TailArgs ta{};
@@ -598,23 +684,45 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
         LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
     }
     RowArgs ra = row_args(p, f);
-    for (int64_t n = 0; n < nsteps; ++n) {
+    // one step: entry kick (with the pending scale), columns, exit kick with the norm
+    // partials, tail (renormalisation scale, field); the potential is frozen at t, so
+    // every step without observables is the same launch sequence
+    auto step = [&](int64_t n, hipStream_t s) -> int {
         ra.n = (int)n;
         ra.reduce = 0;
-        LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
         ColArgs ca = col_args(p, f);
         ca.do_tail = 0;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s));
         ra.reduce = 1;
-        LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
+        LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
         TailArgs ta{};
         ta.partials = p->partials;
         ta.npartials = sh.row_blocks;
         ta.imag = 1;
         ta.alpha_from_partials = adia ? 1 : 0;
         ta.obs = obs ? obs + n * NOBS : nullptr;
-        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, p->stream));
+        LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, s));
+        return GPE_OK;
+    };
+    int rc;
+    int64_t done = 0;
+    if (replay_ok(p, nsteps, obs)) {
+        // the first step directly (its launches set up the kernels), then chunks
+        if ((rc = step(0, p->stream))) return rc;
+        done = 1;
+        if ((rc = capture_chunk(p, 1, f, [&](hipStream_t s) -> int {
+                 for (int j = 0; j < kChunk; ++j) {
+                     int r = step(0, s);
+                     if (r) return r;
+                 }
+                 return GPE_OK;
+             })))
+            return rc;
+        for (; nsteps - done >= kChunk; done += kChunk) HIP_OK(hipGraphLaunch(p->graph[1], p->stream));
     }
+    for (int64_t n = done; n < nsteps; ++n)
+        if ((rc = step(n, p->stream))) return rc;
     LAUNCH_OK(launch_scale(f, (size_t)p->nx * p->ny, p->st, p->stream));
     LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
     return GPE_OK;

@@ -30,6 +30,7 @@ hipError_t launch_col_batched(int n, int r, const BatchPassArgs &a, int blocks, 
 hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, hipStream_t s);
 hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStream_t s);
 hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s);
+hipError_t launch_advance_one(DevState *st, double dt_total, hipStream_t s);
 hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
 hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
 hipError_t launch_adj_tail(const AdjInst *inst, int count, int nrow, int k, hipStream_t s);
@@ -97,6 +98,14 @@ struct gpe_plan {
     PotDev pot{};
     Shape shape{};
     bool have_theta = false;
+    // chunks of steps captured as graphs and replayed (0 real time, 1 imaginary time) on
+    // the plan's stream; captured on a private stream, rebuilt when psi or the potential
+    // changes (kernel arguments are baked into a graph)
+    bool replay = true;  // environment GPE_PLAN_GRAPH=0 at creation: launch every step
+    hipStream_t cap = nullptr;
+    hipGraph_t graph_def[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    const void *graph_psi[2] = {nullptr, nullptr};
     // pass timing (instrumentation)
     int timing_every = 0;
     std::vector<hipEvent_t> ev_pool;
