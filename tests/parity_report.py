@@ -1,0 +1,189 @@
+"""Parity report: run every configured workload at its own size and step count on the
+GPU and print the measured errors against the FP64 oracle (rel-L2 of the state, rel-E of
+the energy functional, and the other checks of the config tests) with the GPU time per
+step.  Test infrastructure, like tests/test_gpu_configs.py (which asserts the same
+quantities); this script prints them.  Usage: python tests/parity_report.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2404_14401_amd import gpe  # noqa: E402
+from paper_2404_14401_amd import workloads as W  # noqa: E402
+from tests.bridge import problem, state  # noqa: E402
+
+
+def rel_l2(a, ref):
+    a, ref = np.asarray(a, np.complex128), np.asarray(ref, np.complex128)
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+
+def rel_e(a, b):
+    return abs(a - b) / abs(b)
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).to("cuda")
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def timed(fn):
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def row(name, **kv):
+    print(f"| {name} | " + " | ".join(f"{k} {v:.2e}" if isinstance(v, float) else f"{k} {v}" for k, v in kv.items())
+          + " |", flush=True)
+
+
+def c1():
+    for g in (0.0, 100.0):
+        for seed in (0, 1, 2):
+            s = W.imag_ground_64(g)
+            psi0 = W.noisy_gaussian(s, seed)
+            ref, _ = O.step_imag(problem(s), state(s), psi0, W.IMAG_64_STEPS)
+            p = gpe.Plan.from_setup(s)
+            d = dev(psi0)
+            t = timed(lambda: p.step_imag(d, W.IMAG_64_STEPS, 0.0))
+            row(f"C1 64^2 imaginary, g={g:g}, seed {seed}, {W.IMAG_64_STEPS} steps",
+                rel_L2=rel_l2(host(d), ref), rel_E=rel_e(p.energy(d)["e"], O.energy(problem(s), ref)["e"]),
+                us_per_step=1e6 * t / W.IMAG_64_STEPS)
+
+
+def c2():
+    import torch
+
+    s = W.dipole_lattice_256()
+    s0 = s.with_(y0=0.0, sx=W.Schedule("const", 0.0), dt=0.005)
+    gs, _ = O.step_imag(problem(s0), state(s0), W.thomas_fermi_guess(s0, float(np.sqrt(s.g / np.pi))), 3000)
+    psi0 = W.to_c64(gs)
+    n = W.DIPOLE_256_STEPS
+    ref, robs = O.step_real(problem(s), state(s), psi0, n, want_obs=True)
+    p = gpe.Plan.from_setup(s)
+    d = dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    half = n // 2
+    p.step_real(d, half, 0.0, obs[:half])
+    e_mid = p.energy(d, half * s.dt)["e"]
+    p.step_real(d, n - half, half * s.dt, obs[half:])
+    e_end = p.energy(d, n * s.dt)["e"]
+    o = obs.cpu().numpy()
+    tt = s.dt * np.arange(1, n + 1)
+    wd = np.arccos(1 - s.dt ** 2 / 2) / s.dt
+    kohn = s.y0 * (1 - np.cos(wd * tt))
+    d2 = dev(psi0)
+    t = timed(lambda: p.step_real(d2, n, 0.0))
+    row(f"C2 256^2 dipole + lattice ramp, {n} steps", rel_L2=rel_l2(host(d), ref),
+        rel_E=rel_e(e_end, O.energy(problem(s), ref, n * s.dt)["e"]), norm_drift=float(np.abs(o[:, 0] - 1).max()),
+        energy_drift_const_H=rel_e(e_end, e_mid), kohn_err=float(np.abs(o[:, 5] - kohn).max()),
+        us_per_step=1e6 * t / n)
+
+
+def c3():
+    import importlib.util
+
+    import torch
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "golden", "cavity_1024_seed0.npz")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "golden", "make_cavity_1024.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    g = np.load(path)
+    s = W.cavity_1024(int(g["seed"]))
+    n = int(g["nsteps"])
+    psi0 = mk.start_state(s)
+    p = gpe.Plan.from_setup(s)
+    d = dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    t = timed(lambda: p.step_real(d, n, 0.0, obs))
+    out = host(d)
+    sub = int(g["sub"])
+    o = obs.cpu().numpy()
+    a_gpu = o[99::100, 2] + 1j * o[99::100, 3]
+    row(f"C3 1024^2 cavity, {n} steps (oracle run stored, every {sub}th point)",
+        rel_L2=rel_l2(out[::sub, ::sub], g["psi_sub"]), rel_E=rel_e(p.energy(d, n * s.dt)["e"], g["energy"][3]),
+        alpha_rel=float(np.abs(a_gpu - g["alpha"]).max() / np.abs(g["alpha"]).max()),
+        theta_abs=float(np.abs(o[99::100, 1] - g["theta"]).max()), us_per_step=1e6 * t / n)
+
+
+def c4():
+    setups = W.sweep_208(0)
+    psi0 = [W.to_c64(W.gaussian(s, 1.0)) for s in setups]
+    devs = [dev(x) for x in psi0]
+    b = gpe.Batch(setups)
+    n = W.SWEEP_STEPS
+    t = timed(lambda: b.step(devs, n, 0.0))
+    for i in (0, 191):
+        s = setups[i]
+        ref, _ = O.step_real(problem(s), state(s), psi0[i], n)
+        row(f"C4 member {i} ({s.nx}^2) of 208, {n} steps", rel_L2=rel_l2(host(devs[i]), ref),
+            rel_E=rel_e(gpe.Plan.from_setup(s).energy(devs[i], n * s.dt)["e"],
+                        O.energy(problem(s), ref, n * s.dt)["e"]))
+    pts = sum(s.nx * s.ny for s in setups)
+    row("C4 208 members batched", pt_steps_per_s=pts * n / t)
+
+
+def c5():
+    nb, n = W.CONTROL_BATCH, W.CONTROL_STEPS
+    setups = [W.control_512(b) for b in range(nb)]
+    s0 = setups[0]
+    st = []
+    for s in (s0.with_(dt=0.01, sx=W.Schedule("const", 0.0)), s0.with_(dt=0.01, sx=W.Schedule("const", 15.0))):
+        p = gpe.Plan.from_setup(s)
+        x = dev(W.to_c64(W.gaussian(s, 1.5)))
+        p.step_imag(x, 800, 0.0)
+        st.append(x)
+    psi0 = [st[0].clone() for _ in range(nb)]
+    tgts = [st[1] for _ in range(nb)]
+    knots = np.stack([s.sx.knots for s in setups])
+    b = gpe.Batch(setups)
+    t0 = time.perf_counter()
+    loss, grad, info = gpe.adjoint(b, psi0, tgts, n, knots, mode="reconstruct")
+    t_adj = time.perf_counter() - t0
+    h = 0.05
+    fd_err = 0.0
+    for m in (10, 100, 190):
+        kp, km = knots.copy(), knots.copy()
+        kp[3, m] += h
+        km[3, m] -= h
+        lp, _, _ = gpe.adjoint(b, psi0, tgts, n, kp)
+        lm, _, _ = gpe.adjoint(b, psi0, tgts, n, km)
+        fd_err = max(fd_err, abs(grad[3, m] - (lp[3] - lm[3]) / (2 * h)) / np.abs(grad[3]).max())
+    row(f"C5 16 x 512^2 gradient, {n} steps", drift=float(info["drift"]), fd_rel=fd_err, adjoint_s=t_adj)
+    ns = 200
+    sh = W.control_512(5, nknots=20, nsteps=ns)
+    p0 = host(st[0]).astype(np.complex64)
+    tg = host(st[1]).astype(np.complex64)
+    bs = gpe.Batch([sh])
+    l_g, g_g, _ = gpe.adjoint(bs, [dev(p0)], [dev(tg)], ns, sh.sx.knots[None, :], mode="reconstruct")
+    l_o, g_o, _ = O.adjoint(problem(sh), 0.0, p0, tg, ns)
+    row(f"C5 gradient vs the oracle adjoint (512^2, {ns} steps, 20 knots)",
+        grad_rel_L2=float(np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o)), loss_abs=abs(float(l_g[0]) - l_o))
+
+
+if __name__ == "__main__":
+    for f in (c1, c2, c3, c4, c5):
+        f()
