@@ -316,11 +316,45 @@ def bench_library_fft(steps: int, us_per_step: float):
     return out
 
 
-def bench_grid_sweep(steps: int, runs: int):
+def _torch_imag_steps(s, psi, nsteps: int):
+    """The paper's route for comparison: imaginary-time split steps written with torch's
+    FFT and elementwise ops in psi's dtype (V/2 decay, fft2, kinetic decay, ifft2, V/2
+    decay, renormalisation), on psi's device; returns the elapsed seconds."""
+    import numpy as np
+    import torch
+
+    real = torch.float64 if psi.dtype == torch.complex128 else torch.float32
+    y, x = np.meshgrid(s.ys(), s.xs(), indexing="ij")
+    V = torch.from_numpy(0.5 * s.wx ** 2 * x ** 2 + 0.5 * s.wy ** 2 * y ** 2).to(psi.device, real)
+    kx = 2 * np.pi * np.fft.fftfreq(s.nx, d=s.lx / s.nx)
+    ky = 2 * np.pi * np.fft.fftfreq(s.ny, d=s.ly / s.ny)
+    K = torch.from_numpy(np.exp(-0.5 * (ky[:, None] ** 2 + kx[None, :] ** 2) * s.dt)).to(psi.device, real)
+    dA, h = (s.lx / s.nx) * (s.ly / s.ny), 0.5 * s.dt
+
+    def run(p, n):
+        for _ in range(n):
+            p = p * torch.exp(-(V + s.g * (p.real * p.real + p.imag * p.imag)) * h)
+            p = torch.fft.ifft2(torch.fft.fft2(p) * K)
+            p = p * torch.exp(-(V + s.g * (p.real * p.real + p.imag * p.imag)) * h)
+            p = p / torch.sqrt((p.real * p.real + p.imag * p.imag).sum() * dA)
+        return p
+
+    run(psi, 2)
+    if psi.is_cuda:
+        return _timed(lambda: run(psi, nsteps))
+    t = time.perf_counter()
+    run(psi, nsteps)
+    return time.perf_counter() - t
+
+
+def bench_grid_sweep(steps: int, runs: int, side_steps: int, oracle_max_n: int):
     """The paper's timing experiment reshaped for this library (Sec. 4.1): imaginary time
     for a non-interacting condensate in a fixed harmonic trap, Nx = Ny = 2^n on
     [-8, 8)^2, dtau = 1e-3, `steps` steps per run, the mean over `runs` runs; n from 6 to
-    12, the plan's largest grid.  Small grids take the LDS-resident path."""
+    12, the plan's largest grid.  Small grids take the LDS-resident path.  Beside it, on
+    bounded samples of `side_steps` steps scaled to `steps`: the paper's route (torch.fft
+    and elementwise ops) on the GPU in complex128 and complex64, and the FP64 oracle on the
+    host's threads for n <= oracle_max_n."""
     import numpy as np
     import torch
 
@@ -336,12 +370,27 @@ def bench_grid_sweep(steps: int, runs: int):
         ts = [_timed(lambda: p.step_imag(psi, steps, 0.0)) for _ in range(runs)]
         t = float(np.mean(ts))
         pts = s.nx * s.ny
-        rows.append({"n": n, "grid": pts, "ms_per_run": 1e3 * t, "ms_runs": [1e3 * x for x in ts],
-                     "value": pts * steps / t, "hbm_frac": 32 * pts * steps / t / (HBM_PEAK_GBS * 1e9)})
+        row = {"n": n, "grid": pts, "ms_per_run": 1e3 * t, "ms_runs": [1e3 * x for x in ts],
+               "value": pts * steps / t, "hbm_frac": 32 * pts * steps / t / (HBM_PEAK_GBS * 1e9)}
         p.close()
+        if side_steps > 0:
+            scale = steps / side_steps
+            for name, dt in (("torch_c128_ms_per_run", torch.complex128), ("torch_c64_ms_per_run", torch.complex64)):
+                row[name] = 1e3 * scale * _torch_imag_steps(s, psi.to(dt), side_steps)
+            if n <= oracle_max_n:
+                sys.path.insert(0, HERE)
+                from oracle import oracle as O
+                from tests.bridge import problem, state
+
+                t0 = time.perf_counter()
+                O.step_imag(problem(s), state(s), W.gaussian(s, 1.5), side_steps)
+                row["oracle_ms_per_run"] = 1e3 * scale * (time.perf_counter() - t0)
         del psi
+        rows.append(row)
     return {"workload": f"imaginary time, g=0, harmonic trap w=1, [-8,8)^2, dtau=1e-3, {steps} steps per run, "
-                        f"mean of {runs} runs", "unit": "grid-point-steps/s", "rows": rows}
+                        f"mean of {runs} runs; torch route and oracle from {side_steps}-step samples scaled to "
+                        f"{steps} steps (oracle on all host threads, n <= {oracle_max_n})",
+            "unit": "grid-point-steps/s", "rows": rows}
 
 
 def bench_out_of_cache(steps: int, members: int):
@@ -470,6 +519,10 @@ def main() -> int:
     ap.add_argument("--sweep-steps", type=int, default=1000,
                     help="steps per run of the 64^2..4096^2 imaginary-time grid sweep (0: skip)")
     ap.add_argument("--sweep-runs", type=int, default=5)
+    ap.add_argument("--sweep-side-steps", type=int, default=50,
+                    help="steps of the torch-route and oracle samples in the grid sweep (0: skip)")
+    ap.add_argument("--sweep-oracle-max-n", type=int, default=9,
+                    help="largest 2^n grid the oracle is timed on in the grid sweep")
     ap.add_argument("--ooc-steps", type=int, default=20,
                     help="steps of the 64 x 1024^2 out-of-cache batch (0: skip)")
     ap.add_argument("--ooc-members", type=int, default=64)
@@ -585,7 +638,8 @@ def main() -> int:
         out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
     if args.sweep_steps > 0:
         log("grid sweep ...")
-        out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs)
+        out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs, args.sweep_side_steps,
+                                             args.sweep_oracle_max_n)
     if args.ooc_steps > 0:
         log("out-of-cache batch ...")
         out["out_of_cache"] = bench_out_of_cache(args.ooc_steps, args.ooc_members)
