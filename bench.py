@@ -70,9 +70,11 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(setup, psi0, budget_s: float, one_core_s: float):
+def cpu_baseline(setup, psi0, budget_s: float, one_core_s: float, sweep_steps: int = 0, sweep_max_n: int = 0,
+                 sweep_per_run: int = 1000):
     """The oracle on all the host's threads (budget_s of work), and on one thread
-    (one_core_s of work, 0: skip)."""
+    (one_core_s of work, 0: skip); and its time for the grid sweep's workload at
+    2^6 .. 2^sweep_max_n from sweep_steps-step samples scaled to sweep_per_run steps."""
     sys.path.insert(0, HERE)
     from oracle import oracle as O
     from tests.bridge import problem, state
@@ -103,6 +105,17 @@ def cpu_baseline(setup, psi0, budget_s: float, one_core_s: float):
         c1, n1, v1 = timed(1, one_core_s)
         out["one_core"] = {"value": v1, "cores": c1, "sample": f"{n1} steps, same workload"}
         O.set_threads(all_threads)
+    if sweep_steps > 0:
+        from paper_2404_14401_amd import workloads as W
+
+        rows = []
+        for n in range(6, sweep_max_n + 1):
+            s = sweep_setup(n)
+            t0 = time.perf_counter()
+            O.step_imag(problem(s), state(s), W.gaussian(s, 1.5), sweep_steps)
+            rows.append({"n": n, "ms_per_run": 1e3 * (time.perf_counter() - t0) * sweep_per_run / sweep_steps})
+        out["grid_sweep"] = {"sample": f"{sweep_steps} imaginary-time steps per grid scaled to {sweep_per_run}, "
+                                       f"all host threads", "rows": rows}
     return out
 
 
@@ -347,14 +360,22 @@ def _torch_imag_steps(s, psi, nsteps: int):
     return time.perf_counter() - t
 
 
-def bench_grid_sweep(steps: int, runs: int, side_steps: int, oracle_max_n: int):
+def sweep_setup(n: int):
+    """Grid-sweep workload: imaginary time, g = 0, harmonic trap w = 1, 2^n x 2^n on
+    [-8, 8)^2, dtau = 1e-3 (the paper's timing experiment, Sec. 4.1)."""
+    from paper_2404_14401_amd import workloads as W
+
+    return W.imag_ground_64(0.0).with_(nx=1 << n, ny=1 << n)
+
+
+def bench_grid_sweep(steps: int, runs: int, side_steps: int):
     """The paper's timing experiment reshaped for this library (Sec. 4.1): imaginary time
     for a non-interacting condensate in a fixed harmonic trap, Nx = Ny = 2^n on
     [-8, 8)^2, dtau = 1e-3, `steps` steps per run, the mean over `runs` runs; n from 6 to
     12, the plan's largest grid.  Small grids take the LDS-resident path.  Beside it, on
     bounded samples of `side_steps` steps scaled to `steps`: the paper's route (torch.fft
-    and elementwise ops) on the GPU in complex128 and complex64, and the FP64 oracle on the
-    host's threads for n <= oracle_max_n."""
+    and elementwise ops) on the GPU in complex128 and complex64.  (The oracle's times for
+    the same sweep are part of the cpu_baseline leg.)"""
     import numpy as np
     import torch
 
@@ -363,7 +384,7 @@ def bench_grid_sweep(steps: int, runs: int, side_steps: int, oracle_max_n: int):
 
     rows = []
     for n in range(6, 13):
-        s = W.imag_ground_64(0.0).with_(nx=1 << n, ny=1 << n)
+        s = sweep_setup(n)
         p = gpe.Plan.from_setup(s)
         psi = torch.from_numpy(W.to_c64(W.gaussian(s, 1.5))).to("cuda")
         p.step_imag(psi, 10, 0.0)
@@ -377,19 +398,10 @@ def bench_grid_sweep(steps: int, runs: int, side_steps: int, oracle_max_n: int):
             scale = steps / side_steps
             for name, dt in (("torch_c128_ms_per_run", torch.complex128), ("torch_c64_ms_per_run", torch.complex64)):
                 row[name] = 1e3 * scale * _torch_imag_steps(s, psi.to(dt), side_steps)
-            if n <= oracle_max_n:
-                sys.path.insert(0, HERE)
-                from oracle import oracle as O
-                from tests.bridge import problem, state
-
-                t0 = time.perf_counter()
-                O.step_imag(problem(s), state(s), W.gaussian(s, 1.5), side_steps)
-                row["oracle_ms_per_run"] = 1e3 * scale * (time.perf_counter() - t0)
         del psi
         rows.append(row)
     return {"workload": f"imaginary time, g=0, harmonic trap w=1, [-8,8)^2, dtau=1e-3, {steps} steps per run, "
-                        f"mean of {runs} runs; torch route and oracle from {side_steps}-step samples scaled to "
-                        f"{steps} steps (oracle on all host threads, n <= {oracle_max_n})",
+                        f"mean of {runs} runs; torch route from {side_steps}-step samples scaled to {steps} steps",
             "unit": "grid-point-steps/s", "rows": rows}
 
 
@@ -522,7 +534,7 @@ def main() -> int:
     ap.add_argument("--sweep-side-steps", type=int, default=50,
                     help="steps of the torch-route and oracle samples in the grid sweep (0: skip)")
     ap.add_argument("--sweep-oracle-max-n", type=int, default=9,
-                    help="largest 2^n grid the oracle is timed on in the grid sweep")
+                    help="largest 2^n grid of the grid sweep the oracle is timed on (cpu_baseline leg)")
     ap.add_argument("--ooc-steps", type=int, default=20,
                     help="steps of the 64 x 1024^2 out-of-cache batch (0: skip)")
     ap.add_argument("--ooc-members", type=int, default=64)
@@ -638,8 +650,7 @@ def main() -> int:
         out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
     if args.sweep_steps > 0:
         log("grid sweep ...")
-        out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs, args.sweep_side_steps,
-                                             args.sweep_oracle_max_n)
+        out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs, args.sweep_side_steps)
     if args.ooc_steps > 0:
         log("out-of-cache batch ...")
         out["out_of_cache"] = bench_out_of_cache(args.ooc_steps, args.ooc_members)
@@ -648,7 +659,9 @@ def main() -> int:
         out["library_fft_side"] = bench_library_fft(args.side_steps, 1e3 * out["ms_per_step"])
     if args.cpu_budget > 0:
         log(f"timing the oracle for ~{args.cpu_budget:.0f} s ...")
-        out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget, args.cpu_one_core)
+        out["cpu_baseline"] = cpu_baseline(setup, psi0, args.cpu_budget, args.cpu_one_core,
+                                           args.sweep_side_steps if args.sweep_steps > 0 else 0,
+                                           args.sweep_oracle_max_n, max(args.sweep_steps, 1))
     print(json.dumps(out), flush=True)
     return 0
 

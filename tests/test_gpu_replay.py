@@ -10,7 +10,10 @@ from tests.gpu_util import to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-N_STEPS = 2 + 2 * 32 + 7  # two replayed chunks and a remainder
+# step counts around the replay threshold: the smallest replayed call (two chunks, no
+# middle remainder in real time), a call whose imaginary steps fill the chunks exactly,
+# and two chunks with remainders
+STEP_COUNTS = (66, 65 + 32, 73)
 
 
 def setup_for(kind):
@@ -23,7 +26,7 @@ def setup_for(kind):
                    sx=W.Schedule("ramp", 0.0, 8.0, 0.0, 0.2))
 
 
-def run_calls(kind, replay, monkeypatch):
+def run_calls(kind, replay, n0, monkeypatch):
     torch = torch_cuda()
     from paper_2404_14401_amd import gpe
 
@@ -40,8 +43,8 @@ def run_calls(kind, replay, monkeypatch):
     for call in range(3):
         if call == 2:
             plan.set_potential(s.with_(wx=1.3))
-        (plan.step_imag if kind == "imag" else plan.step_real)(d, N_STEPS + call, t)
-        t += (N_STEPS + call) * s.dt
+        (plan.step_imag if kind == "imag" else plan.step_real)(d, n0 + call, t)
+        t += (n0 + call) * s.dt
         out.append(to_host(d))
         torch.cuda.synchronize()
         _ = (d.abs() ** 2).sum().item()  # other work on the stream between calls
@@ -49,9 +52,10 @@ def run_calls(kind, replay, monkeypatch):
     return out
 
 
+@pytest.mark.parametrize("n0", STEP_COUNTS)
 @pytest.mark.parametrize("kind", ["real", "imag", "cavity"])
-def test_replayed_chunks_equal_launching_every_step(kind, monkeypatch):
-    a = run_calls(kind, True, monkeypatch)
-    b = run_calls(kind, False, monkeypatch)
+def test_replayed_chunks_equal_launching_every_step(kind, n0, monkeypatch):
+    a = run_calls(kind, True, n0, monkeypatch)
+    b = run_calls(kind, False, n0, monkeypatch)
     for x, y in zip(a, b):
         assert np.array_equal(np.asarray(x), np.asarray(y))
