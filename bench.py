@@ -45,6 +45,44 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+TRAFFIC_KERNELS = {"column_pass": "col_pass<1024, 0>", "row_pass_mid": "row_pass<1024, 1, false>"}
+
+
+def traffic_from(root: str, copy_mib: int = 64) -> dict:
+    """HBM bytes per launch of the two cavity-step passes from four rocprofv3 counter runs
+    under root (fetch/, write/: FETCH_SIZE and WRITE_SIZE of the bench; copy_fetch/,
+    copy_write/: the same counters of --copy-calibration copy_mib), each counter scaled so
+    that the copy of known size reads right."""
+    import csv
+    import glob
+
+    def load(name):
+        path = glob.glob(os.path.join(root, name, "**", "*counter_collection.csv"), recursive=True)[0]
+        vals = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    def mean_kib(vals, pattern):
+        v = [x for k, xs in vals.items() if pattern in k for x in xs]
+        if not v:
+            raise ValueError(f"no launches of {pattern} under {root}")
+        return sum(v) / len(v), len(v)
+
+    copy_bytes = copy_mib << 20
+    scale_f = copy_bytes / (1024 * mean_kib(load("copy_fetch"), "copyBuffer")[0])
+    scale_w = copy_bytes / (1024 * mean_kib(load("copy_write"), "copyBuffer")[0])
+    fe, wr = load("fetch"), load("write")
+    out = {"source_sha": kernel_source_sha(),
+           "calibration": {"fetch_scale": scale_f, "write_scale": scale_w, "copy_bytes": copy_bytes}, "kernels": {}}
+    for key, pat in TRAFFIC_KERNELS.items():
+        (f, n), (w, _) = mean_kib(fe, pat), mean_kib(wr, pat)
+        fb, wb = 1024 * scale_f * f, 1024 * scale_w * w
+        out["kernels"][key] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": n}
+    return out
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
     taken on the current kernel sources."""
@@ -543,7 +581,13 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=os.path.join(HERE, "profiles", "tune_cache.txt"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (scale for rocprofv3 byte counters)")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="only print the per-launch HBM bytes from rocprofv3 counter runs under DIR "
+                         "(fetch/, write/, copy_fetch/, copy_write/; no GPU used)")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from(args.traffic_from), indent=1))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
