@@ -34,6 +34,9 @@ namespace gpe {
 #ifndef GPE_TW_LDS
 #define GPE_TW_LDS 0
 #endif
+#ifndef GPE_ADJ_TW_LDS
+#define GPE_ADJ_TW_LDS 1
+#endif
 constexpr int kRadix = GPE_RADIX;
 constexpr int kLgR = ilog2(GPE_RADIX);
 #if GPE_XCHG_FLOAT
@@ -1181,12 +1184,17 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     constexpr int AREAS = TRAJ ? 1 : 2;
     View la{smem + line * View::words(N)};
     View lb2{smem + ((AREAS - 1) * lines + line) * View::words(N)};
+#if GPE_ADJ_TW_LDS
     double2 *s_tw = (double2 *)((char *)smem + align16(AREAS * lines * View::words(N) * sizeof(XchgT)));
     float4 *s_tx = (float4 *)(s_tw + N);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         s_tw[i] = gd.tw_x[i];
         s_tx[i] = I.pot.tx[i];
     }
+#else
+    const double2 *s_tw = gd.tw_x;
+    const float4 *s_tx = I.pot.tx;
+#endif
     float2 *pp = I.psi + (size_t)row * N;
     float2 *pl = I.lam + (size_t)row * N;
     const float2 *ps = pp;
@@ -1356,12 +1364,17 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
     constexpr int AREAS = TRAJ ? 1 : 2;  // TRAJ: lam alone
     View la{smem + c, w};
     View lb{smem + (AREAS - 1) * words + c, w};
+#if GPE_ADJ_TW_LDS
     double2 *s_tw = (double2 *)((char *)smem + align16(AREAS * words * sizeof(XchgT)));
     double2 *s_ky = s_tw + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         s_tw[i] = gd.tw_y[i];
         s_ky[i] = gd.kin_y[i];
     }
+#else
+    const double2 *s_tw = gd.tw_y;
+    const double2 *s_ky = gd.kin_y;
+#endif
     C v[R], u[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
