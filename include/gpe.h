@@ -228,8 +228,9 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path);
 int gpe_batch_info(gpe_batch *b, int group, int out[8]);
 
 /* Cavity state of batch member m after the batch's last call, as gpe_get_cavity
- * (synchronous; the adiabatic field of Sec. 5.3, Eqs. 17-18, is the only cavity model a
- * batch runs: members with the field ODE are rejected at creation). */
+ * (synchronous).  Members may carry either cavity model: the field ODE (its overlap
+ * history carries over between calls, as on a plan) or the adiabatic field of Sec. 5.3,
+ * Eqs. 17-18. */
 int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 
 /* ------------------------------------------------------------------ adjoint

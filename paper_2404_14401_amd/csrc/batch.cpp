@@ -28,6 +28,7 @@ struct BGroup {
     int nx = 0, ny = 0;
     bool lds = false;
     bool adia = false;  // some member has the adiabatic field: probe passes before its kicks
+    bool ode = false;   // some member has the field ODE: Theta reductions and the recurrence
     std::vector<int> members;
     Tuning tune;
     Shape shape{};
@@ -69,6 +70,7 @@ struct gpe_batch {
     DevState **d_states_mp = nullptr;  // members of multi-pass groups
     int n_mp = 0;
     std::vector<void *> allocs;
+    bool has_ode = false;  // some multi-pass member has the field ODE
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     int chunk = 50;
@@ -135,19 +137,23 @@ static int group_row(gpe_batch *b, BGroup &g, int mode, int n, hipStream_t s)
     a.blocks_per_inst = g.shape.row_blocks;
     a.per_wg = g.shape.row_lines;
     a.n = n;
-    a.adia = g.adia ? 1 : 0;
+    a.cav = (g.adia || g.ode) ? 1 : 0;
     const int blocks = g.shape.row_blocks * (int)g.members.size();
     LAUNCH_OK(launch_row_batched(g.nx, g.tune.radix, mode, a, blocks, g.shape.row_threads, g.shape.row_shmem, s));
     (void)b;
     return GPE_OK;
 }
 
-static int group_col(gpe_batch *b, BGroup &g, hipStream_t s)
+// The column pass of one multi-pass group; first: the column pass of a call's first step.
+static int group_col(gpe_batch *b, BGroup &g, hipStream_t s, bool first = false)
 {
     BatchPassArgs a{};
     a.inst = g.d_inst;
     a.blocks_per_inst = g.shape.col_blocks;
     a.per_wg = g.shape.col_cols;
+    a.ode = g.ode ? 1 : 0;
+    a.first = first ? 1 : 0;
+    a.row_blocks = g.shape.row_blocks;
     const int blocks = g.shape.col_blocks * (int)g.members.size();
     a.xcd_swizzle = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
     LAUNCH_OK(launch_col_batched(g.ny, g.tune.radix, a, blocks, g.shape.col_threads, g.shape.col_shmem, s));
@@ -156,13 +162,13 @@ static int group_col(gpe_batch *b, BGroup &g, hipStream_t s)
 }
 
 // `count` middle steps (column pass + merged-kick row pass) of every multi-pass group,
-// relative step indices n0 .. n0+count-1.
-static int mid_steps(gpe_batch *b, int n0, int count, hipStream_t s)
+// relative step indices n0 .. n0+count-1; first: the first of them is a call's step 0.
+static int mid_steps(gpe_batch *b, int n0, int count, hipStream_t s, bool first = false)
 {
     for (int k = 0; k < count; ++k)
         for (auto &g : b->groups) {
             if (g.lds) continue;
-            int rc = group_col(b, g, s);
+            int rc = group_col(b, g, s, first && k == 0);
             if (rc) return rc;
             if (g.adia && (rc = group_row(b, g, ROW_PROBE_MID, n0 + k, s))) return rc;
             if ((rc = group_row(b, g, ROW_MID, n0 + k, s))) return rc;
@@ -171,16 +177,18 @@ static int mid_steps(gpe_batch *b, int n0, int count, hipStream_t s)
 }
 
 // The last step of a call for every multi-pass group: column pass, probe (adiabatic
-// field), exit row pass.
-static int exit_step(gpe_batch *b, int n)
+// field), exit row pass, then the field-ODE members' last Theta into their history.
+static int exit_step(gpe_batch *b, int n, bool first)
 {
     int rc;
     for (auto &g : b->groups)
-        if (!g.lds && (rc = group_col(b, g, b->work))) return rc;
+        if (!g.lds && (rc = group_col(b, g, b->work, first))) return rc;
     for (auto &g : b->groups) {
         if (g.lds) continue;
         if (g.adia && (rc = group_row(b, g, ROW_PROBE_MID, n, b->work))) return rc;
         if ((rc = group_row(b, g, ROW_EXIT, n, b->work))) return rc;
+        if (g.ode)
+            LAUNCH_OK(launch_tail_batched(g.d_inst, (int)g.members.size(), g.shape.row_blocks, b->work));
     }
     return GPE_OK;
 }
@@ -211,11 +219,8 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
 {
     if (!out || !descs || !pots || n < 1) return fail(GPE_ERR_INVALID, "need n >= 1 descriptions and potentials");
     *out = nullptr;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (descs[i].dt != descs[0].dt) return fail(GPE_ERR_INVALID, "batch members must share dt");
-        if (pots[i].cavity == GPE_CAVITY_ODE)
-            return fail(GPE_ERR_UNSUPPORTED, "batched cavity members: only the adiabatic field");
-    }
     gpe_batch *b = new gpe_batch();
     b->n = n;
     b->dt = descs[0].dt;
@@ -293,6 +298,11 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
                     if ((rc = balloc(b, (void **)&d.probe, sizeof(double) * NPART * g.ny))) return cleanup(rc);
                     g.adia = true;
                 }
+                if (p->pot.cavity == GPE_CAVITY_ODE) {
+                    if ((rc = balloc(b, (void **)&d.partials, sizeof(double) * NPART * g.ny))) return cleanup(rc);
+                    g.ode = true;
+                    b->has_ode = true;
+                }
                 g.h_inst[k] = d;
             }
             if ((rc = balloc(b, (void **)&g.d_inst, sizeof(InstDesc) * m))) return cleanup(rc);
@@ -332,7 +342,10 @@ static int bind_psis(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, bool en
             }
             HIP_OK(hipMemcpyAsync(g.d_lds, g.h_lds.data(), sizeof(LdsArgs) * m, hipMemcpyHostToDevice, b->work));
         } else {
-            for (size_t k = 0; k < m; ++k) g.h_inst[k].psi = (float2 *)psis[g.members[k]];
+            for (size_t k = 0; k < m; ++k) {
+                g.h_inst[k].psi = (float2 *)psis[g.members[k]];
+                g.h_inst[k].first_theta = b->plans[g.members[k]]->have_theta ? 0 : 1;
+            }
             HIP_OK(hipMemcpyAsync(g.d_inst, g.h_inst.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, b->work));
         }
     }
@@ -371,10 +384,11 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
             if ((rc = group_row(b, g, ROW_ENTRY, 0, b->work))) return rc;
         }
         int64_t mids = nsteps - 1, done = 0;
-        if (!b->warmed && mids > 0) {
-            const int k = (int)std::min<int64_t>(mids, 1);
-            if ((rc = mid_steps(b, 0, k, b->work))) return rc;
-            done = k;
+        // step 0 directly: the first call's launches load the kernels, and a field-ODE
+        // member's first column pass treats its overlap history differently
+        if ((!b->warmed || b->has_ode) && mids > 0) {
+            if ((rc = mid_steps(b, 0, 1, b->work, true))) return rc;
+            done = 1;
             b->warmed = true;
         }
         // chunks replayed from the captured graph use steps relative to st->t0,
@@ -387,11 +401,14 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
                 done += b->chunk;
             }
             if ((rc = mid_steps(b, 0, (int)(mids - done), b->work))) return rc;
-            if ((rc = exit_step(b, (int)(mids - done)))) return rc;
+            if ((rc = exit_step(b, (int)(mids - done), false))) return rc;
         } else {
-            if ((rc = mid_steps(b, (int)done, (int)(mids - done), b->work))) return rc;
-            if ((rc = exit_step(b, (int)mids))) return rc;
+            if ((rc = mid_steps(b, (int)done, (int)(mids - done), b->work, done == 0))) return rc;
+            if ((rc = exit_step(b, (int)mids, mids == 0))) return rc;
         }
+        for (auto &g : b->groups)
+            if (!g.lds && g.ode)
+                for (int i : g.members) b->plans[i]->have_theta = true;
     }
     if (side_used) HIP_OK(hipStreamWaitEvent(b->work, b->ev_side, 0));
     HIP_OK(hipEventRecord(b->ev_out, b->work));
@@ -400,7 +417,8 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
 }
 
 // Time `steps` middle steps of group g on its members' scratch arrays (device-side
-// contents are irrelevant to the timing).
+// contents are irrelevant to the timing; the members' cavity states are restored by
+// the caller).
 static double time_group(gpe_batch *b, BGroup &g, int steps)
 {
     std::vector<gpe_c64 *> psis(b->n, nullptr);
@@ -435,6 +453,11 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path)
         std::string l;
         while (std::getline(f, l)) lines.push_back(l);
     }
+    // the timing runs advance the members' cavity states: keep them and put them back
+    std::vector<DevState> saved(b->n);
+    HIP_OK(hipStreamSynchronize(b->work));
+    for (int i = 0; i < b->n; ++i)
+        HIP_OK(hipMemcpy(&saved[i], b->plans[i]->st, sizeof(DevState), hipMemcpyDeviceToHost));
     bool changed = false;
     for (auto &g : b->groups) {
         if (g.lds) continue;
@@ -476,6 +499,9 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path)
         lines.push_back(l.str());
         changed = true;
     }
+    HIP_OK(hipStreamSynchronize(b->work));
+    for (int i = 0; i < b->n; ++i)
+        HIP_OK(hipMemcpy(b->plans[i]->st, &saved[i], sizeof(DevState), hipMemcpyHostToDevice));
     drop_graph(b);
     b->warmed = false;
     if (changed && cache_path && *cache_path) {
@@ -632,7 +658,7 @@ static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     LAUNCH_OK(launch_set_call_batched(b->d_states, b->n, t0 + n0 * b->dt, b->work));
     BatchPassArgs ra{}, ca{};
     ra.inst = w->d_fwd;
-    ra.adia = w->any_adia ? 1 : 0;
+    ra.cav = w->any_adia ? 1 : 0;
     ra.traj = record ? 1 : 0;
     ra.blocks_per_inst = sh.row_blocks;
     ra.per_wg = sh.row_lines;

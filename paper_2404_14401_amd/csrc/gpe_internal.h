@@ -132,6 +132,8 @@ struct InstDesc {
     double *probe;  // adiabatic field: [row work-groups][NPART] partials of the probe pass (else null)
     float2 *traj;   // adjoint forward sweep: post-kick real-space state of every kick but the
                     // last, [kick][ny][nx] (else null)
+    double *partials;  // field ODE: [row work-groups][NPART] Theta partials of each kick (else null)
+    int first_theta;   // field ODE: this call's first kick starts the overlap history
 };
 
 // A batched row or column pass over all members of one grid size.
@@ -141,8 +143,12 @@ struct BatchPassArgs {
     int per_wg;           // rows or columns per work-group
     int n;                // step index within the call
     int xcd_swizzle;
-    int adia;             // some member has the adiabatic field (kick kernels read probe partials)
+    int cav;              // some member has a cavity field: kick kernels read the adiabatic members'
+                          // probe partials and reduce the field-ODE members' Theta
     int traj;             // entry and merged kicks record their output in InstDesc::traj
+    int ode;              // column pass: some member has the field ODE (its first tile runs the recurrence)
+    int first;            // column pass of a call's first step
+    int row_blocks;       // row work-groups per member (Theta partials to reduce)
 };
 
 // One member of an adjoint sweep (device memory): the state being reconstructed

@@ -268,9 +268,10 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).
 // A member with the adiabatic field carries probe partials: the probe modes write them,
 // the kick modes turn them into alpha; other members skip the probe modes.
-// (ADIA is a template flag so that groups without the field keep the probe-free kernel;
-// TRAJ likewise for the adjoint's forward sweep that records every kick's output.)
-template <int N, int R, int MODE, bool ADIA, bool TRAJ>
+// (CAV is a template flag so that groups without a cavity field keep the kernel without
+// probe sums and reductions; TRAJ likewise for the adjoint's forward sweep that records
+// every kick's output.)
+template <int N, int R, int MODE, bool CAV, bool TRAJ>
 __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
 {
     extern __shared__ XchgT smem[];
@@ -285,9 +286,12 @@ __global__ void __launch_bounds__(512) row_pass_b(BatchPassArgs a)
         if (!I.probe) return;
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, I.probe + lb * NPART, a.n, lb, a.per_wg, smem,
                                     red);
-    } else if constexpr (ADIA) {
-        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
-                                    I.probe, a.blocks_per_inst, false, tj);
+    } else if constexpr (CAV) {
+        // adiabatic members take the field from their probe sums; field-ODE members reduce
+        // Theta for the column pass's recurrence (the entry kick only when the history starts)
+        double *pt = (I.partials && (MODE != ROW_ENTRY || I.first_theta)) ? I.partials + lb * NPART : nullptr;
+        row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, pt, a.n, lb, a.per_wg, smem, red, 0.0,
+                                    I.probe, a.blocks_per_inst, true, tj);
     } else {
         row_body<N, R, MODE, false>(I.psi, I.psi, I.grid, I.pot, I.st, nullptr, a.n, lb, a.per_wg, smem, red, 0.0,
                                     nullptr, 0, false, tj);
@@ -455,14 +459,28 @@ __global__ void __launch_bounds__(1024) col_pass(ColArgs a)
                               a.cols_per_wg, smem, red, sc);
 }
 
-template <int N, int R>
+template <int N, int R, bool ODE>
 __global__ void __launch_bounds__(1024) col_pass_b(BatchPassArgs a)
 {
     extern __shared__ XchgT smem[];
     __shared__ double red[16 * NPART];
     const int tile = xcd_tile(a.xcd_swizzle);
     const InstDesc &I = a.inst[tile / a.blocks_per_inst];
-    col_body<N, R, COL_KIN_REAL>(I.psi, I.psi, I.grid, nullptr, tile % a.blocks_per_inst, a.per_wg, smem, red);
+    const int lt = tile % a.blocks_per_inst;
+    if constexpr (ODE) {
+        if (lt == 0 && I.partials) {
+            // this member's cavity field: Theta of the last kick into the overlap history
+            // (at a call's first step only when the history starts), then alpha_{n+1}
+            TailArgs ta{};
+            ta.partials = I.partials;
+            ta.npartials = (a.first && !I.first_theta) ? 0 : a.row_blocks;
+            ta.first_theta = (a.first && I.first_theta) ? 1 : 0;
+            ta.theta_only = 1;
+            ta.advance_alpha = 1;
+            run_tail(ta, I.grid, I.pot, I.st, red);
+        }
+    }
+    col_body<N, R, COL_KIN_REAL>(I.psi, I.psi, I.grid, nullptr, lt, a.per_wg, smem, red);
 }
 
 // --------------------------------------------------------------- small kernels
@@ -1001,7 +1019,7 @@ template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPas
     if (a.traj) {
         // the adjoint's recording forward sweep (radix 8 only): entry and merged kicks
         if constexpr (R == 8) {
-            if (a.adia) {
+            if (a.cav) {
                 if (mode == ROW_ENTRY) GPE_ROWB_T(ROW_ENTRY, true, true);
                 else if (mode == ROW_MID) GPE_ROWB_T(ROW_MID, true, true);
                 else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
@@ -1017,7 +1035,7 @@ template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPas
         } else {
             return hipErrorInvalidValue;
         }
-    } else if (a.adia) {
+    } else if (a.cav) {
         if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, true);
         else if (mode == ROW_MID) GPE_ROWB(ROW_MID, true);
         else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
@@ -1035,18 +1053,25 @@ template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPas
     return hipGetLastError();
 }
 
-template <int N, int R> static hipError_t colb_dispatch(const BatchPassArgs &a, int blocks, int threads, size_t shmem,
-                                                        hipStream_t s)
+template <int N, int R, bool ODE> static hipError_t colb_launch(const BatchPassArgs &a, int blocks, int threads,
+                                                                size_t shmem, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)col_pass_b<N, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024 - 1024);
+        hipError_t e = hipFuncSetAttribute((const void *)col_pass_b<N, R, ODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((col_pass_b<N, R>), dim3(blocks), dim3(threads), shmem, s, a);
+    hipLaunchKernelGGL((col_pass_b<N, R, ODE>), dim3(blocks), dim3(threads), shmem, s, a);
     return hipGetLastError();
+}
+
+template <int N, int R> static hipError_t colb_dispatch(const BatchPassArgs &a, int blocks, int threads, size_t shmem,
+                                                        hipStream_t s)
+{
+    return a.ode ? colb_launch<N, R, true>(a, blocks, threads, shmem, s)
+                 : colb_launch<N, R, false>(a, blocks, threads, shmem, s);
 }
 
 #define GPE_SIZES(F, ...)                                                                          \
@@ -1406,6 +1431,26 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
         if constexpr (!TRAJ) store_c64(I.psi + (size_t)(t + m * T) * nx + col, v[m]);
         store_c64(I.lam + (size_t)(t + m * T) * nx + col, u[m]);
     }
+}
+
+// After a batched call's exit pass: each field-ODE member's Theta of its last kick joins
+// the overlap history (one work-group per member).
+__global__ void __launch_bounds__(256) tail_batched_kernel(const InstDesc *inst, int nrow)
+{
+    __shared__ double red[4 * NPART];
+    const InstDesc &I = inst[blockIdx.x];
+    if (!I.partials) return;
+    TailArgs ta{};
+    ta.partials = I.partials;
+    ta.npartials = nrow;
+    ta.theta_only = 1;
+    run_tail(ta, I.grid, I.pot, I.st, red);
+}
+
+hipError_t launch_tail_batched(const InstDesc *inst, int count, int nrow, hipStream_t s)
+{
+    hipLaunchKernelGGL(tail_batched_kernel, dim3(count), dim3(256), 0, s, inst, nrow);
+    return hipGetLastError();
 }
 
 // The last kick's sums: one work-group per member.

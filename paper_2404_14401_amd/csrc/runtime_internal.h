@@ -33,6 +33,7 @@ hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStr
 hipError_t launch_advance_one(DevState *st, double dt_total, hipStream_t s);
 hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
 hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
+hipError_t launch_tail_batched(const InstDesc *inst, int count, int nrow, hipStream_t s);
 hipError_t launch_adj_tail(const AdjInst *inst, int count, int nrow, int k, hipStream_t s);
 hipError_t launch_pair_sums(const float2 *const *a, const float2 *const *b, size_t npts, int count, int per_inst,
                             double *out, hipStream_t s);

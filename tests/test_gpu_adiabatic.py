@@ -144,13 +144,42 @@ def test_adiabatic_batched_sweep_matches_plain_solver_and_oracle(path, monkeypat
             assert close_alpha(b.cavity(i), st.alpha, 1e-4), i
 
 
-def test_batch_rejects_field_ode_members():
+@pytest.mark.parametrize("path", ["auto", "multipass"])
+def test_batched_field_ode_members_match_plain_solver_and_oracle(path, monkeypatch):
+    """Field-ODE cavity members (Sec. 5.3 with the cavity recurrence) in one batch: 64^2 and
+    128^2 members (LDS-resident beside the multi-pass 256^2 group, unless multi-pass is
+    forced), a 256^2 member (multi-pass, graph replayed) and a member without the cavity,
+    over two calls so that the overlap history carries over: each equals the plain
+    solver, a 128^2 one the oracle."""
     torch_cuda()
     from paper_2404_14401_amd import gpe
 
-    with pytest.raises(gpe.GpeError) as e:
-        gpe.Batch([W.cavity_scaled(64, 0)])
-    assert e.value.code == gpe.ERR_UNSUPPORTED
+    if path != "auto":
+        monkeypatch.setenv("GPE_BATCH_PATH", path)
+    setups = [W.cavity_scaled(64, 1), W.cavity_scaled(128, 2), W.cavity_scaled(128, 3), W.cavity_scaled(256, 0),
+              W.cavity_scaled(128, 0).with_(cavity=False)]
+    psi0 = [W.to_c64(W.thomas_fermi_guess(s.with_(wx=0.6, wy=0.6), np.sqrt(s.g / np.pi) * 0.6)) for s in setups]
+    b = gpe.Batch(setups)
+    lds = {g["nx"]: g["lds"] for g in b.groups()}
+    assert lds == ({64: True, 128: True, 256: False} if path == "auto" else {64: False, 128: False, 256: False})
+    devs = [to_dev(p) for p in psi0]
+    calls = ((0, 170), (170, 37))  # (first step, steps): a replayed call, then a short one
+    for n0, n in calls:
+        b.step(devs, n, n0 * setups[0].dt)
+    for i, s in enumerate(setups):
+        plain = plain_plan_like(b, s)
+        d = to_dev(psi0[i])
+        for n0, n in calls:
+            plain.step_real(d, n, n0 * s.dt)
+        assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-6, i
+        if s.cavity:
+            assert close_alpha(b.cavity(i), plain.cavity()["alpha"], 1e-6), i
+    st = state(setups[1])
+    ref = psi0[1]
+    for n0, n in calls:
+        ref, _ = O.step_real(problem(setups[1]), st, ref, n)
+    assert rel_l2(to_host(devs[1]), ref) < 1e-4
+    assert close_alpha(b.cavity(1), st.alpha, 1e-4)
 
 
 def test_adiabatic_batch_with_multipass_groups():

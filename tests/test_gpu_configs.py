@@ -162,3 +162,29 @@ def test_control_512_full_size_gradient():
     l_o, g_o, _ = O.adjoint(problem(sh), 0.0, p0, t0, ns)
     assert abs(l_g[0] - l_o) < 1e-5
     assert np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o) < 1e-3
+
+
+def test_cavity_1024_eta_sweep_batched_equals_plain_runs():
+    """The cavity workload's eta sweep (seeds 0-3) as one batch of four 1024^2 runs: each
+    member equals its plain run (same kernels' arithmetic) with its own field."""
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = [W.cavity_1024(seed) for seed in range(4)]
+    s0 = setups[0]
+    psi0 = W.to_c64(W.thomas_fermi_guess(s0, float(np.sqrt(s0.g / np.pi) * s0.wx)))
+    n = 300
+    b = gpe.Batch(setups)
+    devs = [to_dev(psi0) for _ in setups]
+    b.step(devs, n, 0.0)
+    alphas = []
+    for i, s in enumerate(setups):
+        plain = plain_plan_like(b, s)
+        d = to_dev(psi0)
+        plain.step_real(d, n, 0.0)
+        assert rel_l2(to_host(devs[i]), to_host(d)) < 1e-6, i
+        a_b, a_p = b.cavity(i), plain.cavity()["alpha"]
+        assert abs(a_b - a_p) <= 1e-6 * max(abs(a_p), 1e-6), i
+        alphas.append(a_b)
+    # the members do differ: eta, hence the field, depends on the seed
+    assert len({round(abs(a), 12) for a in alphas}) == 4
