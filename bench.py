@@ -443,6 +443,36 @@ def bench_grid_sweep(steps: int, runs: int, side_steps: int):
             "unit": "grid-point-steps/s", "rows": rows}
 
 
+def bench_eta_sweep(steps: int, seeds: int = 4):
+    """The cavity workload's eta sweep (seeds 0 .. seeds-1, each its own eta) as one batch
+    of 1024^2 field-ODE runs, against running the seeds one after the other."""
+    import numpy as np
+    import torch
+
+    from paper_2404_14401_amd import gpe
+    from paper_2404_14401_amd import workloads as W
+
+    setups = [W.cavity_1024(k) for k in range(seeds)]
+    s0 = setups[0]
+    psi0 = torch.from_numpy(W.to_c64(W.thomas_fermi_guess(s0, float(np.sqrt(s0.g / np.pi) * s0.wx)))).to("cuda")
+    psis = [psi0.clone() for _ in setups]
+    b = gpe.Batch(setups)
+    b.step(psis, 4, 0.0)
+    t_b = _timed(lambda: b.step(psis, steps, 4 * s0.dt))
+    plans = [gpe.Plan.from_setup(s) for s in setups]
+    ws = [psi0.clone() for _ in setups]
+    for p, w in zip(plans, ws):
+        p.step_real(w, 4, 0.0)
+    t_p = _timed(lambda: [p.step_real(w, steps, 4 * s0.dt) for p, w in zip(plans, ws)])
+    pts = seeds * s0.nx * s0.ny
+    out = {"workload": f"cavity run at 1024^2 for eta seeds 0..{seeds - 1} in one batch, field ODE", "steps": steps,
+           "value": pts * steps / t_b, "unit": "grid-point-steps/s", "us_per_batch_step": 1e6 * t_b / steps,
+           "hbm_frac": 32 * pts * steps / t_b / (HBM_PEAK_GBS * 1e9), "plain_runs_value": pts * steps / t_p,
+           "speedup_vs_plain_runs": t_p / t_b, "alpha": [str(b.cavity(i)) for i in range(seeds)]}
+    b.close()
+    return out
+
+
 def bench_out_of_cache(steps: int, members: int):
     """A state larger than the 256 MB Infinity Cache: `members` real-time condensates at
     1024^2 (trap + pump lattice of the cavity workload, field off) in one batch, so the
@@ -573,6 +603,8 @@ def main() -> int:
                     help="steps of the torch-route and oracle samples in the grid sweep (0: skip)")
     ap.add_argument("--sweep-oracle-max-n", type=int, default=9,
                     help="largest 2^n grid of the grid sweep the oracle is timed on (cpu_baseline leg)")
+    ap.add_argument("--eta-steps", type=int, default=2000,
+                    help="steps of the batched eta sweep of the cavity workload (0: skip)")
     ap.add_argument("--ooc-steps", type=int, default=20,
                     help="steps of the 64 x 1024^2 out-of-cache batch (0: skip)")
     ap.add_argument("--ooc-members", type=int, default=64)
@@ -695,6 +727,9 @@ def main() -> int:
     if args.sweep_steps > 0:
         log("grid sweep ...")
         out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs, args.sweep_side_steps)
+    if args.eta_steps > 0:
+        log("eta sweep batch ...")
+        out["eta_sweep_1024"] = bench_eta_sweep(args.eta_steps)
     if args.ooc_steps > 0:
         log("out-of-cache batch ...")
         out["out_of_cache"] = bench_out_of_cache(args.ooc_steps, args.ooc_members)
