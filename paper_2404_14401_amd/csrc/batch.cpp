@@ -81,7 +81,11 @@ struct gpe_batch {
 static int balloc(gpe_batch *b, void **p, size_t bytes)
 {
     hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // the failure is reported here, not by the next launch check
+        *p = nullptr;
+        return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
     b->allocs.push_back(*p);
     return GPE_OK;
 }

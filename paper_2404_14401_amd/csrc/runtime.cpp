@@ -35,7 +35,11 @@ int dalloc(gpe_plan *p, void **ptr, size_t bytes)
     if (p->max_bytes && p->bytes + bytes > p->max_bytes)
         return fail(GPE_ERR_NOMEM, "plan memory cap exceeded");
     hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // the failure is reported here, not by the next launch check
+        *ptr = nullptr;
+        return fail(GPE_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
     p->allocs.push_back(*ptr);
     p->bytes += bytes;
     return GPE_OK;
@@ -329,8 +333,11 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     if ((rc = dalloc(p, (void **)&p->partials2, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->probe, sizeof(double) * NPART * p->npart_max))) return cleanup(rc);
     if ((rc = dalloc(p, (void **)&p->scratch, sizeof(float2) * (size_t)nx * ny))) return cleanup(rc);
-    if (hipHostMalloc((void **)&p->hpart, sizeof(double) * NPART * p->npart_max) != hipSuccess)
+    if (hipHostMalloc((void **)&p->hpart, sizeof(double) * NPART * p->npart_max) != hipSuccess) {
+        (void)hipGetLastError();
+        p->hpart = nullptr;
         return cleanup(fail(GPE_ERR_NOMEM, "hipHostMalloc"));
+    }
     GridDev &gd = p->grid;
     gd.nx = nx;
     gd.ny = ny;

@@ -243,3 +243,22 @@ def test_stored_trajectory_is_regrown_and_reused_across_calls():
         assert info["workspace_bytes"] >= max(n, 50 if n != 20 else 20) * nb * npts * 8
         assert np.abs(ls - lr).max() < 1e-6
         assert np.linalg.norm(gs - gr) / np.linalg.norm(gr) < 1e-4
+
+
+def test_stored_trajectory_beyond_the_device_reports_nomem_and_the_batch_recovers():
+    """2^27 steps of a 64^2 member would need 4.4 TB of trajectory: the allocation fails
+    cleanly (GPE_ERR_NOMEM, nothing launched) and the batch still serves other calls."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = control_setup(0, nsteps=30)
+    b = gpe.Batch([s])
+    p0, tg = states(s, 0)
+    d0, dt_ = [to_dev(p0)], [to_dev(tg)]
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.adjoint(b, d0, dt_, 1 << 27, s.sx.knots[None, :], mode="store")
+    assert e.value.code == gpe.ERR_NOMEM
+    ls, gs, info = gpe.adjoint(b, d0, dt_, 30, s.sx.knots[None, :], mode="store")
+    lr, gr, _ = gpe.adjoint(b, d0, dt_, 30, s.sx.knots[None, :], mode="reconstruct")
+    assert info["mode"] == "store" and abs(ls[0] - lr[0]) < 1e-6
+    assert np.linalg.norm(gs - gr) / np.linalg.norm(gr) < 1e-4
