@@ -53,10 +53,15 @@ using namespace gpe;
 int gpe_fail(int code, const std::string &msg);
 #define fail gpe_fail
 
+// A failed HIP call is reported by the call that made it; its error is also taken off the
+// thread's last-error state so that a later launch check does not report it again.
 #define HIP_OK(expr)                                                                               \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(GPE_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return fail(GPE_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_));          \
+        }                                                                                          \
     } while (0)
 
 #define LAUNCH_OK(expr)                                                                  \
