@@ -204,7 +204,7 @@ def bench_batched(steps: int, tune_cache: str | None):
     }
 
 
-def bench_adjoint(steps: int, nb: int):
+def bench_adjoint(steps: int, nb: int, tune_cache: str | None = None):
     """Optimal-control gradient: nb members at 512^2, `steps` real-time steps, lattice
     depth over 200 knots from PCG64(member), g = 300; loss = 1 - |<target|psi(T)>|^2 with
     the target the ground state at V0 = 15.  Forward alone vs forward + reverse, in each
@@ -232,6 +232,7 @@ def bench_adjoint(steps: int, nb: int):
     tgts = [states[1] for _ in range(nb)]
     knots = np.stack([s.sx.knots for s in setups])
     b = gpe.Batch(setups)
+    b.tune(tune_cache)  # the forward it is compared with runs its tuned shapes
     gpe.adjoint(b, psi0, tgts, 20, knots[:, :], mode="reconstruct")  # warm-up
     work = [x.clone() for x in psi0]
     torch.cuda.synchronize()
@@ -274,6 +275,7 @@ def bench_adjoint(steps: int, nb: int):
         sy=W.Schedule("knots", t0=0.0, t1=steps * setups[0].dt, knots=-3.0 - setups[b].sx.knots)) for b in range(nb)]
     kc = np.stack([s.sy.knots for s in ca])
     bc = gpe.Batch(ca)
+    bc.tune(tune_cache)
     gpe.adjoint(bc, psi0, tgts, 20, kc, mode="reconstruct", control="pump")  # warm-up
     work = [x.clone() for x in psi0]
     torch.cuda.synchronize()
@@ -723,7 +725,7 @@ def main() -> int:
         out["widened"] = bench_widened(args.widened_steps)
     if args.adjoint_steps > 0:
         log("adjoint ...")
-        out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch)
+        out["adjoint"] = bench_adjoint(args.adjoint_steps, args.adjoint_batch, args.tune_cache)
     if args.sweep_steps > 0:
         log("grid sweep ...")
         out["grid_sweep"] = bench_grid_sweep(args.sweep_steps, args.sweep_runs, args.sweep_side_steps)

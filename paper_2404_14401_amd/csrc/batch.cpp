@@ -756,13 +756,21 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         if (!psi0[i] || (!energy && !target[i])) return fail(GPE_ERR_INVALID, "null member state");
     }
     if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
-    Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, 256);
-    if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, nx / std::max(1, 512 / (ny / 8)));
+    // launch shape of the adjoint's passes: 256 threads per row work-group and at least
+    // 128 column tiles per member, measured best at 16 x 512^2 against row 128/512 and
+    // 32..512 tiles (environment GPE_ADJ_ROW_THREADS, GPE_ADJ_MIN_COL_TILES for tuning runs)
+    auto env = [](const char *name, int dflt) {
+        const char *v = getenv(name);
+        return v && *v ? atoi(v) : dflt;
+    };
+    const int art = env("GPE_ADJ_ROW_THREADS", 256), act = env("GPE_ADJ_MIN_COL_TILES", 128);
+    Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, act);
+    if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, nx / std::max(1, 512 / (ny / 8)));
     if (sh.col_threads > 512) return fail(GPE_ERR_UNSUPPORTED, "column shape");
     // the adjoint column pass holds two exchange areas: narrow the tiles until they fit LDS
     for (int tiles = nx / sh.col_cols * 2; adj_col_shmem(ny, sh.col_cols, 8, 2) > 158 * 1024 && sh.col_cols > 1;
          tiles *= 2)
-        sh = make_shape_r(nx, ny, 8, xchg_bytes(), 256, tiles);
+        sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, tiles);
     if (adj_col_shmem(ny, sh.col_cols, 8, 2) > 158 * 1024 || adj_row_shmem(nx, sh.row_lines, 8, 2) > 158 * 1024)
         return fail(GPE_ERR_UNSUPPORTED, "adjoint passes exceed the LDS of a work-group");
     AdjWork *w = adj_work(b);
