@@ -83,3 +83,31 @@ def test_batch_tune_keeps_results_and_writes_cache(tmp_path):
     b2 = gpe.Batch(setups)
     b2.tune(cache)  # read back from the cache
     assert [g["radix"] for g in b2.groups()] == [g["radix"] for g in b.groups()]
+
+
+def test_tuning_between_calls_keeps_the_cavity_state(monkeypatch):
+    """The tuner's timing runs advance the members' states; it puts them back, so a
+    field-ODE batch tuned between two calls continues exactly where it stopped (to the
+    tuned shapes' rounding) and matches the oracle."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    monkeypatch.setenv("GPE_BATCH_PATH", "multipass")
+    setups = [W.cavity_scaled(128, 2), W.cavity_scaled(128, 3)]
+    psi0 = [W.to_c64(W.thomas_fermi_guess(s.with_(wx=0.6, wy=0.6), np.sqrt(s.g / np.pi) * 0.6)) for s in setups]
+    tuned, plain = gpe.Batch(setups), gpe.Batch(setups)
+    a = [to_dev(p) for p in psi0]
+    c = [to_dev(p) for p in psi0]
+    tuned.step(a, 60, 0.0)
+    before = [tuned.cavity(i) for i in range(2)]
+    tuned.tune(None)
+    assert [tuned.cavity(i) for i in range(2)] == before
+    tuned.step(a, 60, 60 * setups[0].dt)
+    plain.step(c, 120, 0.0)
+    for i, s in enumerate(setups):
+        assert rel_l2(to_host(a[i]), to_host(c[i])) < 1e-5, i
+        assert abs(tuned.cavity(i) - plain.cavity(i)) <= 1e-5 * abs(plain.cavity(i)), i
+    st = state(setups[0])
+    ref, _ = O.step_real(problem(setups[0]), st, psi0[0], 120)
+    assert rel_l2(to_host(a[0]), ref) < 1e-4
+    assert abs(tuned.cavity(0) - st.alpha) <= 1e-4 * abs(st.alpha)
