@@ -604,6 +604,7 @@ static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t n
     }
     if (nsteps + 1 > w->cap_steps) {
         for (int i = 0; i < nb; ++i) {
+            bfree(b, w->kick_grad[i]);  // replaced by a longer one
             int rc;
             if ((rc = balloc(b, (void **)&w->kick_grad[i], sizeof(double) * (size_t)(nsteps + 1)))) return rc;
         }
