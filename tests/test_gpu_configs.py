@@ -6,7 +6,9 @@
   stored oracle run (tests/golden, written by make_cavity_1024.py);
 * 208-member sweep, 5000 steps: sampled members vs the plain solver and the oracle;
 * 16 x 512^2 control gradient, 5000 steps: GPU finite differences, reconstruction drift,
-  and the oracle adjoint on a shorter horizon.
+  and the oracle adjoint on a shorter horizon; the stored trajectory at full size against
+  reconstruction, and the energy loss against GPU finite differences;
+* the cavity workload's eta sweep as one batch of four 1024^2 runs against plain runs.
 """
 import os
 
@@ -188,3 +190,51 @@ def test_cavity_1024_eta_sweep_batched_equals_plain_runs():
         alphas.append(a_b)
     # the members do differ: eta, hence the field, depends on the seed
     assert len({round(abs(a), 12) for a in alphas}) == 4
+
+
+def control_start(setups):
+    """Ground states for the control workload: psi(0) at V0 = 0, the target at V0 = 15."""
+    from paper_2404_14401_amd import gpe
+
+    s0 = setups[0]
+    st = []
+    for s in (s0.with_(dt=0.01, sx=W.Schedule("const", 0.0)), s0.with_(dt=0.01, sx=W.Schedule("const", 15.0))):
+        p = gpe.Plan.from_setup(s)
+        x = to_dev(W.to_c64(W.gaussian(s, 1.5)))
+        p.step_imag(x, 800, 0.0)
+        st.append(x)
+    return st
+
+
+def test_control_512_full_size_stored_trajectory_and_energy_loss():
+    """The full control workload (16 x 512^2, 5000 steps): the stored-trajectory mode
+    (a 168 GB trajectory) gives the reconstruction's gradient, and the energy loss's
+    gradient agrees with central differences of the GPU loss."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nb, n = W.CONTROL_BATCH, W.CONTROL_STEPS
+    setups = [W.control_512(b) for b in range(nb)]
+    st = control_start(setups)
+    psi0 = [st[0].clone() for _ in range(nb)]
+    tgts = [st[1] for _ in range(nb)]
+    knots = np.stack([s.sx.knots for s in setups])
+    b = gpe.Batch(setups)
+    lr, gr, _ = gpe.adjoint(b, psi0, tgts, n, knots, mode="reconstruct")
+    ls, gs, info = gpe.adjoint(b, psi0, tgts, n, knots, mode="store")
+    assert info["mode"] == "store" and info["workspace_bytes"] >= nb * n * 512 * 512 * 8
+    assert np.abs(ls - lr).max() < 1e-6
+    assert np.linalg.norm(gs - gr) / np.linalg.norm(gr) < 1e-4
+    b.close()
+    # energy loss: E(psi(T)) of every member, gradient vs central differences on member 2
+    b = gpe.Batch(setups)
+    le, ge, _ = gpe.adjoint(b, psi0, None, n, knots, mode="reconstruct", loss="energy")
+    h = 0.05
+    for m in (20, 120, 199):
+        kp, km = knots.copy(), knots.copy()
+        kp[2, m] += h
+        km[2, m] -= h
+        lp, _, _ = gpe.adjoint(b, psi0, None, n, kp, loss="energy")
+        lm, _, _ = gpe.adjoint(b, psi0, None, n, km, loss="energy")
+        fd = (lp[2] - lm[2]) / (2 * h)
+        assert abs(ge[2, m] - fd) <= 3e-2 * np.abs(ge[2]).max(), (m, ge[2, m], fd)
