@@ -21,14 +21,22 @@ def plan_for(s):
     return gpe.Plan.from_setup(s)
 
 
-@pytest.mark.parametrize("shape", [(64, 32), (32, 64), (256, 128)])
+def box(n):
+    """Box length for an n-point axis: dx = 3/16 on small grids, at most 48 so that the
+    trap stays physical on the long lines (at 4096 points and 768 units it would reach
+    V ~ 1e5 at the edges, a kick phase of ~2e3 rad per step, where the single-precision
+    potential tables alone carry ~1e-4 rad)."""
+    return min(12.0 * n / 64, 48.0)
+
+
+@pytest.mark.parametrize("shape", [(64, 32), (32, 64), (256, 128), (4096, 16), (16, 4096)])
 def test_kspace_steps_with_every_potential_term(shape):
     """Trap (displaced, anisotropic), both lattices (ramp and const), g > 0; a few steps
     from a random state on non-square grids (the 256 x 128 grid takes the
-    XCD-swizzled column launch)."""
+    XCD-swizzled column launch; 4096 is the longest line either pass takes)."""
     torch = torch_cuda()
     nx, ny = shape
-    s = W.Setup(nx=nx, ny=ny, lx=12.0 * nx / 64, ly=12.0 * ny / 64, dt=0.02, g=30.0, wx=1.1, wy=0.8,
+    s = W.Setup(nx=nx, ny=ny, lx=box(nx), ly=box(ny), dt=0.02, g=30.0, wx=1.1, wy=0.8,
                 x0=0.3, y0=-0.2, kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("ramp", 1.0, 3.0, 0.0, 0.1),
                 sy=W.Schedule("const", 2.0))
     psik0 = W.to_c64(O.fft2d(W.random_state(s, 11)))
@@ -152,11 +160,11 @@ def test_pulse_schedule_in_both_orderings(path, monkeypatch):
 
 # ------------------------------------------------ imaginary time, Fourier-space state
 
-@pytest.mark.parametrize("shape", [(64, 32), (256, 128)])
+@pytest.mark.parametrize("shape", [(64, 32), (256, 128), (4096, 16), (16, 4096)])
 def test_kspace_imaginary_steps_with_every_potential_term(shape):
     torch = torch_cuda()
     nx, ny = shape
-    s = W.Setup(nx=nx, ny=ny, lx=12.0 * nx / 64, ly=12.0 * ny / 64, dt=0.02, g=30.0, wx=1.1, wy=0.8,
+    s = W.Setup(nx=nx, ny=ny, lx=box(nx), ly=box(ny), dt=0.02, g=30.0, wx=1.1, wy=0.8,
                 x0=0.3, y0=-0.2, kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("ramp", 1.0, 3.0, 0.0, 0.1),
                 sy=W.Schedule("const", 2.0))
     psik0 = W.to_c64(O.fft2d(W.random_state(s, 4)))
