@@ -257,3 +257,26 @@ def test_bragg_probe_on_the_cavity_ground_state(path, monkeypatch):
     t = n * s.dt
     e_ref = O.energy(problem(s), ref, t, st.alpha)["e"]
     assert abs(plan.energy(d, t)["e"] - e_ref) / abs(e_ref) < 1e-5
+
+
+def test_adiabatic_field_at_1024_against_oracle():
+    """The widened bench workload (the cavity run with the adiabatic field, 1024^2) for a
+    few steps from the Thomas-Fermi start: psi on the full grid and alpha against the
+    oracle, with the probe pass and the multi-pass kernels the bench times."""
+    torch = torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.cavity_1024_adiabatic(0)
+    psi0 = W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx)))
+    n = 12
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, n, want_obs=True)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    plan.step_real(d, n, 0.0, obs)
+    assert rel_l2(to_host(d), ref) < 1e-5
+    o = obs.cpu().numpy()
+    a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
+    assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
+    assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-4)
