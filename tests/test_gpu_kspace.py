@@ -206,3 +206,17 @@ def test_kspace_imaginary_ground_state_64():
     e_g = O.energy(problem(s), O.fft2d(out, inverse=True))["e"]
     e_r = O.energy(problem(s), O.fft2d(ref, inverse=True))["e"]
     assert abs(e_g - e_r) / abs(e_r) < 1e-5
+
+
+def test_kspace_1024_against_oracle():
+    """The widened bench workload (the cavity grid at 1024^2 with the cavity off, in the
+    printed ordering) for a few steps: psi_k on the full grid against the oracle."""
+    torch_cuda()
+    s = W.cavity_1024(0).with_(cavity=False)
+    psik0 = W.to_c64(O.fft2d(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx))))
+    n = 12
+    ref, _ = O.step_real_k(problem(s), state(s), psik0, n)
+    plan = plan_for(s)
+    d = to_dev(psik0)
+    plan.step_real_k(d, n, 0.0)
+    assert rel_l2(to_host(d), ref) < 1e-5
