@@ -2,7 +2,8 @@
 GPU and print the measured errors against the FP64 oracle (rel-L2 of the state, rel-E of
 the energy functional, and the other checks of the config tests) with the GPU time per
 step.  Test infrastructure, like tests/test_gpu_configs.py (which asserts the same
-quantities); this script prints them.  Usage: python tests/parity_report.py
+quantities); this script prints them.  Usage: python tests/parity_report.py [c1 c2 c3 c4 c5
+widened_1024] (all by default)
 """
 import os
 import sys
@@ -184,6 +185,34 @@ def c5():
         grad_rel_L2=float(np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o)), loss_abs=abs(float(l_g[0]) - l_o))
 
 
+def widened_1024():
+    """The widened bench workloads at 1024^2 for 12 steps: the adiabatic field and the
+    Fourier-space ordering (cavity off)."""
+    import torch
+
+    n = 12
+    s = W.cavity_1024_adiabatic(0)
+    psi0 = W.to_c64(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx)))
+    st = state(s)
+    ref, robs = O.step_real(problem(s), st, psi0, n, want_obs=True)
+    p = gpe.Plan.from_setup(s)
+    d = dev(psi0)
+    obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    p.step_real(d, n, 0.0, obs)
+    o = obs.cpu().numpy()
+    a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
+    row(f"1024^2 adiabatic cavity field, {n} steps", rel_L2=rel_l2(host(d), ref),
+        alpha_rel=float(np.abs(a_gpu - a_ref).max() / np.abs(a_ref).max()))
+    s = W.cavity_1024(0).with_(cavity=False)
+    psik0 = W.to_c64(O.fft2d(W.thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx))))
+    ref, _ = O.step_real_k(problem(s), state(s), psik0, n)
+    p = gpe.Plan.from_setup(s)
+    d = dev(psik0)
+    p.step_real_k(d, n, 0.0)
+    row(f"1024^2 Fourier-space ordering, {n} steps", rel_L2=rel_l2(host(d), ref))
+
+
 if __name__ == "__main__":
-    for f in (c1, c2, c3, c4, c5):
-        f()
+    fns = {f.__name__: f for f in (c1, c2, c3, c4, c5, widened_1024)}
+    for name in sys.argv[1:] or list(fns):
+        fns[name]()
