@@ -211,8 +211,10 @@ const char *gpe_last_error(void);
  * FFT pass over all members of a size.  Members up to 64^2 -- and 128^2 ones beside
  * larger sizes or at least 256 of them -- instead run all their steps in one
  * work-group each, the grid kept in LDS (environment GPE_BATCH_PATH=lds|multipass
- * forces either where it can).  psis: host array of n device pointers.
- * All members share the stream of desc[0]. */
+ * forces either where it can).  The batched multi-pass kernels take lines of 64..2048
+ * points: a member too large for LDS (a side above 128) with a side below 64 or above
+ * 2048 is refused with GPE_ERR_UNSUPPORTED (a plan of its own takes it).  psis: host
+ * array of n device pointers.  All members share the stream of desc[0]. */
 int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const gpe_potential_desc *pots);
 int gpe_batch_destroy(gpe_batch *b);
 int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double t0);

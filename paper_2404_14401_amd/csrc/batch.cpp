@@ -104,6 +104,9 @@ static void bfree(gpe_batch *b, void *p)
 // grid-point-steps/s), or with at least one member per CU, while a batch of fewer
 // 128^2 members alone runs faster multi-pass (80 adiabatic members: 2.7e10 vs 2.2e10).
 // GPE_BATCH_PATH=lds or multipass overrides the choice for every group that can.
+// The batched pass launchers are built for line lengths 64..2048 in both directions.
+static bool multipass_lines(int nx, int ny) { return nx >= 64 && ny >= 64 && nx <= 2048 && ny <= 2048; }
+
 static void choose_group_paths(std::vector<BGroup> &groups)
 {
     const char *force = getenv("GPE_BATCH_PATH");
@@ -115,7 +118,7 @@ static void choose_group_paths(std::vector<BGroup> &groups)
     }
     for (auto &g : groups) {
         if (!g.lds) continue;
-        if (none) g.lds = false;
+        if (none) g.lds = !multipass_lines(g.nx, g.ny);
         else if (!all_lds && g.nx * g.ny > 64 * 64) g.lds = any_mp || g.members.size() >= 256;
     }
 }
@@ -266,6 +269,12 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
         it->members.push_back(i);
     }
     choose_group_paths(b->groups);
+    for (auto &g : b->groups)
+        if (!g.lds && !multipass_lines(g.nx, g.ny))
+            return cleanup(fail(GPE_ERR_UNSUPPORTED, "batch member of " + std::to_string(g.nx) + " x " +
+                                                         std::to_string(g.ny) +
+                                                         ": beyond one work-group's LDS, both sides must be 64..2048 "
+                                                         "(a plan takes it)"));
     std::vector<DevState *> states(n);
     for (int i = 0; i < n; ++i) states[i] = b->plans[i]->st;
     if ((rc = balloc(b, (void **)&b->d_states, sizeof(DevState *) * n))) return cleanup(rc);

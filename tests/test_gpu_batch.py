@@ -111,3 +111,91 @@ def test_tuning_between_calls_keeps_the_cavity_state(monkeypatch):
     ref, _ = O.step_real(problem(setups[0]), st, psi0[0], 120)
     assert rel_l2(to_host(a[0]), ref) < 1e-4
     assert abs(tuned.cavity(0) - st.alpha) <= 1e-4 * abs(st.alpha)
+
+
+def nonsquare_members(mode):
+    """Members of seven grid shapes, wide and tall (LDS-resident 64 x 32 and 32 x 128;
+    multi-pass up to 2048 x 64 and 64 x 2048), one shape twice, all at the cavity
+    workload's spacing dx = 1/16, with the cavity off, the field ODE or the adiabatic field."""
+    shapes = [(64, 32), (32, 128), (256, 64), (256, 64), (64, 256), (512, 128), (2048, 64), (64, 2048)]
+    out = []
+    for i, (nx, ny) in enumerate(shapes):
+        s = W.cavity_scaled(16, i).with_(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0)
+        if mode == "off":
+            s = s.with_(cavity=False)
+        elif mode == "adiabatic":
+            s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("path", ["auto", "multipass"])
+@pytest.mark.parametrize("mode", ["off", "ode", "adiabatic"])
+def test_nonsquare_members_match_plain_solver_and_oracle(mode, path, monkeypatch):
+    """Batch groups of non-square grids (rows and columns of different lengths in one
+    member, ragged member counts per group): over two calls every member equals the plain
+    solver on the same kernels, and after the first call the smallest, the widest and the
+    tallest member equal the oracle, cavity field included.  Forced multi-pass leaves the
+    groups with 32-point lines in LDS (the batched passes take lines of 64..2048)."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    if path != "auto":
+        monkeypatch.setenv("GPE_BATCH_PATH", path)
+    setups = nonsquare_members(mode)
+    psi0 = [W.to_c64(W.gaussian(s, 1.0, 0.2, -0.1)) for s in setups]
+    b = gpe.Batch(setups)
+    assert sorted((g["nx"], g["ny"], g["members"]) for g in b.groups()) == sorted(
+        {(s.nx, s.ny, sum((t.nx, t.ny) == (s.nx, s.ny) for t in setups)) for s in setups})
+    lds = {(g["nx"], g["ny"]): g["lds"] for g in b.groups()}
+    assert lds[(64, 32)] and lds[(32, 128)] and not any(v for k, v in lds.items() if min(k) >= 64)
+    devs = [to_dev(p) for p in psi0]
+    plains = [plain_plan_like(b, s) for s in setups]
+    mine = [to_dev(p) for p in psi0]
+    n1, n2 = 120, 37
+    b.step(devs, n1, 0.0)
+    for p, d in zip(plains, mine):
+        p.step_real(d, n1, 0.0)
+    for i, s in enumerate(setups):
+        assert rel_l2(to_host(devs[i]), to_host(mine[i])) < 1e-6, (i, s.nx, s.ny)
+        if s.cavity:
+            a, c = b.cavity(i), plains[i].cavity()["alpha"]
+            assert abs(a - c) <= 1e-6 * abs(c), (i, a, c)
+    for i in (0, 6, 7):
+        s = setups[i]
+        st = state(s)
+        ref, _ = O.step_real(problem(s), st, psi0[i], n1)
+        assert rel_l2(to_host(devs[i]), ref) < 1e-4, (i, s.nx, s.ny)
+        if s.cavity:
+            assert abs(b.cavity(i) - st.alpha) <= 1e-4 * abs(st.alpha), (i, b.cavity(i), st.alpha)
+    b.step(devs, n2, n1 * setups[0].dt)
+    for p, d in zip(plains, mine):
+        p.step_real(d, n2, n1 * setups[0].dt)
+    for i, s in enumerate(setups):
+        assert rel_l2(to_host(devs[i]), to_host(mine[i])) < 1e-6, (i, s.nx, s.ny)
+
+
+@pytest.mark.parametrize("path", ["auto", "multipass"])
+def test_members_beyond_the_batched_line_lengths_are_refused_at_creation(path, monkeypatch):
+    """A member too large for one work-group's LDS with a side outside 64..2048 is refused
+    when the batch is made (not at its first step), and a plan still takes that grid."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    if path != "auto":
+        monkeypatch.setenv("GPE_BATCH_PATH", path)
+    base = W.cavity_scaled(16, 0).with_(cavity=False)
+    ok = base.with_(nx=64, ny=64, lx=4.0, ly=4.0)
+    for nx, ny in ((4096, 16), (16, 2048), (256, 32), (4096, 64), (64, 4096)):
+        s = base.with_(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0)
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.Batch([ok, s])
+        assert e.value.code == gpe.ERR_UNSUPPORTED and f"{nx} x {ny}" in str(e.value)
+        p = gpe.Plan.from_setup(s)
+        d = to_dev(W.to_c64(W.gaussian(s, 1.0)))
+        p.step_real(d, 3, 0.0)
+        assert np.isfinite(to_host(d)).all()
+    b = gpe.Batch([ok])
+    d = to_dev(W.to_c64(W.gaussian(ok, 1.0)))
+    b.step([d], 3, 0.0)
+    assert np.isfinite(to_host(d)).all()
