@@ -262,3 +262,60 @@ def test_stored_trajectory_beyond_the_device_reports_nomem_and_the_batch_recover
     lr, gr, _ = gpe.adjoint(b, d0, dt_, 30, s.sx.knots[None, :], mode="reconstruct")
     assert info["mode"] == "store" and abs(ls[0] - lr[0]) < 1e-6
     assert np.linalg.norm(gs - gr) / np.linalg.norm(gr) < 1e-4
+
+
+@pytest.mark.parametrize("shape", [(128, 64), (64, 256)])
+@pytest.mark.parametrize("kind", ["x-reconstruct", "x-store", "pump-checkpoint", "cavity-store", "energy-reconstruct"])
+def test_nonsquare_adjoint_matches_oracle(shape, kind):
+    """Rows and columns of different lengths through the adjoint's passes (the row pass
+    transforms along x, the column pass along y): wide and tall grids at the spacing of
+    the square cases, every control and loss, against the oracle adjoint."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nx, ny = shape
+    nsteps, nb = 40, 2
+    control, mode = kind.split("-")
+    box = dict(nx=nx, ny=ny, lx=nx / 4.0, ly=ny / 4.0)
+    if control == "cavity":
+        setups = [cavity_control_setup(b, "pump", nsteps=nsteps).with_(**box) for b in range(nb)]
+    elif control == "pump":
+        setups = [pump_setup(b, nsteps=nsteps).with_(**box) for b in range(nb)]
+    else:
+        setups = [control_setup(b, nsteps=nsteps).with_(**box) for b in range(nb)]
+    pump = control in ("pump", "cavity")
+    energy = control == "energy"
+    batch = gpe.Batch(setups)
+    p0, tg = zip(*[states(s, b) for b, s in enumerate(setups)])
+    knots = np.stack([(s.sy if pump else s.sx).knots for s in setups])
+    loss, grad, info = gpe.adjoint(batch, [to_dev(p) for p in p0], None if energy else [to_dev(t) for t in tg],
+                                   nsteps, knots, mode=mode, control="pump" if pump else "x",
+                                   loss="energy" if energy else "fidelity")
+    assert info["mode"] == mode and info["drift"] < 1e-4
+    for b, s in enumerate(setups):
+        l_ref, g_ref, _ = O.adjoint(problem(s), 0.0, p0[b], p0[b] if energy else tg[b], nsteps,
+                                    loss="energy" if energy else "fidelity", control="y" if pump else "x")
+        assert abs(loss[b] - l_ref) <= (1e-5 * abs(l_ref) if energy else 1e-5), (b, loss[b], l_ref)
+        assert np.linalg.norm(grad[b] - g_ref) / np.linalg.norm(g_ref) < 1e-3, b
+
+
+def test_adjoint_argument_and_size_refusals():
+    """Refused before anything runs: members of different grids, grids outside 64..1024,
+    the field-ODE cavity, a knot count that does not match the members' schedules."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    def call(setups, knots=None, err=gpe.ERR_INVALID):
+        b = gpe.Batch(setups)
+        d = [to_dev(states(s, 0)[0]) for s in setups]
+        k = np.stack([s.sx.knots for s in setups]) if knots is None else knots
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.adjoint(b, d, d, 10, k)
+        assert e.value.code == err, str(e.value)
+
+    call([control_setup(0, nsteps=10), control_setup(1, n=128, nsteps=10)])
+    call([control_setup(0, n=32, nsteps=10)], err=gpe.ERR_UNSUPPORTED)
+    call([control_setup(0, nsteps=10).with_(nx=2048, lx=512.0)], err=gpe.ERR_UNSUPPORTED)
+    call([control_setup(0, nsteps=10)], knots=np.zeros((1, 5)))
+    ode = W.cavity_scaled(64, 0).with_(sx=control_setup(0, nsteps=10).sx)
+    call([ode], err=gpe.ERR_UNSUPPORTED)
