@@ -280,3 +280,27 @@ def test_adiabatic_field_at_1024_against_oracle():
     a_gpu, a_ref = o[:, 2] + 1j * o[:, 3], robs[:, 2] + 1j * robs[:, 3]
     assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
     assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-4)
+
+
+@pytest.mark.parametrize("shape", [(256, 64), (64, 512)])
+@pytest.mark.parametrize("cavity", ["ode", "adiabatic"])
+def test_cavity_on_wide_and_tall_grids_with_replayed_chunks(shape, cavity, monkeypatch):
+    """Both cavity models on non-square multi-pass grids (the cavity workload's spacing,
+    dx = 1/16) over 300 real-time steps without per-step records, so that the plan
+    replays captured chunks: psi, alpha and the energy against the oracle."""
+    nx, ny = shape
+    s = W.cavity_scaled(16, 2).with_(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0)
+    if cavity == "adiabatic":
+        s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+    psi0 = W.to_c64(W.gaussian(s, 1.0, 0.2, -0.1))
+    n = 300
+    st = state(s)
+    ref, _ = O.step_real(problem(s), st, psi0, n)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    plan.step_real(d, n, 0.0)
+    assert rel_l2(to_host(d), ref) < 1e-4
+    assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-4) and abs(st.alpha) > 1e-3
+    t = n * s.dt
+    e_ref = O.energy(problem(s), ref, t, st.alpha)["e"]
+    assert abs(plan.energy(d, t)["e"] - e_ref) <= 1e-5 * abs(e_ref)
