@@ -150,6 +150,33 @@ def test_imag_ground_state_64(path, g, monkeypatch):
     assert abs(plan.norm(d) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("shape", [(256, 64), (64, 512)])
+@pytest.mark.parametrize("cavity", ["off", "adiabatic"])
+def test_imag_on_wide_and_tall_grids_with_replayed_chunks(shape, cavity, monkeypatch):
+    """Imaginary time on non-square multi-pass grids (dx = 1/8, anisotropic trap, both
+    lattices) for 400 steps without per-step records, so that the plan replays captured
+    chunks with the pending renormalisation carried between them; with the adiabatic
+    field, alpha follows the state."""
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=nx / 8.0, ly=ny / 8.0, dt=2e-3, g=200.0, wx=0.15, wy=0.2, x0=0.4,
+                kx_lat=1.0, ky_lat=1.5, sx=W.Schedule("const", 1.0), sy=W.Schedule("const", -2.0))
+    if cavity == "adiabatic":
+        s = s.with_(cavity=True, cavity_mode="adiabatic", vc=-0.2, kc=1.5, delta_c=-6.0, kappa=3.0, n_atoms=50.0)
+    psi0 = W.noisy_gaussian(s, 2)
+    n = 400
+    st = state(s)
+    ref, _ = O.step_imag(problem(s), st, psi0, n)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    plan.step_imag(d, n, 0.0)
+    assert rel_l2(to_host(d), ref) < TOL_L2
+    assert rel_e(plan.energy(d)["e"], O.energy(problem(s), ref, 0.0, st.alpha)["e"]) < TOL_E
+    assert abs(plan.norm(d) - 1.0) < 1e-6
+    if cavity == "adiabatic":
+        a = plan.cavity()["alpha"]
+        assert abs(a - st.alpha) <= 1e-4 * abs(st.alpha) and abs(st.alpha) > 1e-3
+
+
 # --------------------------------------------------------------- real time
 
 @pytest.mark.parametrize("path", ["lds", "multipass"])
