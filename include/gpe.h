@@ -12,20 +12,20 @@
  * (imaginary time: the same with -i dt -> -dt and psi renormalised to unit norm after
  * every step).  The potential is
  *   V = 1/2 wx^2 (x-x0)^2 + 1/2 wy^2 (y-y0)^2                     trap (Sec. 5.1)
- *     + Vx(t) cos^2(kx_lat x) + Vy(t) cos^2(ky_lat y)              lattices (Sec. 5.2, Eq. 12)
+ *     + Vx(t) cos^2(kx_lat x) + Vy(t) cos^2(ky_lat y)              lattices (Sec. 5.2, Eq. 9)
  *     + Vc |alpha|^2 cos^2(kc x)
- *     + 2 sqrt(Vy(t) Vc) Re(alpha) cos(kc x) cos(kc y)             cavity (Sec. 5.3, Eqs. 13-16)
+ *     + 2 sqrt(Vy(t) Vc) Re(alpha) cos(kc x) cos(kc y)             cavity (Sec. 5.3, Eqs. 10-13)
  *     + V_user(x, y)                                              optional static array
  * and the cavity field alpha either (GPE_CAVITY_ODE) obeys
  *   d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta,  Theta = <psi| cos kc x cos kc y |psi>
- * (the driven-damped form whose fixed point is Sec. 5.3, Eq. 17), advanced once per
+ * (the driven-damped form whose fixed point is Sec. 5.3, Eq. 14), advanced once per
  * step by an exponential integrator with the forcing extrapolated to second order, or
- * (GPE_CAVITY_ADIABATIC) is Eq. 17 itself with the dispersive shift of Eq. 18,
+ * (GPE_CAVITY_ADIABATIC) is Eq. 14 itself with the dispersive shift of Eq. 15,
  *   alpha = N sqrt(Vy(t) Vc) Theta / (Delta_c - N Vc C + i kappa),  C = <psi| cos^2 kc x |psi>,
  * Theta and C per unit norm, N = n_atoms, evaluated from the density about to be kicked:
  * before every kick in real time (a probe pass reduces that density first), once per
  * step from the state entering it in imaginary time.  The on-axis cavity probe of
- * Sec. 5.4 adds Omega_c e^{i (Delta_p t + phi)} / (Delta_c - N Vc C + i kappa) to it.
+ * Sec. 5.4 (Eq. 17) adds Omega_c e^{i (Delta_p t + phi)} / (Delta_c - N Vc C + i kappa) to it.
  *
  * Grid: x_i = -lx/2 + i lx/nx (i < nx), likewise y; psi is stored row-major
  * [ny][nx] (x fastest) as interleaved (re, im) floats; periodic boundaries (the FFT
@@ -232,7 +232,7 @@ int gpe_batch_info(gpe_batch *b, int group, int out[8]);
 /* Cavity state of batch member m after the batch's last call, as gpe_get_cavity
  * (synchronous).  Members may carry either cavity model: the field ODE (its overlap
  * history carries over between calls, as on a plan) or the adiabatic field of Sec. 5.3,
- * Eqs. 17-18. */
+ * Eqs. 14-15. */
 int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
 
 /* ------------------------------------------------------------------ adjoint

@@ -20,15 +20,15 @@
  *   - dimensionless oscillator units, hbar = m = 1            (Sec. 3.2)
  *   - imaginary time dt -> -i dtau, normalise after every
  *     step                                                    (Sec. 3.3)
- *   - optical lattice V0 cos^2(k y)                           (Sec. 5.2, Eq. 12)
- *   - cavity potential V_t + V_p + V_c + V_i                  (Sec. 5.3, Eqs. 13-16)
+ *   - optical lattice V0 cos^2(k y)                           (Sec. 5.2, Eq. 9)
+ *   - cavity potential V_t + V_p + V_c + V_i                  (Sec. 5.3, Eqs. 10-13)
  *   - cavity field driven by the overlap
- *     <psi| cos kx cos ky |psi>                               (Sec. 5.3, Eq. 17), here as
+ *     <psi| cos kx cos ky |psi>                               (Sec. 5.3, Eq. 14), here as
  *                                                              the driven-damped ODE
- *     d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta, whose fixed point is Eq. 17
+ *     d alpha/dt = (i Delta_c - kappa) alpha - i eta Theta, whose fixed point is Eq. 14
  *     with eta standing for N sqrt(V0 U0) and the undressed detuning (cavity = 1);
- *     or Eq. 17 itself, recomputed from the current density before every kick, with
- *     the dispersively shifted detuning of Eq. 18 (cavity = 2).
+ *     or Eq. 14 itself, recomputed from the current density before every kick, with
+ *     the dispersively shifted detuning of Eq. 15 (cavity = 2).
  *
  * The FFT is an iterative radix-2 Cooley-Tukey transform (bit reversal, then
  * butterflies) with every twiddle factor taken from cos/sin of its own index.
@@ -77,7 +77,7 @@ typedef struct {
     orc_sched sx, sy;
     /* cavity (Sec. 5.3): the pump is the y lattice, depth Vy(t), wavenumber kc.
      * cavity 0: off; 1: field from the driven-damped ODE (coupling eta); 2: field from
-     * the adiabatic expression of Eqs. 17-18 with n_atoms atoms (eta unused) */
+     * the adiabatic expression of Eqs. 14-15 with n_atoms atoms (eta unused) */
     int cavity;
     double vc, kc, delta_c, kappa, eta;
     /* optional extra static potential [ny][nx] (may be NULL) */
@@ -293,7 +293,7 @@ double orc_norm(const orc_problem *p, const cplx *psi)
     return s * da;
 }
 
-/* Theta = integral cos(kc x) cos(kc y) |psi|^2 dx dy  (Sec. 5.3, Eq. 17 numerator). */
+/* Theta = integral cos(kc x) cos(kc y) |psi|^2 dx dy  (Sec. 5.3, Eq. 14 numerator). */
 double orc_theta(const orc_problem *p, const cplx *psi)
 {
     double s = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
@@ -309,7 +309,7 @@ double orc_theta(const orc_problem *p, const cplx *psi)
 }
 
 /* C = integral cos^2(kc x) |psi|^2 dx dy, the overlap in the dispersive shift
- * (Sec. 5.3, Eq. 18). */
+ * (Sec. 5.3, Eq. 15). */
 double orc_cos2(const orc_problem *p, const cplx *psi)
 {
     double s = 0, da = (p->lx / p->nx) * (p->ly / p->ny);
@@ -323,7 +323,7 @@ double orc_cos2(const orc_problem *p, const cplx *psi)
     return s * da;
 }
 
-/* The adiabatic cavity field of the density of psi at time t (Sec. 5.3, Eqs. 17-18):
+/* The adiabatic cavity field of the density of psi at time t (Sec. 5.3, Eqs. 14-15):
  *   alpha = N sqrt(Vp(t) U0) Theta / (Delta_c~ + i kappa),
  *   Delta_c~ = Delta_c - N U0 C,
  * Theta and C per unit norm (psi describes one atom; N = n_atoms counts them in both
@@ -367,7 +367,7 @@ void orc_moments(const orc_problem *p, const cplx *psi, double *mx, double *my)
  * d alpha/dt = lambda alpha - i eta Theta(t), lambda = i Delta_c - kappa, with the
  * forcing extrapolated to second order, Theta_bar = (3 Theta_n - Theta_{n-1}) / 2:
  *   alpha_{n+1} = e^{lambda dt} alpha_n + (e^{lambda dt} - 1)/lambda * (-i eta Theta_bar).
- * Exact when Theta is constant.  (The adiabatic value of Sec. 5.3, Eq. 17, is this
+ * Exact when Theta is constant.  (The adiabatic value of Sec. 5.3, Eq. 14, is this
  * ODE's fixed point.) */
 static cplx cavity_advance(const orc_problem *p, cplx alpha, double theta_n, double theta_prev)
 {
@@ -593,7 +593,7 @@ static void hat_weights(const orc_sched *s, double t, int *i0, double *w0, doubl
  * its input (reconstructed exactly as zout e^{+i theta}, |z| = |zout|) and G the
  * gradient with respect to it.  Accumulates dL/dc into grad. */
 /* Backward through one kick with the adiabatic cavity field (cavity 2).  The field
- * alpha(rho, t) of Eqs. 17-18 depends on the density through Theta^ = Theta/Nrm and
+ * alpha(rho, t) of Eqs. 14-15 depends on the density through Theta^ = Theta/Nrm and
  * C^ = C/Nrm, so besides the local terms the kick has a global one:
  *   A = sum_x s dV/dalpha = 2 U0 alpha S_c + 2 sqrt(Vp U0) S_x    (S_c = sum s cos^2 kx,
  *       S_x = sum s cos kx cos ky, s = Im(conj(G') psi')),

@@ -6,7 +6,7 @@ It shares no code with the HIP path.
 
 Every routine marshals numpy arrays into the C oracle and back; the arithmetic
 lives in ``gpe_oracle.c`` (split step: paper Sec. 3.1; imaginary time: Sec. 3.3;
-cavity potential and field: Sec. 5.3, Eqs. 13-17).
+cavity potential and field: Sec. 5.3, Eqs. 10-14).
 """
 from __future__ import annotations
 
@@ -151,7 +151,7 @@ class Problem:
     ky_lat: float = 0.0
     sx: Sched = field(default_factory=Sched)
     sy: Sched = field(default_factory=Sched)
-    cavity: int = 0          # 0 off, 1 (True) field ODE, 2 adiabatic field (Eqs. 17-18)
+    cavity: int = 0          # 0 off, 1 (True) field ODE, 2 adiabatic field (Eqs. 14-15)
     vc: float = 0.0
     kc: float = 0.0
     delta_c: float = 0.0
@@ -286,7 +286,7 @@ def cos2(prob: Problem, psi) -> float:
 
 
 def alpha_adiabatic(prob: Problem, psi, t: float = 0.0) -> complex:
-    """The adiabatic cavity field of the density of psi at time t (Eqs. 17-18)."""
+    """The adiabatic cavity field of the density of psi at time t (Eqs. 14-15)."""
     lib().orc_alpha_adiabatic.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
     p, keep = prob.cstruct()
     a = _c128(psi)

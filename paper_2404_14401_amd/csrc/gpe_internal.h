@@ -20,7 +20,7 @@ struct PotDev {
     const float4 *ty;  // [ny]
     const float *vuser;  // [ny][nx] or null
     Sched sx, sy;
-    int cavity;  // 0 off, 1 field ODE, 2 adiabatic field (Sec. 5.3, Eqs. 17-18)
+    int cavity;  // 0 off, 1 field ODE, 2 adiabatic field (Sec. 5.3, Eqs. 14-15)
     double vc;
     // cavity field step: alpha_{n+1} = ecav alpha_n + phi1 (-i eta Theta_bar)
     double ecav_re, ecav_im, phi1_re, phi1_im, eta;

@@ -1266,7 +1266,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     }
     const double tk = I.st->t0 + kick * gd.dt;
     const double tau = (MODE == ADJ_MID) ? gd.dt : 0.5 * gd.dt;
-    // adiabatic field (Sec. 5.3, Eqs. 17-18): alpha of the kicked density and the global
+    // adiabatic field (Sec. 5.3, Eqs. 14-15): alpha of the kicked density and the global
     // adjoint term of its density dependence, from the probe sums of this member
     double are = 0.0, aim = 0.0, bth = 0.0, bc = 0.0, thn = 0.0, c2n = 0.0, inv0 = 0.0, extra = 0.0;
     if (I.aprobe) {

@@ -121,8 +121,8 @@ template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], dou
     __syncthreads();
 }
 
-// Adiabatic cavity field (Sec. 5.3, Eqs. 17-18) of a density with integrals nrm,
-// Theta = th and C = c2 at time t, with the on-axis probe of Sec. 5.4:
+// Adiabatic cavity field (Sec. 5.3, Eqs. 14-15) of a density with integrals nrm,
+// Theta = th and C = c2 at time t, with the on-axis probe of Sec. 5.4 (Eq. 17):
 //   [N sqrt(Vp(t) U0) (th/nrm) + Omega_c e^{i (Delta_p t + phi)}] / (Delta_c - N U0 c2/nrm + i kappa).
 __device__ __forceinline__ void alpha_adiabatic(const PotDev &p, double t, double nrm, double th, double c2,
                                                 double *are, double *aim)

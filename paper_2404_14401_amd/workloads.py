@@ -159,7 +159,7 @@ CAVITY_1024_STEPS = 20000
 
 
 def cavity_1024_adiabatic(seed: int = 0) -> Setup:
-    """The cavity run with the adiabatic field of Sec. 5.3 (Eqs. 17-18) in place of the
+    """The cavity run with the adiabatic field of Sec. 5.3 (Eqs. 14-15) in place of the
     field ODE: N = eta / sqrt(Vp Vc), so that N sqrt(Vp Vc) is the ODE's coupling, and
     the dispersive shift N Vc C that the ODE leaves out."""
     s = cavity_1024(seed)

@@ -1,4 +1,4 @@
-"""The adiabatic cavity field (Sec. 5.3, Eqs. 17-18: alpha from the current density, with
+"""The adiabatic cavity field (Sec. 5.3, Eqs. 14-15: alpha from the current density, with
 the dispersively shifted detuning) on the GPU against the FP64 oracle, on both paths,
 in real and imaginary time, and in batched form over a Fig. 5-shaped sweep."""
 import numpy as np

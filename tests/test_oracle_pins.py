@@ -330,7 +330,7 @@ def test_cavity_field_with_frozen_overlap_has_closed_form():
     """With Vc = 0 and no pump the potential ignores alpha; the real-time discrete
     Gaussian is stationary in |psi|, so Theta is constant and alpha must follow
     alpha(t) = e^{lambda t} alpha_0 + (e^{lambda t} - 1)/lambda (-i eta Theta),
-    tending to the adiabatic value eta Theta / (Delta_c + i kappa) (Sec. 5.3, Eq. 17)."""
+    tending to the adiabatic value eta Theta / (Delta_c + i kappa) (Sec. 5.3, Eq. 14)."""
     dt = 0.01
     s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dt, g=0.0, cavity=True, vc=0.0, kc=0.7,
                 delta_c=-3.0, kappa=1.5, eta=2.0, alpha0=0.1 + 0.05j)
@@ -347,6 +347,81 @@ def test_cavity_field_with_frozen_overlap_has_closed_form():
     ref = np.exp(lam * t) * s.alpha0 + (np.exp(lam * t) - 1) / lam * (-1j * s.eta * th)
     assert np.abs(obs[:, 2] + 1j * obs[:, 3] - ref).max() < 1e-10
     assert abs(ref[-1] - s.eta * th / (s.delta_c + 1j * s.kappa)) < np.exp(-s.kappa * t[-1])
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_cavity_potential_is_the_intensity_of_pump_plus_cavity_field(sign):
+    """Sec. 5.3, Eqs. 10-13: pump, cavity and interference lattices together are the
+    light shift of the two interfering standing waves, sign * |sqrt|V0| cos(ky) +
+    sign * sqrt|U0| alpha cos(kx)|^2 (sign: blue (+) or red (-) detuning, V0 and U0
+    alike), on top of the trap.  A wrong power of |alpha|, a dropped factor 2 or
+    square root, or a swapped cos(kx)/cos(ky) breaks the identity at k != 0."""
+    vp, u0, alpha, k = 2.3 * sign, 1.7 * sign, 0.7 + 0.4j, 0.9
+    s = W.Setup(nx=32, ny=16, lx=12.0, ly=8.0, dt=0.01, g=5.0, wx=0.8, wy=1.3, x0=0.2, y0=-0.3, ky_lat=k,
+                sy=W.Schedule("const", vp), cavity=True, vc=u0, kc=k, delta_c=-3.0, kappa=1.0)
+    v = O.potential(problem(s), 0.0, alpha)
+    x, y = np.meshgrid(s.xs(), s.ys())
+    trap = 0.5 * 0.8**2 * (x - 0.2) ** 2 + 0.5 * 1.3**2 * (y + 0.3) ** 2
+    field = np.sqrt(abs(vp)) * np.cos(k * y) + sign * np.sqrt(abs(u0)) * alpha * np.cos(k * x)
+    assert np.abs(v - (trap + sign * np.abs(field) ** 2)).max() < 1e-12
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_cavity_field_enters_the_kick_phase_exactly(sign):
+    """A uniform condensate with kc = ky_lat = 0 (every cosine is 1), no trap and a
+    frozen field (Delta_c = kappa = eta = 0, so alpha stays alpha_0) is an exact
+    eigenstate of the kinetic step; each real-time step then multiplies it by
+    exp(-i (V0 + U0 |alpha|^2 + 2 sqrt(V0 U0) Re alpha + g |psi|^2) dt) (Sec. 5.3,
+    Eqs. 10-13 at the lattice maxima, Sec. 3.1 kick)."""
+    vp, u0, alpha0, dt, g, n = 2.3 * sign, 1.7 * sign, 0.7 + 0.4j, 0.01, 3.0, 50
+    s = W.Setup(nx=16, ny=16, lx=8.0, ly=8.0, dt=dt, g=g, wx=0.0, wy=0.0, sy=W.Schedule("const", vp),
+                cavity=True, vc=u0, kc=0.0, alpha0=alpha0)
+    psi0 = W.normalise(s, np.full((16, 16), 0.6 + 0.8j))
+    out, obs = O.step_real(problem(s), state(s), psi0, n, want_obs=True)
+    assert np.abs(obs[:, 2] + 1j * obs[:, 3] - alpha0).max() == 0.0
+    rho = abs(psi0[0, 0]) ** 2
+    light = sign * abs(np.sqrt(abs(vp)) + sign * np.sqrt(abs(u0)) * alpha0) ** 2
+    ref = psi0 * np.exp(-1j * (light + g * rho) * n * dt)
+    assert np.abs(out - ref).max() < 1e-13 * np.abs(psi0).max() * n
+
+
+def test_cavity_field_forcing_is_second_order():
+    """Atoms decoupled from the field (U0 = V0 = 0) and a coherent state oscillating in
+    a unit trap, x(t) = d cos t, so the overlap follows the closed form Theta(t) =
+    e^{-kc^2/2} cos(kc d cos t) (|psi|^2 a unit-variance-1/2 Gaussian).  The field must
+    then approach the exact solution of d alpha/dt = (i Delta_c - kappa) alpha - i eta
+    Theta(t) (the configuration's ODE, whose fixed point is Sec. 5.3, Eq. 14) at second
+    order in dt: the error falls 4x per halving.  Forcing with Theta_n alone, with the
+    history swapped or shifted by one step converges at first order (ratio 2, and an
+    error ~100x larger at these steps)."""
+    from scipy import integrate
+
+    kc, d, dc, kap, eta, T = 1.3, 1.5, -3.0, 1.0, 2.0, 4.0
+    lam = 1j * dc - kap
+    theta = lambda t: np.exp(-kc**2 / 2) * np.cos(kc * d * np.cos(t))
+
+    def exact(tc):
+        f = lambda u, part: part(np.exp(lam * (tc - u)) * (-1j * eta * theta(u)))
+        return complex(*[integrate.quad(f, 0.0, tc, args=(part,), epsabs=1e-14, epsrel=1e-13, limit=200)[0]
+                         for part in (np.real, np.imag)])
+
+    checks = (1.0, 2.0, 3.0, 4.0)
+    ref = {tc: exact(tc) for tc in checks}
+    errs, th_errs = [], []
+    for dt in (0.02, 0.01, 0.005):
+        s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=dt, g=0.0, cavity=True, vc=0.0, kc=kc, delta_c=dc,
+                    kappa=kap, eta=eta)
+        x, y = np.meshgrid(s.xs(), s.ys())
+        psi0 = W.normalise(s, np.exp(-((x - d) ** 2 + y**2) / 2).astype(complex))
+        _, obs = O.step_real(problem(s), state(s), psi0, int(round(T / dt)), want_obs=True)
+        alpha = obs[:, 2] + 1j * obs[:, 3]
+        errs.append(max(abs(alpha[int(round(tc / dt)) - 1] - ref[tc]) for tc in checks))
+        t = dt * np.arange(1, obs.shape[0] + 1)
+        th_errs.append(np.abs(obs[:, 1] - theta(t)).max())
+    assert max(th_errs) < 2e-4   # the driver itself follows its closed form (to the splitting error)
+    assert errs[1] < 1e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4
 
 
 # ------------------------------------------------------------ adjoint (p15)
@@ -408,7 +483,7 @@ def test_pump_control_adjoint_matches_central_differences_and_transposition(loss
 
 @pytest.mark.parametrize("control", ["y", "x"])
 def test_adjoint_through_the_adiabatic_cavity_matches_central_differences(control):
-    """With the adiabatic field on (Eqs. 17-18, probe included) the kick's phase depends
+    """With the adiabatic field on (Eqs. 14-15, probe included) the kick's phase depends
     on the whole density through alpha; the adjoint's global term must reproduce
     central differences for pump (y) and x-lattice knots.  The cavity moves the
     gradient by ~10%, so a missing or wrong global term fails."""
@@ -596,7 +671,7 @@ def test_momentum_orders_of_known_plane_waves(axis):
         O.momentum_orders(problem(s), O.fft2d(psi), axis, B, (n_ax // B + 1) // 2)
 
 
-# ----------------------------------- adiabatic cavity field (Sec. 5.3, Eqs. 17-18)
+# ----------------------------------- adiabatic cavity field (Sec. 5.3, Eqs. 14-15)
 
 def adiabatic_setup(**kw):
     base = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=2e-3, g=10.0, x0=0.3, ky_lat=2.0,
