@@ -39,7 +39,7 @@ def log(*a):
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_engine.h", "physics.h", "gpe_internal.h"):
+    for f in ("kernels.h", "kernels_plan.hip", "fft_engine.h", "physics.h", "gpe_internal.h"):
         with open(os.path.join(HERE, "paper_2404_14401_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

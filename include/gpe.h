@@ -34,9 +34,11 @@
  * Conventions of every entry point:
  *   - return 0 (GPE_OK) or a negative GPE_ERR_* code; no exception crosses the ABI;
  *     gpe_last_error() gives a thread-local message for the last failure.
- *   - argument errors are reported immediately; device-side failures (non-finite
- *     values found by the fused reductions) are reported by the next synchronising
- *     call (gpe_sync, gpe_energy, gpe_norm, gpe_get_cavity).
+ *   - argument errors are reported immediately; device-side failures (a NaN or an
+ *     infinity in psi, seen by every kicking pass whether or not it reduces anything)
+ *     are reported by the next synchronising call (gpe_sync, gpe_get_cavity; batches:
+ *     gpe_batch_sync, gpe_batch_get_cavity); gpe_norm and gpe_energy report a
+ *     non-finite input of their own.
  *   - device pointers are caller-owned and must stay valid until the work queued on
  *     the plan's stream has finished; all work is queued on that stream.
  *   - a plan or batch must not be used from two threads at once.
@@ -55,7 +57,7 @@ extern "C" {
 #define GPE_ERR_INVALID (-1)     /* bad argument or plan state */
 #define GPE_ERR_NOMEM (-2)       /* device allocation failed or exceeds max_bytes */
 #define GPE_ERR_DEVICE (-3)      /* HIP runtime error */
-#define GPE_ERR_NONFINITE (-4)   /* NaN/Inf detected in psi by a fused reduction */
+#define GPE_ERR_NONFINITE (-4)   /* NaN/Inf detected in psi by a kick or a reduction */
 #define GPE_ERR_UNSUPPORTED (-5) /* valid request the library does not implement */
 
 typedef struct gpe_plan gpe_plan;
@@ -168,7 +170,8 @@ int gpe_step_imag(gpe_plan *plan, gpe_c64 *psi, int64_t nsteps, double t, double
 /* Energy functional of psi at time t with the plan's current cavity field
  * (synchronous): out = {E_kin, E_pot, E_int, E, mu, norm}, each per unit norm,
  * E_kin = sum_k |k|^2/2 |psi_k|^2 from the spectrum, E_int = g/2 int |psi|^4,
- * mu = E_kin + E_pot + 2 E_int. */
+ * mu = E_kin + E_pot + 2 E_int.  GPE_ERR_NONFINITE (out still written) if a sum is not
+ * finite. */
 int gpe_energy(gpe_plan *plan, const gpe_c64 *psi, double t, double out[6]);
 
 /* Populations of the momentum orders |2 n hbar k> of a Fourier-space state (Sec. 5.2:
@@ -182,7 +185,8 @@ int gpe_energy(gpe_plan *plan, const gpe_c64 *psi, double t, double out[6]);
  * {0, 1}, order_step < 1, or (2 nmax + 1) order_step above the points on the axis. */
 int gpe_momentum_orders(gpe_plan *plan, const gpe_c64 *psik, int axis, int order_step, int nmax, double *out);
 
-/* sum |psi|^2 dx dy (synchronous). */
+/* sum |psi|^2 dx dy (synchronous); GPE_ERR_NONFINITE (out still written) if it is not
+ * finite. */
 int gpe_norm(gpe_plan *plan, const gpe_c64 *psi, double *out);
 
 /* Cavity state (synchronous): {Re alpha, Im alpha, Theta_n, Theta_{n-1}}; and its
@@ -229,6 +233,13 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path);
  * radix, row threads per work-group, column work-groups per member, number of groups}. */
 int gpe_batch_info(gpe_batch *b, int group, int out[8]);
 
+/* Wait for the batch's queued work and report deferred device errors: GPE_ERR_NONFINITE
+ * if any member's wave function held a NaN or an infinity when one of its kicks (or, for
+ * members kept in LDS, the end of a call) read it; first_bad (nullable, host) receives
+ * the lowest such member index, -1 if none.  Like gpe_sync, the flag stays set until the
+ * batch is destroyed. */
+int gpe_batch_sync(gpe_batch *b, int *first_bad);
+
 /* Cavity state of batch member m after the batch's last call, as gpe_get_cavity
  * (synchronous).  Members may carry either cavity model: the field ODE (its overlap
  * history carries over between calls, as on a plan) or the adiabatic field of Sec. 5.3,
@@ -258,11 +269,13 @@ int gpe_batch_get_cavity(gpe_batch *b, int member, double out[4]);
  * calls, GPE_ERR_NOMEM if the device cannot hold it), so the reverse sweep transforms
  * the adjoint alone: the fastest mode where HBM allows it.
  * psi0, target: host arrays of nb device pointers ([ny][nx] gpe_c64 each; target may
- * be null for the energy loss and is ignored there); knots: host, nb * nknots values (they replace the
- * members' knots of the controlled lattice); loss: host, nb values; grad: host,
- * nb * nknots values;
+ * be null for the energy loss and is ignored there); knots: host, nb * nknots finite values (they replace
+ * the members' knots of the controlled lattice; pump knots of a cavity member must be nonzero with the
+ * sign of vc; GPE_ERR_INVALID otherwise, before anything runs); loss: host, nb values; grad: host,
+ * nb * nknots values, or NULL for the loss alone (the forward sweep only: no reverse sweep, no
+ * checkpoints or stored trajectory, mode ignored);
  * psi_final (nullable): host array of nb device pointers receiving psi(T).
- * info (nullable): host, 4 doubles {mode used (1 reconstruct, 2 checkpoint, 3 store),
+ * info (nullable): host, 4 doubles {mode used (0 loss alone, 1 reconstruct, 2 checkpoint, 3 store),
  * reconstruction drift, peak scratch bytes, number of forward steps run}. */
 #define GPE_LOSS_FIDELITY 0
 #define GPE_LOSS_ENERGY 1

@@ -3,8 +3,10 @@ infidelity (or energy) of a batch of condensates with respect to their lattice-d
 controls.
 
 Forward runs the real-time split step on every member with the given knot values and
-returns the per-member losses; backward returns the discrete-adjoint gradient that
-the same call computed (the reverse sweep reuses the forward's final state)."""
+returns the per-member losses; when the knots need a gradient the same call also runs
+the discrete adjoint's reverse sweep (reusing the forward's final state), whose result
+backward returns.  A loss-only evaluation (no_grad, or knots without requires_grad)
+runs the forward sweep alone."""
 from __future__ import annotations
 
 import numpy as np
@@ -24,9 +26,11 @@ class GPEControl(torch.autograd.Function):
     @staticmethod
     def forward(ctx, knots, batch, psi0s, targets, nsteps, t0=0.0, mode="auto", control="x", loss="fidelity"):
         k = knots.detach().to("cpu", torch.float64).numpy()
+        want = bool(ctx.needs_input_grad[0])
         loss, grad, info = gpe.adjoint(batch, psi0s, targets, nsteps, k, t0=t0, mode=mode, control=control,
-                                       loss=loss)
-        ctx.save_for_backward(torch.from_numpy(grad).to(knots.device))
+                                       loss=loss, want_grad=want)
+        if want:
+            ctx.save_for_backward(torch.from_numpy(grad).to(knots.device))
         ctx.info = info
         return torch.from_numpy(loss).to(knots.device)
 

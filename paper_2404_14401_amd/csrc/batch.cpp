@@ -68,6 +68,7 @@ struct gpe_batch {
     hipEvent_t ev_in = nullptr, ev_fork = nullptr, ev_side = nullptr, ev_out = nullptr;
     DevState **d_states = nullptr;     // every member
     DevState **d_states_mp = nullptr;  // members of multi-pass groups
+    int *d_flags = nullptr;            // gathered non-finite flags (gpe_batch_sync)
     int n_mp = 0;
     std::vector<void *> allocs;
     bool has_ode = false;  // some multi-pass member has the field ODE
@@ -278,6 +279,7 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
     std::vector<DevState *> states(n);
     for (int i = 0; i < n; ++i) states[i] = b->plans[i]->st;
     if ((rc = balloc(b, (void **)&b->d_states, sizeof(DevState *) * n))) return cleanup(rc);
+    if ((rc = balloc(b, (void **)&b->d_flags, sizeof(int) * n))) return cleanup(rc);
     HIP_OK(hipMemcpy(b->d_states, states.data(), sizeof(DevState *) * n, hipMemcpyHostToDevice));
     // the time base of multi-pass members is advanced by the graph while the LDS groups
     // (side stream) read theirs, so the two sets are kept apart
@@ -392,7 +394,12 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
         if (!g.lds) continue;
         if (!side_used) HIP_OK(hipStreamWaitEvent(b->side, b->ev_fork, 0));
         side_used = true;
-        LAUNCH_OK(launch_lds_batched(g.nx, g.ny, g.d_lds, (int)g.members.size(), b->side));
+        // bounded launches (about 2^26 point-steps per member each): a long call is a
+        // sequence of kernels of well under a second, not one kernel of minutes
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(1 << 20, (1LL << 26) / ((int64_t)g.nx * g.ny)));
+        for (int64_t s0 = 0; s0 < nsteps; s0 += chunk)
+            LAUNCH_OK(launch_lds_batched(g.nx, g.ny, g.d_lds, (int)g.members.size(), s0,
+                                         (int)std::min<int64_t>(chunk, nsteps - s0), b->side));
     }
     if (side_used) HIP_OK(hipEventRecord(b->ev_side, b->side));
     // multi-pass groups
@@ -543,6 +550,24 @@ int gpe_batch_info(gpe_batch *b, int group, int out[8])
     out[5] = g.shape.row_threads;
     out[6] = g.shape.col_blocks;
     out[7] = (int)b->groups.size();
+    return GPE_OK;
+}
+
+int gpe_batch_sync(gpe_batch *b, int *first_bad)
+{
+    if (!b) return fail(GPE_ERR_INVALID, "null batch");
+    if (first_bad) *first_bad = -1;
+    HIP_OK(hipStreamSynchronize(b->work));
+    HIP_OK(hipStreamSynchronize(b->side));
+    std::vector<int> flags((size_t)b->n, 0);
+    LAUNCH_OK(launch_gather_flags(b->d_states, b->n, b->d_flags, b->work));
+    HIP_OK(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int) * (size_t)b->n, hipMemcpyDeviceToHost, b->work));
+    HIP_OK(hipStreamSynchronize(b->work));
+    for (int i = 0; i < b->n; ++i)
+        if (flags[i]) {
+            if (first_bad) *first_bad = i;
+            return fail(GPE_ERR_NONFINITE, "non-finite values in the wave function of batch member " + std::to_string(i));
+        }
     return GPE_OK;
 }
 
@@ -749,13 +774,13 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     if (control != GPE_CONTROL_X_LATTICE && control != GPE_CONTROL_PUMP)
         return fail(GPE_ERR_INVALID, "control must be GPE_CONTROL_X_LATTICE or GPE_CONTROL_PUMP");
     const bool pump = control == GPE_CONTROL_PUMP;
-    if (!b || !psi0 || !loss || !grad || nsteps < 1 || !knots)
-        return fail(GPE_ERR_INVALID, "null argument or nsteps < 1");
+    if (!b || !psi0 || !loss || nsteps < 1 || !knots) return fail(GPE_ERR_INVALID, "null argument or nsteps < 1");
+    const bool loss_only = grad == nullptr;  // forward sweep and loss, no reverse sweep
     if (loss_kind != GPE_LOSS_FIDELITY && loss_kind != GPE_LOSS_ENERGY) return fail(GPE_ERR_INVALID, "bad loss kind");
     const bool energy = loss_kind == GPE_LOSS_ENERGY;
     if (!energy && !target) return fail(GPE_ERR_INVALID, "fidelity loss needs target states");
     if (mode < GPE_ADJ_AUTO || mode > GPE_ADJ_STORE) return fail(GPE_ERR_INVALID, "bad adjoint mode");
-    const bool store = mode == GPE_ADJ_STORE;
+    const bool store = mode == GPE_ADJ_STORE && !loss_only;
     if (nsteps > (1 << 28)) return fail(GPE_ERR_INVALID, "nsteps too large");
     const int nb = b->n;
     const int nx = b->plans[0]->nx, ny = b->plans[0]->ny;
@@ -770,6 +795,16 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         if (energy && p->pot.cavity != GPE_CAVITY_OFF)
             return fail(GPE_ERR_UNSUPPORTED, "the energy loss with a cavity (fidelity only there)");
         if (!psi0[i] || (!energy && !target[i])) return fail(GPE_ERR_INVALID, "null member state");
+        // the knots replace the controlled schedule's values: the checks gpe_set_potential
+        // applies to a schedule apply to them too
+        for (int m = 0; m < nknots; ++m) {
+            const double k = knots[(size_t)i * nknots + m];
+            if (!std::isfinite(k)) return fail(GPE_ERR_INVALID, "knot values must be finite");
+            // the interference lattice's sqrt(Vp U0) needs the pump and U0 on one side of
+            // zero, and its derivative by Vp is singular at Vp = 0
+            if (pump && p->pot.cavity != GPE_CAVITY_OFF && !(k * p->pot.vc > 0))
+                return fail(GPE_ERR_INVALID, "pump knots of a cavity member must share the sign of vc and be nonzero");
+        }
     }
     if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
     // launch shape of the adjoint's passes: 256 threads per row work-group and at least
@@ -792,7 +827,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     AdjWork *w = adj_work(b);
     const int64_t seg = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
     const int64_t nseg = (nsteps + seg - 1) / seg;
-    int rc = adj_alloc(b, w, nx, ny, nb, nsteps, (mode == GPE_ADJ_AUTO || mode == GPE_ADJ_CHECKPOINT) ? (int)nseg : 0,
+    int rc = adj_alloc(b, w, nx, ny, nb, nsteps,
+                       (!loss_only && (mode == GPE_ADJ_AUTO || mode == GPE_ADJ_CHECKPOINT)) ? (int)nseg : 0,
                        store ? nsteps : 0);
     if (rc) return rc;
     const size_t npts = (size_t)nx * ny;
@@ -868,6 +904,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
             HIP_OK(hipMemcpyAsync(w->d_pa, pa.data(), sizeof(void *) * nb, hipMemcpyHostToDevice, b->work));
             LAUNCH_OK(launch_scaled_copy(w->d_dst, w->d_pa, w->d_coef, npts, nb, 64, b->work));
         }
+        *drift = 0;
+        if (loss_only) return GPE_OK;
         if (checkpoint) {
             for (int64_t s = nseg - 1; s >= 0; --s) {
                 const int64_t e = std::min(nsteps, (s + 1) * seg);
@@ -894,8 +932,19 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     };
 
     double drift = 0;
-    bool ckpt = (mode == GPE_ADJ_CHECKPOINT);
+    bool ckpt = (mode == GPE_ADJ_CHECKPOINT) && !loss_only;
     if ((rc = run(ckpt, &drift))) return rc;
+    if (loss_only) {
+        if (info) {
+            info[0] = 0;
+            info[1] = 0;
+            info[2] = (double)w->bytes;
+            info[3] = (double)nsteps;
+        }
+        HIP_OK(hipEventRecord(b->ev_out, b->work));
+        HIP_OK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+        return GPE_OK;
+    }
     int64_t fwd_steps = nsteps;
     if (mode == GPE_ADJ_AUTO && !(drift <= drift_tol)) {
         if ((rc = adj_alloc(b, w, nx, ny, nb, nsteps, (int)nseg))) return rc;

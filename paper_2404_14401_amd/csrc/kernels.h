@@ -1,4 +1,6 @@
-// kernels.hip -- gfx950 kernels of the split-step GPE path and their launchers.
+#pragma once
+// kernels.h -- device code of the split-step GPE path shared by the kernel sources
+// (kernels_plan.hip, kernels_batch.hip, kernels_adj.hip): pass bodies and kernel templates.
 //
 // Multi-pass path (any size): a step is a row pass and a column pass over the caller's
 // complex64 array, updated in place.  Between passes the array holds the x-transformed
@@ -37,6 +39,9 @@ namespace gpe {
 #ifndef GPE_ADJ_TW_LDS
 #define GPE_ADJ_TW_LDS 1
 #endif
+// host-side helper defined with the plan's launchers (threads of an LDS-resident grid)
+int lds_threads(int nx, int ny);
+
 constexpr int kRadix = GPE_RADIX;
 constexpr int kLgR = ilog2(GPE_RADIX);
 #if GPE_XCHG_FLOAT
@@ -68,22 +73,7 @@ __device__ __forceinline__ void store_c64(float2 *p, double2 v)
 #endif
 }
 
-int kernel_radix() { return kRadix; }
-size_t xchg_bytes() { return sizeof(XchgT); }
-// extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
-size_t staged_table_bytes(int n) { return GPE_TW_LDS ? (size_t)n * (sizeof(double2) + sizeof(float4)) : 0; }
-// LDS of the adjoint passes: exchange areas for `arrays` lines (state and adjoint, or the
-// adjoint alone) plus the tables
-size_t adj_row_shmem(int n, int lines, int r, int arrays)
-{
-    const size_t words = (size_t)n + (n >> ilog2(r));
-    return align16(arrays * lines * words * sizeof(XchgT)) + (size_t)n * (sizeof(double2) + sizeof(float4));
-}
-size_t adj_col_shmem(int n, int w, int r, int arrays)
-{
-    const size_t words = (size_t)n * w + (n >> ilog2(r)) + w;
-    return align16(arrays * words * sizeof(XchgT)) + (size_t)n * 2 * sizeof(double2);
-}
+
 
 // --------------------------------------------------------------------- row pass
 // One work-group transforms `lines` rows.  `row` is this thread's row; the caller has
@@ -187,6 +177,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, twx);
 
     double part[NPART] = {};
+    double fin = 0.0;  // sum of this thread's densities: non-finite iff one of its points is
     if constexpr (MODE == ROW_ENTRY && IMAG) {
         const double sc = st->scale;
 #pragma unroll
@@ -200,6 +191,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
         double V = vpoint(vl, tx);
         if (vu) V += (double)vu[i];
         const double d = v[m].x * v[m].x + v[m].y * v[m].y;
+        fin += d;
         if constexpr (MODE == ROW_FWD) {
             part[0] += d;
             part[1] += V * d;
@@ -229,6 +221,10 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
             }
         }
     }
+    // every kicking pass flags a non-finite input, whether or not it reduces anything
+    // (a plain store of the same value from any work-group: no atomics needed)
+    if constexpr (MODE != ROW_FWD)
+        if (!isfinite(fin)) st->nonfinite = 1;
     if constexpr (!IMAG && (MODE == ROW_ENTRY || MODE == ROW_MID)) {
         // the adjoint's stored trajectory: this kick's output in real space
         if (traj)
@@ -483,100 +479,6 @@ __global__ void __launch_bounds__(1024) col_pass_b(BatchPassArgs a)
     col_body<N, R, COL_KIN_REAL>(I.psi, I.psi, I.grid, nullptr, lt, a.per_wg, smem, red);
 }
 
-// --------------------------------------------------------------- small kernels
-__global__ void __launch_bounds__(256) tail_kernel(TailArgs ta, GridDev gd, PotDev pot, DevState *st)
-{
-    __shared__ double red[4 * NPART];
-    run_tail(ta, gd, pot, st, red);
-}
-
-// psi <- psi * st->scale (final renormalisation in imaginary time)
-__global__ void __launch_bounds__(256) scale_kernel(float2 *psi, size_t n, const DevState *st)
-{
-    const double sc = st->scale;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        float2 p = psi[i];
-        psi[i] = make_float2((float)(p.x * sc), (float)(p.y * sc));
-    }
-}
-
-// Start of a call: record its first time; imaginary time starts unscaled.
-__global__ void set_call_kernel(DevState *st, double t0, int reset_scale, int clear_history)
-{
-    if (threadIdx.x == 0) {
-        st->t0 = t0;
-        if (reset_scale) st->scale = 1.0;
-        if (clear_history) st->have_theta = 0;
-    }
-}
-
-// sum |psi|^2 per work-group (norm)
-__global__ void __launch_bounds__(256) norm_kernel(const float2 *psi, size_t n, double *partials)
-{
-    __shared__ double red[4 * 1];
-    double s[1] = {0.0};
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        float2 p = psi[i];
-        s[0] += (double)p.x * p.x + (double)p.y * p.y;
-    }
-    block_sum<1>(s, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
-}
-
-// Marginals of |psi|^2: axis 1 sums every row (out[j], one work-group per row), axis 0
-// every column (out[i]; a work-group owns 64 columns, its four waves take every fourth
-// row and are combined in a fixed order).  Fixed summation order throughout.
-__global__ void __launch_bounds__(256) marginal_kernel(const float2 *psi, int nx, int ny, int axis, double *out)
-{
-    __shared__ double red[4 * 64];
-    if (axis == 1) {
-        const float2 *row = psi + (size_t)blockIdx.x * nx;
-        double s[1] = {0.0};
-        for (int i = threadIdx.x; i < nx; i += blockDim.x) s[0] += (double)row[i].x * row[i].x + (double)row[i].y * row[i].y;
-        block_sum<1>(s, red);
-        if (threadIdx.x == 0) out[blockIdx.x] = s[0];
-        return;
-    }
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int col = blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (col < nx)
-        for (int j = q; j < ny; j += 4) {
-            const float2 p = psi[(size_t)j * nx + col];
-            s += (double)p.x * p.x + (double)p.y * p.y;
-        }
-    red[q * 64 + lane] = s;
-    __syncthreads();
-    if (q == 0 && col < nx) out[col] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
-}
-
-// Terminal adjoint of the energy loss (one work-group per row): with lam = T psi on
-// entry, lam <- 2 dA (T psi + (V(t) + g|psi|^2) psi), the gradient of E_kin + E_pot +
-// E_int; partials[row] = dA sum_x w(x) |psi|^2, the loss's derivative by the depth of
-// the controlled lattice (w = cos^2 along x, or along y for axis 1).
-__global__ void __launch_bounds__(256) energy_grad_kernel(const float2 *psi, float2 *lam, GridDev gd, PotDev pot,
-                                                          const DevState *st, int axis, double *partials)
-{
-    __shared__ double red[4];
-    const int row = blockIdx.x, nx = gd.nx;
-    const VLine vl = vline_cav(pot, row, st->t0, st->alpha_re, st->alpha_im);
-    const float4 ty = pot.ty[row];
-    const float *vu = pot.vuser ? pot.vuser + (size_t)row * nx : nullptr;
-    double s[1] = {0.0};
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        const size_t q = (size_t)row * nx + i;
-        const float4 tx = pot.tx[i];
-        const float2 p = psi[q], l = lam[q];
-        const double d = (double)p.x * p.x + (double)p.y * p.y;
-        double V = vpoint(vl, tx);
-        if (vu) V += (double)vu[i];
-        const double f = V + gd.g * d;
-        lam[q] = make_float2((float)(2.0 * gd.dA * ((double)l.x + f * p.x)), (float)(2.0 * gd.dA * ((double)l.y + f * p.y)));
-        s[0] += (axis ? (double)ty.y : (double)tx.y) * d;
-    }
-    block_sum<1>(s, red);
-    if (threadIdx.x == 0) partials[row] = s[0] * gd.dA;
-}
 
 // ------------------------------------------------------------- whole grid in LDS
 // One work-group owns one grid for all steps; psi stays in LDS as complex64 (row pitch
@@ -587,7 +489,10 @@ __global__ void __launch_bounds__(256) energy_grad_kernel(const float2 *psi, flo
 // a line in both the row and the column sweeps.
 constexpr int kLdsRadix = 8;
 
-template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs &a)
+// s0, nsteps: this launch runs steps s0 .. s0 + nsteps - 1 of the call (long batched
+// calls are split into launches of bounded length; real-time kicks are timed from
+// st->t0 + s0 dt).
+template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs &a, int64_t s0, int nsteps)
 {
     using C = double2;
     constexpr int R = kLdsRadix;
@@ -609,7 +514,7 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
     const bool cav = pot.cavity == 1 && !a.imag;  // field ODE (real time only)
     const bool adia = pot.cavity == 2;             // adiabatic field, both times
     const bool want = cav || adia || a.obs != nullptr || a.imag;
-    const double t0 = st->t0;
+    const double t0 = a.imag ? st->t0 : st->t0 + (double)s0 * gd.dt;
 
     for (int i = threadIdx.x; i < NX * NY; i += NTH) g[(i / NX) * P + (i % NX)] = a.psi[i];
     if (threadIdx.x == 0) {
@@ -735,7 +640,7 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
         __syncthreads();
     }
 
-    for (int n = 0; n < a.nsteps; ++n) {
+    for (int n = 0; n < nsteps; ++n) {
         const double tn = a.imag ? t0 : t0 + n * gd.dt;
         const double tn1 = a.imag ? t0 : t0 + (n + 1) * gd.dt;
         const double are0 = s_are, aim0 = s_aim, sc = s_scale;
@@ -785,10 +690,15 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
         }
     }
     const double sc = s_scale;
+    double fin = 0.0;
     for (int i = threadIdx.x; i < NX * NY; i += NTH) {
         float2 f = g[(i / NX) * P + (i % NX)];
+        fin += (double)f.x * f.x + (double)f.y * f.y;
         a.psi[i] = make_float2((float)(f.x * sc), (float)(f.y * sc));
     }
+    // the state returned is checked even where no reduction ran during the steps
+    if (!isfinite(fin)) st->nonfinite = 1;
+    __syncthreads();
     if (threadIdx.x == 0) {
         st->alpha_re = s_are;
         st->alpha_im = s_aim;
@@ -804,383 +714,17 @@ template <int NX, int NY> __device__ __forceinline__ void lds_body(const LdsArgs
 template <int NX, int NY>
 __global__ void __launch_bounds__((NX * NY / kLdsRadix) < 1024 ? NX * NY / kLdsRadix : 1024) lds_grid(LdsArgs a)
 {
-    lds_body<NX, NY>(a);
+    lds_body<NX, NY>(a, 0, a.nsteps);
 }
 
 // Batched: work-group b runs member b of the batch for all steps.
 template <int NX, int NY>
 __global__ void __launch_bounds__((NX * NY / kLdsRadix) < 1024 ? NX * NY / kLdsRadix : 1024)
-    lds_grid_b(const LdsArgs *arr)
+    lds_grid_b(const LdsArgs *arr, int64_t s0, int nsteps)
 {
-    lds_body<NX, NY>(arr[blockIdx.x]);
+    lds_body<NX, NY>(arr[blockIdx.x], s0, nsteps);
 }
 
-// ------------------------------------------------------------------- launchers
-// With e0/e1, the launch records the kernel's own start and end in those events
-// (hipExtLaunchKernel), which times the kernel without extra queue markers.
-template <int N> static hipError_t row_dispatch(int mode, bool imag, const RowArgs &a, int blocks, int threads,
-                                                size_t shmem, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-#define GPE_ROW(M, I)                                                                              \
-    do {                                                                                           \
-        static bool attr_ = false;                                                                 \
-        if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass<N, M, I>,                   \
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
-            if (e_ != hipSuccess) return e_;                                                       \
-            attr_ = true;                                                                          \
-        }                                                                                          \
-        if (e0)                                                                                    \
-            hipExtLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), (uint32_t)shmem, s, e0, e1, 0, a); \
-        else                                                                                       \
-            hipLaunchKernelGGL((row_pass<N, M, I>), dim3(blocks), dim3(threads), shmem, s, a);     \
-    } while (0)
-    if (imag) {
-        if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, true);
-        else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, true);
-        else if (mode == ROW_MID) GPE_ROW(ROW_MID, true);
-        else return hipErrorInvalidValue;
-    } else {
-        if (mode == ROW_ENTRY) GPE_ROW(ROW_ENTRY, false);
-        else if (mode == ROW_MID) GPE_ROW(ROW_MID, false);
-        else if (mode == ROW_EXIT) GPE_ROW(ROW_EXIT, false);
-        else if (mode == ROW_FWD) GPE_ROW(ROW_FWD, false);
-        else if (mode == ROW_PROBE_REAL) GPE_ROW(ROW_PROBE_REAL, false);
-        else if (mode == ROW_PROBE_MID) GPE_ROW(ROW_PROBE_MID, false);
-        else if (mode == ROW_INV) GPE_ROW(ROW_INV, false);
-        else return hipErrorInvalidValue;
-    }
-#undef GPE_ROW
-    return hipGetLastError();
-}
-
-hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, int threads, size_t shmem,
-                      hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-    switch (n) {
-    case 16: return row_dispatch<16>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 32: return row_dispatch<32>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 64: return row_dispatch<64>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 128: return row_dispatch<128>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 256: return row_dispatch<256>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 512: return row_dispatch<512>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 1024: return row_dispatch<1024>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 2048: return row_dispatch<2048>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    case 4096: return row_dispatch<4096>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int N> static hipError_t col_dispatch(int mode, const ColArgs &a, int blocks, int threads, size_t shmem,
-                                                hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-#define GPE_COL(M)                                                                                 \
-    do {                                                                                           \
-        static bool attr_ = false;                                                                 \
-        if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)col_pass<N, M>,                      \
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
-            if (e_ != hipSuccess) return e_;                                                       \
-            attr_ = true;                                                                          \
-        }                                                                                          \
-        if (e0)                                                                                    \
-            hipExtLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), (uint32_t)shmem, s, e0, e1, 0, a); \
-        else                                                                                       \
-            hipLaunchKernelGGL((col_pass<N, M>), dim3(blocks), dim3(threads), shmem, s, a);        \
-    } while (0)
-    if (mode == COL_KIN_REAL) GPE_COL(COL_KIN_REAL);
-    else if (mode == COL_KIN_IMAG) GPE_COL(COL_KIN_IMAG);
-    else if (mode == COL_EKIN) GPE_COL(COL_EKIN);
-    else if (mode == COL_KHALF_INV) GPE_COL(COL_KHALF_INV);
-    else if (mode == COL_FWD_KHALF) GPE_COL(COL_FWD_KHALF);
-    else if (mode == COL_KHALF_INV_IM) GPE_COL(COL_KHALF_INV_IM);
-    else if (mode == COL_FWD_KHALF_IM) GPE_COL(COL_FWD_KHALF_IM);
-    else if (mode == COL_KIN_APPLY) GPE_COL(COL_KIN_APPLY);
-    else return hipErrorInvalidValue;
-#undef GPE_COL
-    return hipGetLastError();
-}
-
-hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s,
-                      hipEvent_t e0, hipEvent_t e1)
-{
-    switch (n) {
-    case 16: return col_dispatch<16>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 32: return col_dispatch<32>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 64: return col_dispatch<64>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 128: return col_dispatch<128>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 256: return col_dispatch<256>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 512: return col_dispatch<512>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 1024: return col_dispatch<1024>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 2048: return col_dispatch<2048>(mode, a, blocks, threads, shmem, s, e0, e1);
-    case 4096: return col_dispatch<4096>(mode, a, blocks, threads, shmem, s, e0, e1);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s)
-{
-    hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(256), 0, s, ta, gd, pot, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s)
-{
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(256), 0, s, psi, n, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s)
-{
-    hipLaunchKernelGGL(set_call_kernel, dim3(1), dim3(64), 0, s, st, t0, reset_scale, clear_history);
-    return hipGetLastError();
-}
-
-hipError_t launch_norm(const float2 *psi, size_t n, double *partials, int blocks, hipStream_t s)
-{
-    hipLaunchKernelGGL(norm_kernel, dim3(blocks), dim3(256), 0, s, psi, n, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_energy_grad(const float2 *psi, float2 *lam, const GridDev &gd, const PotDev &pot,
-                              const DevState *st, int axis, double *partials, hipStream_t s)
-{
-    hipLaunchKernelGGL(energy_grad_kernel, dim3(gd.ny), dim3(256), 0, s, psi, lam, gd, pot, st, axis, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_marginal(const float2 *psi, int nx, int ny, int axis, double *out, hipStream_t s)
-{
-    const int blocks = axis == 1 ? ny : (nx + 63) / 64;
-    hipLaunchKernelGGL(marginal_kernel, dim3(blocks), dim3(256), 0, s, psi, nx, ny, axis, out);
-    return hipGetLastError();
-}
-
-template <int NX, int NY> static hipError_t lds_launch(const LdsArgs &a, int threads, hipStream_t s)
-{
-    const size_t shmem = (size_t)(NX + 1) * NY * sizeof(float2);
-    hipError_t e = hipFuncSetAttribute((const void *)lds_grid<NX, NY>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((lds_grid<NX, NY>), dim3(1), dim3(threads), shmem, s, a);
-    return hipGetLastError();
-}
-
-bool lds_supported(int nx, int ny)
-{
-    return nx >= 16 && ny >= 16 && nx <= 128 && ny <= 128 && (size_t)(nx + 1) * ny * 8 <= 160 * 1024;
-}
-
-int lds_threads(int nx, int ny)
-{
-    const int n = nx * ny / kLdsRadix;
-    return n < 1024 ? n : 1024;
-}
-
-hipError_t launch_lds_grid(const LdsArgs &a, hipStream_t s)
-{
-    const int nx = a.grid.nx, ny = a.grid.ny, th = lds_threads(nx, ny);
-#define GPE_LDS_Y(X)                                              \
-    switch (ny) {                                                 \
-    case 16: return lds_launch<X, 16>(a, th, s);                  \
-    case 32: return lds_launch<X, 32>(a, th, s);                  \
-    case 64: return lds_launch<X, 64>(a, th, s);                  \
-    case 128: return lds_launch<X, 128>(a, th, s);                \
-    default: return hipErrorInvalidValue;                         \
-    }
-    switch (nx) {
-    case 16: GPE_LDS_Y(16)
-    case 32: GPE_LDS_Y(32)
-    case 64: GPE_LDS_Y(64)
-    case 128: GPE_LDS_Y(128)
-    default: return hipErrorInvalidValue;
-    }
-#undef GPE_LDS_Y
-}
-
-// ------------------------------------------------------------ batched launchers
-template <int N, int R> static hipError_t rowb_dispatch(int mode, const BatchPassArgs &a, int blocks, int threads,
-                                                        size_t shmem, hipStream_t s)
-{
-#define GPE_ROWB_T(M, A, TJ)                                                                       \
-    do {                                                                                           \
-        static bool attr_ = false;                                                                 \
-        if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_pass_b<N, R, M, A, TJ>,          \
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
-            if (e_ != hipSuccess) return e_;                                                       \
-            attr_ = true;                                                                          \
-        }                                                                                          \
-        hipLaunchKernelGGL((row_pass_b<N, R, M, A, TJ>), dim3(blocks), dim3(threads), shmem, s, a); \
-    } while (0)
-#define GPE_ROWB(M, A) GPE_ROWB_T(M, A, false)
-    if (a.traj) {
-        // the adjoint's recording forward sweep (radix 8 only): entry and merged kicks
-        if constexpr (R == 8) {
-            if (a.cav) {
-                if (mode == ROW_ENTRY) GPE_ROWB_T(ROW_ENTRY, true, true);
-                else if (mode == ROW_MID) GPE_ROWB_T(ROW_MID, true, true);
-                else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
-                else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL, true);
-                else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID, true);
-                else return hipErrorInvalidValue;
-            } else {
-                if (mode == ROW_ENTRY) GPE_ROWB_T(ROW_ENTRY, false, true);
-                else if (mode == ROW_MID) GPE_ROWB_T(ROW_MID, false, true);
-                else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, false);
-                else return hipErrorInvalidValue;
-            }
-        } else {
-            return hipErrorInvalidValue;
-        }
-    } else if (a.cav) {
-        if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, true);
-        else if (mode == ROW_MID) GPE_ROWB(ROW_MID, true);
-        else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, true);
-        else if (mode == ROW_PROBE_REAL) GPE_ROWB(ROW_PROBE_REAL, true);
-        else if (mode == ROW_PROBE_MID) GPE_ROWB(ROW_PROBE_MID, true);
-        else return hipErrorInvalidValue;
-    } else {
-        if (mode == ROW_ENTRY) GPE_ROWB(ROW_ENTRY, false);
-        else if (mode == ROW_MID) GPE_ROWB(ROW_MID, false);
-        else if (mode == ROW_EXIT) GPE_ROWB(ROW_EXIT, false);
-        else return hipErrorInvalidValue;
-    }
-#undef GPE_ROWB
-#undef GPE_ROWB_T
-    return hipGetLastError();
-}
-
-template <int N, int R, bool ODE> static hipError_t colb_launch(const BatchPassArgs &a, int blocks, int threads,
-                                                                size_t shmem, hipStream_t s)
-{
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)col_pass_b<N, R, ODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL((col_pass_b<N, R, ODE>), dim3(blocks), dim3(threads), shmem, s, a);
-    return hipGetLastError();
-}
-
-template <int N, int R> static hipError_t colb_dispatch(const BatchPassArgs &a, int blocks, int threads, size_t shmem,
-                                                        hipStream_t s)
-{
-    return a.ode ? colb_launch<N, R, true>(a, blocks, threads, shmem, s)
-                 : colb_launch<N, R, false>(a, blocks, threads, shmem, s);
-}
-
-#define GPE_SIZES(F, ...)                                                                          \
-    switch (n) {                                                                                   \
-    case 64: return F<64, RR>(__VA_ARGS__);                                                        \
-    case 128: return F<128, RR>(__VA_ARGS__);                                                      \
-    case 256: return F<256, RR>(__VA_ARGS__);                                                      \
-    case 512: return F<512, RR>(__VA_ARGS__);                                                      \
-    case 1024: return F<1024, RR>(__VA_ARGS__);                                                    \
-    case 2048: return F<2048, RR>(__VA_ARGS__);                                                    \
-    default: return hipErrorInvalidValue;                                                          \
-    }
-
-hipError_t launch_row_batched(int n, int r, int mode, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
-                              hipStream_t s)
-{
-    if (r == 8) {
-        constexpr int RR = 8;
-        GPE_SIZES(rowb_dispatch, mode, a, blocks, threads, shmem, s)
-    } else if (r == 4) {
-        constexpr int RR = 4;
-        GPE_SIZES(rowb_dispatch, mode, a, blocks, threads, shmem, s)
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_col_batched(int n, int r, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
-                              hipStream_t s)
-{
-    if (r == 8) {
-        constexpr int RR = 8;
-        GPE_SIZES(colb_dispatch, a, blocks, threads, shmem, s)
-    } else if (r == 4) {
-        constexpr int RR = 4;
-        GPE_SIZES(colb_dispatch, a, blocks, threads, shmem, s)
-    }
-    return hipErrorInvalidValue;
-}
-#undef GPE_SIZES
-
-template <int NX, int NY> static hipError_t ldsb_launch(const LdsArgs *arr, int count, int threads, hipStream_t s)
-{
-    const size_t shmem = (size_t)(NX + 1) * NY * sizeof(float2);
-    hipError_t e = hipFuncSetAttribute((const void *)lds_grid_b<NX, NY>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((lds_grid_b<NX, NY>), dim3(count), dim3(threads), shmem, s, arr);
-    return hipGetLastError();
-}
-
-hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, hipStream_t s)
-{
-    const int th = lds_threads(nx, ny);
-#define GPE_LDSB_Y(X)                                                                              \
-    switch (ny) {                                                                                  \
-    case 16: return ldsb_launch<X, 16>(arr, count, th, s);                                         \
-    case 32: return ldsb_launch<X, 32>(arr, count, th, s);                                         \
-    case 64: return ldsb_launch<X, 64>(arr, count, th, s);                                         \
-    case 128: return ldsb_launch<X, 128>(arr, count, th, s);                                       \
-    default: return hipErrorInvalidValue;                                                          \
-    }
-    switch (nx) {
-    case 16: GPE_LDSB_Y(16)
-    case 32: GPE_LDSB_Y(32)
-    case 64: GPE_LDSB_Y(64)
-    case 128: GPE_LDSB_Y(128)
-    default: return hipErrorInvalidValue;
-    }
-#undef GPE_LDSB_Y
-}
-
-// Start of a batched call: every member's state records the call's first time.
-__global__ void set_call_batched_kernel(DevState *const *st, int n, double t0)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        st[i]->t0 = t0;
-        st[i]->scale = 1.0;
-    }
-}
-
-// After a replayed chunk of steps: advance every member's first time.
-__global__ void advance_t0_kernel(DevState *const *st, int n, double dt_total)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) st[i]->t0 += dt_total;
-}
-
-hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStream_t s)
-{
-    hipLaunchKernelGGL(set_call_batched_kernel, dim3(1), dim3(256), 0, s, st, n, t0);
-    return hipGetLastError();
-}
-
-// One plan's time base moves on by dt_total (after a replayed chunk of steps).
-__global__ void advance_one_kernel(DevState *st, double dt_total)
-{
-    if (threadIdx.x == 0) st->t0 += dt_total;
-}
-
-hipError_t launch_advance_one(DevState *st, double dt_total, hipStream_t s)
-{
-    hipLaunchKernelGGL(advance_one_kernel, dim3(1), dim3(64), 0, s, st, dt_total);
-    return hipGetLastError();
-}
-
-hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s)
-{
-    hipLaunchKernelGGL(advance_t0_kernel, dim3(1), dim3(256), 0, s, st, n, dt_total);
-    return hipGetLastError();
-}
 
 
 // ------------------------------------------------------------- adjoint passes
@@ -1435,158 +979,5 @@ __global__ void __launch_bounds__(512) col_adj_b(AdjPassArgs a)
 
 // After a batched call's exit pass: each field-ODE member's Theta of its last kick joins
 // the overlap history (one work-group per member).
-__global__ void __launch_bounds__(256) tail_batched_kernel(const InstDesc *inst, int nrow)
-{
-    __shared__ double red[4 * NPART];
-    const InstDesc &I = inst[blockIdx.x];
-    if (!I.partials) return;
-    TailArgs ta{};
-    ta.partials = I.partials;
-    ta.npartials = nrow;
-    ta.theta_only = 1;
-    run_tail(ta, I.grid, I.pot, I.st, red);
-}
-
-hipError_t launch_tail_batched(const InstDesc *inst, int count, int nrow, hipStream_t s)
-{
-    hipLaunchKernelGGL(tail_batched_kernel, dim3(count), dim3(256), 0, s, inst, nrow);
-    return hipGetLastError();
-}
-
-// The last kick's sums: one work-group per member.
-__global__ void __launch_bounds__(256) adj_tail_kernel(const AdjInst *inst, int nrow, int k)
-{
-    __shared__ double red[4];
-    adj_tail(inst[blockIdx.x], nrow, k, red);
-}
-
-// Per work-group partial sums over one member's points: {Re, Im} of sum conj(a) b, and
-// sum |a - b|^2, sum |b|^2.  Work-group b serves member b / per_inst.
-__global__ void __launch_bounds__(256) pair_sums_kernel(const float2 *const *a, const float2 *const *b, size_t npts,
-                                                        int per_inst, double *out)
-{
-    __shared__ double red[4 * 4];
-    const int inst = blockIdx.x / per_inst, lb = blockIdx.x % per_inst;
-    const float2 *pa = a[inst], *pb = b[inst];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < npts; i += (size_t)per_inst * blockDim.x) {
-        const float2 x = pa[i], y = pb[i];
-        s[0] += (double)x.x * y.x + (double)x.y * y.y;
-        s[1] += (double)x.x * y.y - (double)x.y * y.x;
-        const double dx = (double)x.x - y.x, dy = (double)x.y - y.y;
-        s[2] += dx * dx + dy * dy;
-        s[3] += (double)y.x * y.x + (double)y.y * y.y;
-    }
-    block_sum<4>(s, red);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) out[blockIdx.x * 4 + k] = s[k];
-}
-
-// lam_i = coef_i * src_i (terminal adjoint of the fidelity loss).
-__global__ void __launch_bounds__(256) scaled_copy_kernel(float2 *const *dst, const float2 *const *src,
-                                                          const double2 *coef, size_t npts, int per_inst)
-{
-    const int inst = blockIdx.x / per_inst, lb = blockIdx.x % per_inst;
-    const double2 c = coef[inst];
-    float2 *d = dst[inst];
-    const float2 *s = src[inst];
-    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < npts; i += (size_t)per_inst * blockDim.x) {
-        const float2 x = s[i];
-        d[i] = make_float2((float)(c.x * x.x - c.y * x.y), (float)(c.x * x.y + c.y * x.x));
-    }
-}
-
-template <int N, int R, bool TRAJ> static hipError_t rowadj_mode(int mode, const AdjPassArgs &a, int blocks,
-                                                                 int threads, size_t shmem, hipStream_t s)
-{
-#define GPE_RADJ(M)                                                                                \
-    do {                                                                                           \
-        static bool attr_ = false;                                                                 \
-        if (!attr_) {                                                                              \
-            hipError_t e_ = hipFuncSetAttribute((const void *)row_adj_b<N, R, M, TRAJ>,            \
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024); \
-            if (e_ != hipSuccess) return e_;                                                       \
-            attr_ = true;                                                                          \
-        }                                                                                          \
-        hipLaunchKernelGGL((row_adj_b<N, R, M, TRAJ>), dim3(blocks), dim3(threads), shmem, s, a);  \
-    } while (0)
-    if (mode == ADJ_FIRST) GPE_RADJ(ADJ_FIRST);
-    else if (mode == ADJ_MID) GPE_RADJ(ADJ_MID);
-    else if (mode == ADJ_LAST) GPE_RADJ(ADJ_LAST);
-    else if (mode == ADJ_PROBE_FIRST) GPE_RADJ(ADJ_PROBE_FIRST);
-    else if (mode == ADJ_PROBE_MID) GPE_RADJ(ADJ_PROBE_MID);
-    else return hipErrorInvalidValue;
-#undef GPE_RADJ
-    return hipGetLastError();
-}
-
-template <int N, int R> static hipError_t rowadj_dispatch(int mode, const AdjPassArgs &a, int blocks, int threads,
-                                                          size_t shmem, hipStream_t s)
-{
-    return a.traj ? rowadj_mode<N, R, true>(mode, a, blocks, threads, shmem, s)
-                  : rowadj_mode<N, R, false>(mode, a, blocks, threads, shmem, s);
-}
-
-template <int N, int R, bool TRAJ> static hipError_t coladj_launch(const AdjPassArgs &a, int blocks, int threads,
-                                                                   size_t shmem, hipStream_t s)
-{
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)col_adj_b<N, R, TRAJ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL((col_adj_b<N, R, TRAJ>), dim3(blocks), dim3(threads), shmem, s, a);
-    return hipGetLastError();
-}
-
-template <int N, int R> static hipError_t coladj_dispatch(const AdjPassArgs &a, int blocks, int threads, size_t shmem,
-                                                          hipStream_t s)
-{
-    return a.traj ? coladj_launch<N, R, true>(a, blocks, threads, shmem, s)
-                  : coladj_launch<N, R, false>(a, blocks, threads, shmem, s);
-}
-
-#define GPE_ADJ_SIZES(F, ...)                                                                      \
-    switch (n) {                                                                                   \
-    case 64: return F<64, 8>(__VA_ARGS__);                                                         \
-    case 128: return F<128, 8>(__VA_ARGS__);                                                       \
-    case 256: return F<256, 8>(__VA_ARGS__);                                                       \
-    case 512: return F<512, 8>(__VA_ARGS__);                                                       \
-    case 1024: return F<1024, 8>(__VA_ARGS__);                                                     \
-    default: return hipErrorInvalidValue;                                                          \
-    }
-
-hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
-{
-    GPE_ADJ_SIZES(rowadj_dispatch, mode, a, blocks, threads, shmem, s)
-}
-
-hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s)
-{
-    GPE_ADJ_SIZES(coladj_dispatch, a, blocks, threads, shmem, s)
-}
-#undef GPE_ADJ_SIZES
-
-hipError_t launch_adj_tail(const AdjInst *inst, int count, int nrow, int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(adj_tail_kernel, dim3(count), dim3(256), 0, s, inst, nrow, k);
-    return hipGetLastError();
-}
-
-hipError_t launch_pair_sums(const float2 *const *a, const float2 *const *b, size_t npts, int count, int per_inst,
-                            double *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(pair_sums_kernel, dim3(count * per_inst), dim3(256), 0, s, a, b, npts, per_inst, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, const double2 *coef, size_t npts,
-                              int count, int per_inst, hipStream_t s)
-{
-    hipLaunchKernelGGL(scaled_copy_kernel, dim3(count * per_inst), dim3(256), 0, s, dst, src, coef, npts, per_inst);
-    return hipGetLastError();
-}
 
 }  // namespace gpe

@@ -762,6 +762,7 @@ int gpe_norm(gpe_plan *p, const gpe_c64 *psi, double *out)
     double s = 0;
     for (int i = 0; i < blocks; ++i) s += p->hpart[i];
     *out = s * p->grid.dA;
+    if (!std::isfinite(s)) return fail(GPE_ERR_NONFINITE, "non-finite values in psi");
     return GPE_OK;
 }
 
@@ -829,6 +830,8 @@ int gpe_energy(gpe_plan *p, const gpe_c64 *psi, double t, double out[6])
     out[3] = (ek + ep + ei) / nrm;
     out[4] = (ek + ep + 2 * ei) / nrm;
     out[5] = nrm;
+    if (!std::isfinite(nrm) || !std::isfinite(ek) || !std::isfinite(ep) || !std::isfinite(ei))
+        return fail(GPE_ERR_NONFINITE, "non-finite values in psi");
     return GPE_OK;
 }
 

@@ -27,10 +27,11 @@ hipError_t launch_row_batched(int n, int r, int mode, const BatchPassArgs &a, in
                               hipStream_t s);
 hipError_t launch_col_batched(int n, int r, const BatchPassArgs &a, int blocks, int threads, size_t shmem,
                               hipStream_t s);
-hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, hipStream_t s);
+hipError_t launch_lds_batched(int nx, int ny, const LdsArgs *arr, int count, int64_t s0, int nsteps, hipStream_t s);
 hipError_t launch_set_call_batched(DevState *const *st, int n, double t0, hipStream_t s);
 hipError_t launch_advance_t0(DevState *const *st, int n, double dt_total, hipStream_t s);
 hipError_t launch_advance_one(DevState *st, double dt_total, hipStream_t s);
+hipError_t launch_gather_flags(DevState *const *st, int n, int *out, hipStream_t s);
 hipError_t launch_row_adj(int n, int mode, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
 hipError_t launch_col_adj(int n, const AdjPassArgs &a, int blocks, int threads, size_t shmem, hipStream_t s);
 hipError_t launch_tail_batched(const InstDesc *inst, int count, int nrow, hipStream_t s);

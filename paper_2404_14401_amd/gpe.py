@@ -33,7 +33,7 @@ EXPORTS = (
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
     "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
-    "gpe_batch_get_cavity", "gpe_adjoint",
+    "gpe_batch_get_cavity", "gpe_batch_sync", "gpe_adjoint",
 )
 
 
@@ -101,6 +101,7 @@ def lib():
         L.gpe_batch_tune.argtypes = [P, C.c_char_p]
         L.gpe_batch_info.argtypes = [P, I, P]
         L.gpe_batch_get_cavity.argtypes = [P, I, P]
+        L.gpe_batch_sync.argtypes = [P, P]
         L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, I, D, P, P, P, P]
         for name in EXPORTS:
             if name != "gpe_last_error":
@@ -305,6 +306,16 @@ class Batch:
                             row_threads=out[5], col_blocks=out[6]))
         return res
 
+    def sync(self) -> None:
+        """Wait for the batch; raises GpeError (ERR_NONFINITE, .member set) if a member's
+        wave function went non-finite."""
+        bad = C.c_int(-1)
+        rc = lib().gpe_batch_sync(self._h, C.byref(bad))
+        if rc != OK:
+            err = GpeError(rc, lib().gpe_last_error().decode())
+            err.member = bad.value
+            raise err
+
     def cavity(self, member: int) -> complex:
         """Cavity field of one member after the last call."""
         out = np.zeros(4)
@@ -313,23 +324,26 @@ class Batch:
 
 
 def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, mode: str = "auto",
-            drift_tol: float = 1e-4, psi_finals=None, control: str = "x", loss: str = "fidelity"):
+            drift_tol: float = 1e-4, psi_finals=None, control: str = "x", loss: str = "fidelity",
+            want_grad: bool = True):
     """Loss 1 - |<target|psi(T)>|^2 (loss "fidelity") or E_kin + E_pot + E_int of psi(T)
     (loss "energy", targets None) and its gradient w.r.t. the knot values of the
     x-lattice (control "x") or pump, y-lattice (control "pump"), depth of every batch
     member (discrete adjoint on the GPU).  knots: array (n, M).
-    Returns (loss[n], grad[n, M], info dict)."""
+    Returns (loss[n], grad[n, M], info dict); with want_grad False only the forward
+    sweep runs and grad is None."""
     k = np.ascontiguousarray(knots, dtype=np.float64)
     n, m = k.shape
     if n != batch.n:
         raise ValueError("one row of knots per batch member")
     out = np.zeros(n)
-    grad = np.zeros((n, m))
+    grad = np.zeros((n, m)) if want_grad else None
     info = np.zeros(4)
     fin = batch._ptrs(psi_finals) if psi_finals is not None else None
     tg = batch._ptrs(targets) if targets is not None else None
     check(lib().gpe_adjoint(batch._h, batch._ptrs(psi0s), tg, int(nsteps), float(t0),
                             k.ctypes.data, m, CONTROL[control], LOSS[loss], ADJ_MODE[mode], float(drift_tol),
-                            out.ctypes.data, grad.ctypes.data, fin, info.ctypes.data))
-    return out, grad, {"mode": {1: "reconstruct", 2: "checkpoint", 3: "store"}[int(info[0])], "drift": info[1],
+                            out.ctypes.data, grad.ctypes.data if want_grad else None, fin, info.ctypes.data))
+    return out, grad, {"mode": {0: "loss", 1: "reconstruct", 2: "checkpoint", 3: "store"}[int(info[0])],
+                       "drift": info[1],
                         "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}

@@ -319,3 +319,64 @@ def test_adjoint_argument_and_size_refusals():
     call([control_setup(0, nsteps=10)], knots=np.zeros((1, 5)))
     ode = W.cavity_scaled(64, 0).with_(sx=control_setup(0, nsteps=10).sx)
     call([ode], err=gpe.ERR_UNSUPPORTED)
+
+
+def test_adjoint_refuses_nonfinite_knots_and_pump_knots_across_zero():
+    """The knots replace the controlled schedule's values, so they get the schedule's
+    checks: finite values, and for pump control of a cavity member the sign of vc
+    (sqrt(Vp U0) coupling, singular derivative at Vp = 0).  Refused before anything runs;
+    valid knots still work afterwards."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = control_setup(0, nsteps=10)
+    b = gpe.Batch([s])
+    d = [to_dev(states(s, 0)[0])]
+    k = s.sx.knots[None, :].copy()
+    for bad in (np.nan, np.inf):
+        kb = k.copy()
+        kb[0, 3] = bad
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.adjoint(b, d, d, 10, kb)
+        assert e.value.code == gpe.ERR_INVALID
+    cs = cavity_control_setup(0, "pump", nsteps=10)
+    cb = gpe.Batch([cs])
+    cd = [to_dev(states(cs, 0)[0])]
+    kp = cs.sy.knots[None, :].copy()
+    assert np.all(kp * cs.vc > 0)
+    for bad in (0.0, -kp[0, 1]):
+        kb = kp.copy()
+        kb[0, 1] = bad
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.adjoint(cb, cd, cd, 10, kb, control="pump")
+        assert e.value.code == gpe.ERR_INVALID
+    loss, grad, _ = gpe.adjoint(cb, cd, cd, 10, kp, control="pump")
+    assert np.isfinite(loss).all() and np.isfinite(grad).all()
+
+
+def test_loss_only_evaluation_runs_the_forward_sweep_alone():
+    """Without a gradient request (no_grad, or knots that do not require grad) the
+    autograd wrapper asks for the loss alone: the same loss, no reverse sweep; the
+    library reports mode 0 and one forward sweep."""
+    torch = torch_cuda()
+    from paper_2404_14401_amd import autograd as A
+    from paper_2404_14401_amd import gpe
+
+    nsteps = 60
+    s = control_setup(1, nsteps=nsteps)
+    batch = gpe.Batch([s])
+    p0, tg = states(s, 1)
+    d0, dt_ = [to_dev(p0)], [to_dev(tg)]
+    full, grad, info = gpe.adjoint(batch, d0, dt_, nsteps, s.sx.knots[None, :], mode="reconstruct")
+    only, none, info2 = gpe.adjoint(batch, d0, dt_, nsteps, s.sx.knots[None, :], want_grad=False)
+    assert none is None and info2["mode"] == "loss" and info2["forward_steps"] == nsteps
+    assert only[0] == full[0]
+    knots = torch.tensor(s.sx.knots[None, :], dtype=torch.float64, requires_grad=True)
+    with torch.no_grad():
+        l_ng = A.control_loss(knots, batch, d0, dt_, nsteps)
+    assert not l_ng.requires_grad and float(l_ng[0]) == full[0]
+    l_nr = A.control_loss(knots.detach(), batch, d0, dt_, nsteps)
+    assert float(l_nr[0]) == full[0]
+    l = A.control_loss(knots, batch, d0, dt_, nsteps, mode="reconstruct")
+    l.sum().backward()
+    assert np.allclose(knots.grad.numpy()[0], grad[0], rtol=0, atol=0)

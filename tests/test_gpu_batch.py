@@ -199,3 +199,28 @@ def test_members_beyond_the_batched_line_lengths_are_refused_at_creation(path, m
     d = to_dev(W.to_c64(W.gaussian(ok, 1.0)))
     b.step([d], 3, 0.0)
     assert np.isfinite(to_host(d)).all()
+
+
+def test_long_lds_group_call_is_split_into_bounded_launches(monkeypatch):
+    """Members kept in LDS run a long call as several launches of at most 2^26
+    point-steps each (4096 steps at 128^2); the split carries the kick times and the
+    field-ODE state across launches, so the member still equals a plain plan run as
+    one launch (time-dependent lattice ramp and the cavity field both on)."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    monkeypatch.setenv("GPE_BATCH_PATH", "lds")
+    nsteps = 4096 + 37
+    s = W.cavity_scaled(128, 1).with_(kx_lat=1.0, sx=W.Schedule("ramp", 0.0, 2.0, 0.0, nsteps * 2e-4))
+    psi0 = W.to_c64(W.gaussian(s, 1.5))
+    b = gpe.Batch([s])
+    assert b.groups()[0]["lds"]
+    d = to_dev(psi0)
+    b.step([d], nsteps, 0.0)
+    b.sync()
+    monkeypatch.setenv("GPE_PATH", "lds")
+    plain = gpe.Plan.from_setup(s)
+    e = to_dev(psi0)
+    plain.step_real(e, nsteps, 0.0)
+    assert rel_l2(to_host(d), to_host(e)) < 1e-5
+    assert abs(b.cavity(0) - plain.cavity()["alpha"]) <= 1e-5 * abs(plain.cavity()["alpha"]) + 1e-12

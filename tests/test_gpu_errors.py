@@ -106,3 +106,89 @@ def test_widened_entry_points_validate_arguments():
     with pytest.raises(gpe.GpeError) as e:   # the y lattice has no knots
         gpe.adjoint(b, [d], [d], 10, knots[None, :], control="pump")
     assert e.value.code == gpe.ERR_INVALID
+
+
+def _nan_state(s, at=(10, 10)):
+    psi = W.to_c64(W.gaussian(s, 1.0))
+    psi[at] = np.nan
+    return psi
+
+
+@pytest.mark.parametrize("path, n, nsteps", [("multipass", 128, 5), ("multipass", 128, 80), ("lds", 32, 5)])
+def test_nan_is_reported_on_paths_that_reduce_nothing(path, n, nsteps, monkeypatch):
+    """A plain real-time call without cavity or observables runs no reduction; its kicks
+    still flag a non-finite input (multi-pass with and without replayed chunks, and the
+    grid kept in LDS), and gpe_sync reports it."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    monkeypatch.setenv("GPE_PATH", path)
+    s = W.Setup(nx=n, ny=n, lx=16.0, ly=16.0, dt=1e-3, g=10.0)
+    plan = gpe.Plan.from_setup(s)
+    clean = to_dev(W.to_c64(W.gaussian(s, 1.0)))
+    plan.step_real(clean, nsteps, 0.0)
+    plan.sync()  # a finite state is not flagged
+    d = to_dev(_nan_state(s))
+    plan.step_real(d, nsteps, 0.0)
+    with pytest.raises(gpe.GpeError) as e:
+        plan.sync()
+    assert e.value.code == gpe.ERR_NONFINITE
+
+
+def test_nan_is_reported_by_the_fourier_space_ordering_without_observables():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.Setup(nx=128, ny=64, lx=16.0, ly=8.0, dt=1e-3, g=10.0)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(_nan_state(s, (3, 70)))
+    plan.step_real_k(d, 4, 0.0)
+    with pytest.raises(gpe.GpeError) as e:
+        plan.sync()
+    assert e.value.code == gpe.ERR_NONFINITE
+
+
+def test_norm_and_energy_report_a_nonfinite_input():
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    s = W.Setup(nx=64, ny=64, lx=16.0, ly=16.0, dt=1e-3, g=10.0)
+    plan = gpe.Plan.from_setup(s)
+    d = to_dev(_nan_state(s))
+    for call in (lambda: plan.norm(d), lambda: plan.energy(d)):
+        with pytest.raises(gpe.GpeError) as e:
+            call()
+        assert e.value.code == gpe.ERR_NONFINITE
+    inf = W.to_c64(W.gaussian(s, 1.0))
+    inf[5, 7] = np.inf
+    with pytest.raises(gpe.GpeError) as e:
+        plan.norm(to_dev(inf))
+    assert e.value.code == gpe.ERR_NONFINITE
+
+
+@pytest.mark.parametrize("bad", [1, 2])
+def test_nan_in_a_cavity_free_batch_member_is_reported(bad):
+    """A cavity-free batch reduces nothing; a member's non-finite state is still flagged,
+    by the batched kick passes (256^2, multi-pass) or at the end of the call (64^2, in
+    LDS), and gpe_batch_sync names the first bad member."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    setups = [W.Setup(nx=256, ny=256, lx=32.0, ly=32.0, dt=5e-4, g=100.0),
+              W.Setup(nx=256, ny=256, lx=32.0, ly=32.0, dt=5e-4, g=200.0),
+              W.Setup(nx=64, ny=64, lx=8.0, ly=8.0, dt=5e-4, g=50.0)]
+    b = gpe.Batch(setups)
+    lds = {(g["nx"], g["ny"]): g["lds"] for g in b.groups()}
+    assert not lds[(256, 256)] and lds[(64, 64)]
+    psis = [to_dev(W.to_c64(W.gaussian(s, 1.0))) for s in setups]
+    b.step(psis, 60, 0.0)
+    b.sync()  # finite members are not flagged
+    member = 1 if bad == 1 else 2
+    psis[member] = to_dev(_nan_state(setups[member], (7, 9)))
+    b.step(psis, 60, 0.0)
+    with pytest.raises(gpe.GpeError) as e:
+        b.sync()
+    assert e.value.code == gpe.ERR_NONFINITE and e.value.member == member
+    with pytest.raises(gpe.GpeError):
+        b.cavity(member)
+    b.cavity(0)  # the other members' state is readable

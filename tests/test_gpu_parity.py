@@ -127,14 +127,51 @@ def test_energy_inside_a_ramp_is_taken_at_the_given_time(path, monkeypatch):
         assert rel_e(plan.energy(d, t)["e"], O.energy(problem(s), psi0, t)["e"]) < 1e-9, t
 
 
+def _assert_pointwise(out, ref, l2=2e-6, amax=1e-5):
+    """rel-L2 and the largest pointwise error against the largest value: an indexing
+    slip in one tile or row shows in the second even where the first averages it away."""
+    assert rel_l2(out, ref) < l2
+    err = np.abs(out - ref)
+    assert err.max() <= amax * np.abs(ref).max(), (np.unravel_index(err.argmax(), err.shape), err.max())
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (2048, 512), (512, 2048)])
+@pytest.mark.parametrize("mode", ["real", "imag"])
+def test_full_spectrum_states_on_the_headline_launch_shapes(shape, mode, monkeypatch):
+    """White-noise states (every kx, ky mode and every row and column populated,
+    box-edge points included) through the headline launch shapes: one line per row
+    work-group, narrow column tiles in the XCD-aware order, the merged real-time kick
+    of the middle row passes and the field ODE with a non-zero field (1024^2 runs the
+    cavity workload's physics at alpha0 = 0.3 - 0.2i).  Three real or two imaginary
+    steps against the oracle, pointwise."""
+    nx, ny = shape
+    if shape == (1024, 1024):
+        s = W.cavity_1024(2).with_(alpha0=0.3 - 0.2j)
+    else:
+        s = W.Setup(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0, dt=2e-4, g=800.0, wx=0.05, wy=0.07, x0=0.7,
+                    kx_lat=1.0, ky_lat=2.0, sx=W.Schedule("ramp", 0.0, 3.0, 0.0, 1e-3), sy=W.Schedule("const", 1.5),
+                    cavity=True, vc=1.5, kc=1.0, delta_c=-20.0, kappa=10.0, eta=4.0, alpha0=0.2 + 0.1j)
+    psi0 = W.random_state(s, 31)
+    n = 3 if mode == "real" else 2
+    st = state(s)
+    ref, _ = (O.step_real if mode == "real" else O.step_imag)(problem(s), st, psi0, n)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    (plan.step_real if mode == "real" else plan.step_imag)(d, n, 0.0)
+    _assert_pointwise(to_host(d), ref)
+    if mode == "real":
+        assert abs(plan.cavity()["alpha"] - st.alpha) <= 1e-6 * abs(st.alpha)
+
+
 # ----------------------------------------------- imaginary-time ground state
 
 @pytest.mark.parametrize("path", ["lds", "multipass"])
 @pytest.mark.parametrize("g", [0.0, 100.0])
-def test_imag_ground_state_64(path, g, monkeypatch):
-    """64x64 on [-8,8)^2, dtau = 1e-3, 2000 steps, seed-perturbed Gaussian."""
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_imag_ground_state_64(path, g, seed, monkeypatch):
+    """64x64 on [-8,8)^2, dtau = 1e-3, 2000 steps, seed-perturbed Gaussian (seeds 0-2)."""
     s = W.imag_ground_64(g)
-    psi0 = W.noisy_gaussian(s, 0)
+    psi0 = W.noisy_gaussian(s, seed)
     ref, robs = O.step_imag(problem(s), state(s), psi0, W.IMAG_64_STEPS, want_obs=True)
     plan = make_plan(s, path, monkeypatch)
     import torch
