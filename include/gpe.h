@@ -289,6 +289,26 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
                 double t0, const double *knots, int nknots, int control, int loss_kind, int mode,
                 double drift_tol, double *loss, double *grad, gpe_c64 *const *psi_final, double *info);
 
+/* ------------------------------------------------------------ allocation-free
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the real-time steps of gpe_step_real
+ * without a plan.  The call does what gpe_step_real does on a fresh plan created from
+ * desc with potential pot (same kernels, same launch shapes): the cavity field starts at
+ * alpha0 with no overlap history.  Instead of plan memory it uses one static device array
+ * of 1 MiB (per device, held until the process ends): every call rebuilds the tables in
+ * it with kernels and issues only kernel launches on desc->stream -- no hipMalloc, no
+ * hipFree, no memset, no host-to-device copy, no graph of its own.  Calls on one device
+ * share the array, so calls that overlap on one device (other streams or threads) race.
+ * desc, pot: as for gpe_plan_create / gpe_set_potential (host, read during the call);
+ * knot schedules hold at most 256 knots; every grid the plan takes (powers of two 16 to
+ * 4096 per side) fits the array.  psi: device [ny][nx] gpe_c64, updated in place,
+ * asynchronously.  nonfinite: optional device int that receives 1 if a kick met a NaN or
+ * an infinity in psi, else 0 (the call itself cannot wait for the device); untouched when
+ * nsteps = 0.  No observables.  Errors: GPE_ERR_INVALID for bad descriptors, negative
+ * nsteps, more than 256 knots; GPE_ERR_DEVICE for a failed launch. */
+int gpe_step_real_noalloc(const gpe_plan_desc *desc, const gpe_potential_desc *pot, gpe_c64 *psi, int64_t nsteps,
+                          double t0, int *nonfinite);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels_plan.hip", "kernels_batch.hip", "kernels_adj.hip", "runtime.cpp", "batch.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels_plan.hip", "kernels_batch.hip", "kernels_adj.hip", "runtime.cpp", "batch.cpp", "noalloc.hip")]
 OUT = os.path.join(HERE, "libgpe.so")
 ARCH = os.environ.get("GPE_OFFLOAD_ARCH", "gfx950")
 

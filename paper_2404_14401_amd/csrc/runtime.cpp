@@ -187,13 +187,10 @@ static int upload_knots(gpe_plan *p, const gpe_schedule &s, double **dev, int *c
     return GPE_OK;
 }
 
-extern "C" {
-
-const char *gpe_last_error(void) { return g_err.c_str(); }
-
-int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
+// Argument checks of a potential description (gpe_set_potential and the allocation-free
+// entry point).
+int check_potential_desc(const gpe_potential_desc *v)
 {
-    if (!p || !v) return fail(GPE_ERR_INVALID, "null plan or potential");
     int rc = check_sched(v->sx, "sx");
     if (rc) return rc;
     if ((rc = check_sched(v->sy, "sy"))) return rc;
@@ -212,32 +209,27 @@ int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
         return fail(GPE_ERR_INVALID, "probe parameters must be finite");
     if (v->probe_omega != 0 && v->cavity != 2)
         return fail(GPE_ERR_INVALID, "the cavity probe acts on the adiabatic field only");
-    HIP_OK(hipStreamSynchronize(p->stream));
-    drop_plan_graphs(p);  // the potential is baked into captured kernel arguments
-    const int nx = p->nx, ny = p->ny;
-    std::vector<float4> tx(nx), ty(ny);
-    for (int i = 0; i < nx; ++i) {
-        const double x = -0.5 * p->lx + i * (p->lx / nx);
-        const double c = std::cos(v->kx_lat * x);
-        tx[i] = make_float4((float)(0.5 * v->wx * v->wx * (x - v->x0) * (x - v->x0)), (float)(c * c),
-                            (float)std::cos(v->kc * x), (float)x);
-    }
-    for (int j = 0; j < ny; ++j) {
-        const double y = -0.5 * p->ly + j * (p->ly / ny);
-        const double c = std::cos(v->ky_lat * y);
-        ty[j] = make_float4((float)(0.5 * v->wy * v->wy * (y - v->y0) * (y - v->y0)), (float)(c * c),
-                            (float)std::cos(v->kc * y), (float)y);
-    }
-    HIP_OK(hipMemcpy(p->tx, tx.data(), sizeof(float4) * nx, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(p->ty, ty.data(), sizeof(float4) * ny, hipMemcpyHostToDevice));
-    if ((rc = upload_knots(p, v->sx, &p->knots_x, &p->knots_cap_x))) return rc;
-    if ((rc = upload_knots(p, v->sy, &p->knots_y, &p->knots_cap_y))) return rc;
-    PotDev &d = p->pot;
-    d.tx = p->tx;
-    d.ty = p->ty;
+    return GPE_OK;
+}
+
+// One entry of a per-axis potential table at coordinate x: {1/2 w^2 (x - x0)^2,
+// cos^2(k_lat x), cos(kc x), x} (trap, lattice of Sec. 5.2 Eq. 9, cavity mode of Sec. 5.3).
+static float4 axis_entry(double w, double x0, double klat, double kc, double x)
+{
+    const double c = std::cos(klat * x);
+    return make_float4((float)(0.5 * w * w * (x - x0) * (x - x0)), (float)(c * c), (float)std::cos(kc * x), (float)x);
+}
+
+// Device view of a potential whose tables and knots sit at the given device addresses,
+// with the cavity field's one-step propagator e^{lambda dt}, (e^{lambda dt} - 1)/lambda.
+void potdev_from_desc(PotDev &d, const gpe_potential_desc *v, double dt, const float4 *tx, const float4 *ty,
+                      const double *knots_x, const double *knots_y)
+{
+    d.tx = tx;
+    d.ty = ty;
     d.vuser = v->v_user;
-    d.sx = to_sched(v->sx, p->knots_x);
-    d.sy = to_sched(v->sy, p->knots_y);
+    d.sx = to_sched(v->sx, knots_x);
+    d.sy = to_sched(v->sy, knots_y);
     d.cavity = v->cavity;
     d.vc = v->vc;
     d.eta = v->eta;
@@ -248,16 +240,85 @@ int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
     d.probe_detuning = v->probe_detuning;
     d.probe_phase = v->probe_phase;
     const std::complex<double> lam(-v->kappa, v->delta_c);
-    const std::complex<double> e = std::exp(lam * p->dt);
-    const std::complex<double> phi1 = std::abs(lam) > 0 ? (e - 1.0) / lam : std::complex<double>(p->dt, 0.0);
+    const std::complex<double> e = std::exp(lam * dt);
+    const std::complex<double> phi1 = std::abs(lam) > 0 ? (e - 1.0) / lam : std::complex<double>(dt, 0.0);
     d.ecav_re = e.real();
     d.ecav_im = e.imag();
     d.phi1_re = phi1.real();
     d.phi1_im = phi1.imag();
+}
+
+// Device state after a potential is set: field alpha0, no overlap history, no pending scale.
+DevState initial_state(const gpe_potential_desc *v)
+{
     DevState st{};
     st.alpha_re = v->alpha0_re;
     st.alpha_im = v->alpha0_im;
     st.scale = 1.0;
+    return st;
+}
+
+int check_plan_desc(const gpe_plan_desc *d)
+{
+    if (!pow2_in(d->nx, 16, 4096) || !pow2_in(d->ny, 16, 4096))
+        return fail(GPE_ERR_INVALID, "nx, ny must be powers of two in [16, 4096]");
+    if (!(d->lx > 0) || !(d->ly > 0) || !(d->dt > 0) || !(d->g >= 0) || !std::isfinite(d->dt) ||
+        !std::isfinite(d->g) || !std::isfinite(d->lx) || !std::isfinite(d->ly))
+        return fail(GPE_ERR_INVALID, "need lx, ly, dt > 0 and g >= 0, all finite");
+    return GPE_OK;
+}
+
+// Scalars of the grid (the table pointers are filled by the caller).
+void griddev_from_desc(GridDev &gd, const gpe_plan_desc *d)
+{
+    gd = GridDev{};
+    gd.nx = d->nx;
+    gd.ny = d->ny;
+    gd.lx = d->lx;
+    gd.ly = d->ly;
+    gd.dx = d->lx / d->nx;
+    gd.dy = d->ly / d->ny;
+    gd.dA = gd.dx * gd.dy;
+    gd.dt = d->dt;
+    gd.g = d->g;
+}
+
+Shape plan_shape(int nx, int ny) { return make_shape(nx, ny); }
+
+// Path, tile order and graph replay as the environment selects them (GPE_PATH, GPE_XCD,
+// GPE_PLAN_GRAPH).
+void plan_env(gpe_plan *p)
+{
+    const char *force = getenv("GPE_PATH");
+    if (force && !strcmp(force, "multipass")) p->path = 1;
+    if (force && !strcmp(force, "lds")) p->path = 2;
+    const char *xcd = getenv("GPE_XCD");
+    if (xcd && !strcmp(xcd, "0")) p->xcd = 0;
+    const char *rep = getenv("GPE_PLAN_GRAPH");
+    if (rep && !strcmp(rep, "0")) p->replay = false;
+}
+
+extern "C" {
+
+const char *gpe_last_error(void) { return g_err.c_str(); }
+
+int gpe_set_potential(gpe_plan *p, const gpe_potential_desc *v)
+{
+    if (!p || !v) return fail(GPE_ERR_INVALID, "null plan or potential");
+    int rc = check_potential_desc(v);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(p->stream));
+    drop_plan_graphs(p);  // the potential is baked into captured kernel arguments
+    const int nx = p->nx, ny = p->ny;
+    std::vector<float4> tx(nx), ty(ny);
+    for (int i = 0; i < nx; ++i) tx[i] = axis_entry(v->wx, v->x0, v->kx_lat, v->kc, -0.5 * p->lx + i * (p->lx / nx));
+    for (int j = 0; j < ny; ++j) ty[j] = axis_entry(v->wy, v->y0, v->ky_lat, v->kc, -0.5 * p->ly + j * (p->ly / ny));
+    HIP_OK(hipMemcpy(p->tx, tx.data(), sizeof(float4) * nx, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->ty, ty.data(), sizeof(float4) * ny, hipMemcpyHostToDevice));
+    if ((rc = upload_knots(p, v->sx, &p->knots_x, &p->knots_cap_x))) return rc;
+    if ((rc = upload_knots(p, v->sy, &p->knots_y, &p->knots_cap_y))) return rc;
+    potdev_from_desc(p->pot, v, p->dt, p->tx, p->ty, p->knots_x, p->knots_y);
+    const DevState st = initial_state(v);
     HIP_OK(hipMemcpy(p->st, &st, sizeof(st), hipMemcpyHostToDevice));
     p->have_theta = false;
     return GPE_OK;
@@ -267,11 +328,8 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
 {
     if (!out || !d) return fail(GPE_ERR_INVALID, "null argument");
     *out = nullptr;
-    if (!pow2_in(d->nx, 16, 4096) || !pow2_in(d->ny, 16, 4096))
-        return fail(GPE_ERR_INVALID, "nx, ny must be powers of two in [16, 4096]");
-    if (!(d->lx > 0) || !(d->ly > 0) || !(d->dt > 0) || !(d->g >= 0) || !std::isfinite(d->dt) ||
-        !std::isfinite(d->g))
-        return fail(GPE_ERR_INVALID, "need lx, ly, dt > 0 and g >= 0, all finite");
+    int rc0 = check_plan_desc(d);
+    if (rc0) return rc0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(GPE_ERR_DEVICE, "no HIP device");
     gpe_plan *p = new gpe_plan();
@@ -283,13 +341,7 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
     p->g = d->g;
     p->stream = (hipStream_t)d->stream;
     p->max_bytes = d->max_bytes;
-    const char *force = getenv("GPE_PATH");
-    if (force && !strcmp(force, "multipass")) p->path = 1;
-    if (force && !strcmp(force, "lds")) p->path = 2;
-    const char *xcd = getenv("GPE_XCD");
-    if (xcd && !strcmp(xcd, "0")) p->xcd = 0;
-    const char *rep = getenv("GPE_PLAN_GRAPH");
-    if (rep && !strcmp(rep, "0")) p->replay = false;
+    plan_env(p);
     const int nx = d->nx, ny = d->ny;
     p->shape = make_shape(nx, ny);
     int rc = 0;
@@ -339,15 +391,7 @@ int gpe_plan_create(gpe_plan **out, const gpe_plan_desc *d)
         return cleanup(fail(GPE_ERR_NOMEM, "hipHostMalloc"));
     }
     GridDev &gd = p->grid;
-    gd.nx = nx;
-    gd.ny = ny;
-    gd.lx = d->lx;
-    gd.ly = d->ly;
-    gd.dx = d->lx / nx;
-    gd.dy = d->ly / ny;
-    gd.dA = gd.dx * gd.dy;
-    gd.dt = d->dt;
-    gd.g = d->g;
+    griddev_from_desc(gd, d);
     gd.kin_x = p->kin_x;
     gd.kin_y = p->kin_y;
     gd.kim_x = p->kim_x;

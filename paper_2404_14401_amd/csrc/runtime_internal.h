@@ -128,4 +128,15 @@ int dalloc(gpe_plan *p, void **ptr, size_t bytes);
 int energy_terminal(gpe_plan *p, const float2 *psi, float2 *lam, double t, int axis, double *rpart, hipStream_t s,
                     double *loss, double *lat);
 Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles);
+// the launch shape a plan of this size takes (environment overrides included)
+Shape plan_shape(int nx, int ny);
+// descriptor checks and device views shared by gpe_plan_create / gpe_set_potential and
+// the allocation-free entry point
+int check_plan_desc(const gpe_plan_desc *d);
+int check_potential_desc(const gpe_potential_desc *v);
+void griddev_from_desc(GridDev &gd, const gpe_plan_desc *d);
+void potdev_from_desc(PotDev &d, const gpe_potential_desc *v, double dt, const float4 *tx, const float4 *ty,
+                      const double *knots_x, const double *knots_y);
+DevState initial_state(const gpe_potential_desc *v);
+void plan_env(gpe_plan *p);
 

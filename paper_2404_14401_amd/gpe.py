@@ -33,7 +33,7 @@ EXPORTS = (
     "gpe_energy", "gpe_norm", "gpe_get_cavity", "gpe_set_cavity", "gpe_sync", "gpe_last_error",
     "gpe_set_timing", "gpe_get_timing",
     "gpe_batch_create", "gpe_batch_destroy", "gpe_step_batched", "gpe_batch_tune", "gpe_batch_info",
-    "gpe_batch_get_cavity", "gpe_batch_sync", "gpe_adjoint",
+    "gpe_batch_get_cavity", "gpe_batch_sync", "gpe_adjoint", "gpe_step_real_noalloc",
 )
 
 
@@ -103,6 +103,7 @@ def lib():
         L.gpe_batch_get_cavity.argtypes = [P, I, P]
         L.gpe_batch_sync.argtypes = [P, P]
         L.gpe_adjoint.argtypes = [P, P, P, I64, D, P, I, I, I, I, D, P, P, P, P]
+        L.gpe_step_real_noalloc.argtypes = [C.POINTER(PlanDesc), C.POINTER(PotentialDesc), P, I64, D, P]
         for name in EXPORTS:
             if name != "gpe_last_error":
                 getattr(L, name).restype = C.c_int
@@ -347,3 +348,15 @@ def adjoint(batch: Batch, psi0s, targets, nsteps: int, knots, t0: float = 0.0, m
     return out, grad, {"mode": {0: "loss", 1: "reconstruct", 2: "checkpoint", 3: "store"}[int(info[0])],
                        "drift": info[1],
                         "workspace_bytes": int(info[2]), "forward_steps": int(info[3])}
+
+
+def step_real_noalloc(setup, psi, nsteps: int, t0: float = 0.0, stream=None, v_user=None, nonfinite=None):
+    """gpe_step_real_noalloc: real-time steps of `psi` under the plan and potential that
+    `setup` describes, without a plan and without allocating (the library's static
+    scratch holds every table).  nonfinite: optional CUDA int32 tensor of one element
+    that receives 1 if a kick met a non-finite value, else 0."""
+    d = PlanDesc(setup.nx, setup.ny, setup.lx, setup.ly, setup.dt, setup.g, _stream_handle(stream), 0)
+    pd, keep = potential_desc(setup, v_user)
+    flag = _ptr(nonfinite, "int32") if nonfinite is not None else None
+    check(lib().gpe_step_real_noalloc(C.byref(d), C.byref(pd), _ptr(psi), int(nsteps), float(t0), flag))
+    del keep
