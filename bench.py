@@ -647,9 +647,17 @@ def main() -> int:
 
     setup = W.cavity_1024(seed=0)
     npts = setup.nx * setup.ny
-    psi0 = W.to_c64(W.thomas_fermi_guess(setup, float(np.sqrt(setup.g / np.pi) * setup.wx)))
-    psi = torch.from_numpy(psi0).to("cuda")
+    # the run's start: the Thomas-Fermi guess relaxed in imaginary time (trap + pump,
+    # cavity off), here by the library itself
+    psi = torch.from_numpy(W.to_c64(W.cavity_start_guess(setup))).to("cuda")
+    relax = gpe.Plan.from_setup(W.cavity_relax(setup))
+    relax.step_imag(psi, W.CAVITY_RELAX_STEPS, 0.0)
+    relax.sync()
+    relax.close()
+    psi0 = psi.cpu().numpy()
     plan = gpe.Plan.from_setup(setup)
+    # device copies first: their measurement also brings the GPU to its working clock
+    copy = stream_copy_gbs()
 
     plan.step_real(psi, args.warmup, 0.0)
     plan.sync()
@@ -691,8 +699,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "cavity-QED self-consistent real-time split step, 1024x1024 on [-32,32)^2, "
-                        "complex64 state, g=1000, trap w=0.05, Vp=Vc=3, k=1, Delta_c=-20, kappa=10, "
-                        "eta=5*U(seed 0), dt=2e-4",
+                        "complex64 state, g=1000, trap w=0.05, red-detuned Vp=Vc=-25, k=1, Delta_c=-20, "
+                        "kappa=10, eta=5*U(seed 0), dt=2e-4, from the relaxed trap + pump ground state",
             "grid": [setup.ny, setup.nx],
             "storage": "c64",
             "arithmetic": "f64 registers",
@@ -714,8 +722,12 @@ def main() -> int:
                           "frac": 2 * B_PASS * value / (HBM_PEAK_GBS * 1e9)},
         "wall_s": wall,
     }
-    copy = stream_copy_gbs()
     out["stream_copy_gbs"] = copy
+    # the side legs run on their own: the headline's plan and state are released first
+    plan.close()
+    del psi
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     out["step_roofline"]["frac_of_stream_copy"] = 2 * B_PASS * value / (copy * 1e9)
     if args.batched_steps > 0:
         log("batched sweep ...")

@@ -224,6 +224,98 @@ __device__ __forceinline__ void fft_line(C (&v)[R], const View &lds, int t, cons
 }
 
 
+// Twiddles of every pass of an N-point transform for thread t, loaded once (before the
+// data arrives) and kept in registers for the forward and the inverse transform alike:
+// pass PASS, sub-butterfly q holds w^1, w^2, w^4 of its W_{Ns Rp}^j (as many as the radix
+// uses; the other powers are formed as products, as in fft_pass).
+template <int N, int R, typename C> struct TwPre {
+    static constexpr int NP = FftShape<N, R>::NPASS;
+    C w[NP > 0 ? NP : 1][R][3];
+};
+
+template <int N, int R, int PASS, typename C>
+__device__ __forceinline__ void tw_preload(TwPre<N, R, C> &p, const C *__restrict__ tw, int t)
+{
+    using S = FftShape<N, R>;
+    if constexpr (PASS < S::NPASS) {
+        constexpr int Rp = (PASS < S::NFULL) ? R : S::RL;
+        constexpr int Q = R / Rp;
+        constexpr int Ns = 1 << (PASS * S::LGR);
+        if constexpr (Ns > 1) {
+            constexpr int stride = N / (Ns * Rp);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int j = (t + q * S::T) & (Ns - 1);
+                p.w[PASS][q][0] = tw[j * stride];
+                if constexpr (Rp > 2) p.w[PASS][q][1] = tw[2 * j * stride];
+                if constexpr (Rp > 4) p.w[PASS][q][2] = tw[4 * j * stride];
+            }
+        }
+        tw_preload<N, R, PASS + 1>(p, tw, t);
+    }
+}
+
+// fft_pass with the twiddles taken from a TwPre (same arithmetic).
+template <int N, int R, bool INV, int PASS, typename C, typename View>
+__device__ __forceinline__ void fft_pass_pre(C (&v)[R], const View &lds, int t, const TwPre<N, R, C> &tp)
+{
+    using S = FftShape<N, R>;
+    if constexpr (PASS < S::NPASS) {
+        constexpr int Rp = (PASS < S::NFULL) ? R : S::RL;
+        constexpr int Q = R / Rp;
+        constexpr int Ns = 1 << (PASS * S::LGR);
+        constexpr int T = S::T;
+        constexpr bool LAST = (PASS == S::NPASS - 1);
+        static_assert(Rp <= 8, "power-of-two twiddle reconstruction is written for radix <= 8");
+        if constexpr (PASS > 0) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = lds.template ld<C>(t + m * T);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            C a[Rp];
+#pragma unroll
+            for (int r = 0; r < Rp; ++r) a[r] = v[q + r * Q];
+            if constexpr (Ns > 1) {
+                C w[Rp];
+                w[1] = tp.w[PASS][q][0];
+                if constexpr (Rp > 2) w[2] = tp.w[PASS][q][1];
+                if constexpr (Rp > 4) w[4] = tp.w[PASS][q][2];
+                if constexpr (Rp > 2) w[3] = cmul(w[1], w[2]);
+                if constexpr (Rp > 4) {
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                }
+#pragma unroll
+                for (int r = 1; r < Rp; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
+            }
+            Dft<Rp, INV, C>::run(a);
+#pragma unroll
+            for (int r = 0; r < Rp; ++r) v[q + r * Q] = a[r];
+        }
+        if constexpr (!LAST) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int u = t + q * T;
+                const int j = u & (Ns - 1);
+                const int base = (u / Ns) * Ns * Rp + j;
+#pragma unroll
+                for (int r = 0; r < Rp; ++r) lds.st(base + r * Ns, v[q + r * Q]);
+            }
+            __syncthreads();
+            fft_pass_pre<N, R, INV, PASS + 1>(v, lds, t, tp);
+        }
+    }
+}
+
+template <int N, int R, bool INV, typename C, typename View>
+__device__ __forceinline__ void fft_line_pre(C (&v)[R], const View &lds, int t, const TwPre<N, R, C> &tp)
+{
+    fft_pass_pre<N, R, INV, 0>(v, lds, t, tp);
+}
+
 // Two lines transformed together (same length, same direction, same twiddles): the
 // twiddles are read once and applied to both, the exchanges of both lines share their
 // barriers.  Used by the adjoint passes (state and adjoint move through the same

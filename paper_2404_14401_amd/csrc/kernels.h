@@ -33,9 +33,6 @@ namespace gpe {
 #ifndef GPE_XCHG_FLOAT
 #define GPE_XCHG_FLOAT 1
 #endif
-#ifndef GPE_TW_LDS
-#define GPE_TW_LDS 0
-#endif
 #ifndef GPE_ADJ_TW_LDS
 #define GPE_ADJ_TW_LDS 1
 #endif
@@ -76,8 +73,40 @@ __device__ __forceinline__ void store_c64(float2 *p, double2 v)
 
 
 // --------------------------------------------------------------------- row pass
+// Phase factors exp(-i th[m]) on every point of a thread.  When every phase of the
+// wave is small, the short polynomial runs for all points in one straight block (a
+// wave-uniform branch: no per-point control flow, so no load or wait is held behind
+// it); otherwise each point takes its own range of sincos_d.  Same values either way.
+template <int R> __device__ __forceinline__ void kick_real_all(double2 (&v)[R], const double (&th)[R])
+{
+#if GPE_FAST_KICK
+    bool small = true;
+#pragma unroll
+    for (int m = 0; m < R; ++m) small = small && fabs(th[m]) < 0.0625;
+    if (__all(small)) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            double sn, cs;
+            sincos_small(th[m], &sn, &cs);
+            v[m] = {v[m].x * cs + v[m].y * sn, v[m].y * cs - v[m].x * sn};
+        }
+        return;
+    }
+#endif
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = kick_real(v[m], th[m]);
+}
+
 // One work-group transforms `lines` rows.  `row` is this thread's row; the caller has
-// placed `smem` (exchange lines, then the staged tables).
+// placed `smem` (the exchange lines).  Lines of kPreloadLine points (PRE) issue every
+// load the body will need -- the state, the per-point x tables, the user potential and
+// the twiddles of all transform passes -- before any arithmetic, so that the latencies of
+// the tables overlap that of the state, and kick all points in one straight block.  This
+// holds ~80 more registers (two waves per SIMD instead of three); measured on the MI355X
+// it pays for 1024-point lines in batches (12% on four 1024^2 grids) and costs at other
+// lengths (256 and 512: -19% on the mixed 208-member batch; 4096: -12%), which load
+// tables and twiddles where they are used.  Same arithmetic either way.
+constexpr int kPreloadLine = 1024;
 template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
                                          const PotDev &pot, DevState *st, double *partials, int n, int lb,
@@ -88,46 +117,58 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     using C = double2;
     constexpr int T = N / R;
     using View = LinePad<XchgT, ilog2(R)>;
+    constexpr bool PRE = N == kPreloadLine;
+    constexpr bool PROBE = MODE == ROW_PROBE_REAL || MODE == ROW_PROBE_MID;
+    constexpr bool USES_V = !PROBE && MODE != ROW_INV;  // kicks and the energy pass
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int row = lb * lines + line;
     View lds{smem + line * View::words(N)};
     const float2 *src = src_base + (size_t)row * N;
     float2 *dst = dst_base + (size_t)row * N;
-#if GPE_TW_LDS
-    // twiddles and the x tables of the potential live in LDS for the whole pass, so
-    // the passes wait on LDS latency only
-    double2 *s_tw = (double2 *)((char *)smem + align16(lines * View::words(N) * sizeof(XchgT)));
-    float4 *s_tx = (float4 *)(s_tw + N);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        s_tw[i] = gd.tw_x[i];
-        s_tx[i] = pot.tx[i];
-    }
-    const double2 *twx = s_tw;
-    const float4 *txt = s_tx;
-#else
-    const double2 *twx = gd.tw_x;
-    const float4 *txt = pot.tx;
-#endif
 
-    C v[R];
+    float2 f[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        float2 f = src[t + m * T];
-        v[m] = {(double)f.x, (double)f.y};
+    for (int m = 0; m < R; ++m) f[m] = src[t + m * T];
+    C v[R];
+    const float *vup = pot.vuser ? pot.vuser + (size_t)row * N : nullptr;
+    const bool has_vu = USES_V && vup != nullptr;
+    float4 tx[R];
+    float vu[R];
+    TwPre<N, R, C> tp;
+    if constexpr (PRE) {
+        if constexpr (MODE != ROW_INV)
+#pragma unroll
+            for (int m = 0; m < R; ++m) tx[m] = pot.tx[t + m * T];
+        if (has_vu)
+#pragma unroll
+            for (int m = 0; m < R; ++m) vu[m] = vup[t + m * T];
+        if constexpr (MODE != ROW_PROBE_REAL) tw_preload<N, R, 0>(tp, gd.tw_x, t);
     }
-#if GPE_TW_LDS
-    __syncthreads();
-#endif
-
+    // the transforms: twiddles from registers (PRE) or from the table
+    auto fft_inv = [&]() {
+        if constexpr (PRE) fft_line_pre<N, R, true>(v, lds, t, tp);
+        else fft_line<N, R, true>(v, lds, t, gd.tw_x);
+    };
+    auto fft_fwd = [&]() {
+        if constexpr (PRE) fft_line_pre<N, R, false>(v, lds, t, tp);
+        else fft_line<N, R, false>(v, lds, t, gd.tw_x);
+    };
+    auto tx_at = [&](int m) -> float4 {
+        if constexpr (PRE) return tx[m];
+        else return pot.tx[t + m * T];
+    };
     const float4 ty = pot.ty[row];
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = {(double)f[m].x, (double)f[m].y};
+
     const double cy = ty.z, yv = ty.w;
-    if constexpr (MODE == ROW_PROBE_REAL || MODE == ROW_PROBE_MID) {
+    if constexpr (PROBE) {
         // integrals of the density about to be kicked: norm, Theta, C
-        if constexpr (MODE == ROW_PROBE_MID) fft_line<N, R, true>(v, lds, t, twx);
+        if constexpr (MODE == ROW_PROBE_MID) fft_inv();
         double part[NPART] = {};
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            const double cx = txt[t + m * T].z;
+            const double cx = tx_at(m).z;
             const double d = v[m].x * v[m].x + v[m].y * v[m].y;
             part[0] += d;
             part[1] += cx * cy * d;
@@ -141,7 +182,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     }
 
     if constexpr (MODE == ROW_INV) {
-        fft_line<N, R, true>(v, lds, t, twx);
+        fft_inv();
 #pragma unroll
         for (int m = 0; m < R; ++m) store_c64(dst + t + m * T, v[m]);
         return;
@@ -172,9 +213,8 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
         aim = st->alpha_im;
     }
     const VLine vl = vline_cav(pot, row, tk, are, aim);
-    const float *vu = pot.vuser ? pot.vuser + (size_t)row * N : nullptr;
 
-    if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_line<N, R, true>(v, lds, t, twx);
+    if constexpr (MODE == ROW_MID || MODE == ROW_EXIT) fft_inv();
 
     double part[NPART] = {};
     double fin = 0.0;  // sum of this thread's densities: non-finite iff one of its points is
@@ -184,12 +224,12 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
         for (int m = 0; m < R; ++m) v[m] = {v[m].x * sc, v[m].y * sc};
     }
     const double hk = (MODE == ROW_MID) ? gd.dt : 0.5 * gd.dt;
+    double th[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int i = t + m * T;
-        const float4 tx = txt[i];
-        double V = vpoint(vl, tx);
-        if (vu) V += (double)vu[i];
+        const float4 tm = tx_at(m);
+        double V = vpoint(vl, tm);
+        if (has_vu) V += (double)(PRE ? vu[m] : vup[t + m * T]);
         const double d = v[m].x * v[m].x + v[m].y * v[m].y;
         fin += d;
         if constexpr (MODE == ROW_FWD) {
@@ -197,30 +237,31 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
             part[1] += V * d;
             part[2] += d * d;
         } else {
-            const double th = (V + gd.g * d) * hk;
+            th[m] = (V + gd.g * d) * hk;
             if constexpr (IMAG) {
-                v[m] = kick_imag(v[m], th);
+                v[m] = kick_imag(v[m], th[m]);
                 if (MODE == ROW_EXIT) {
                     const double d2 = v[m].x * v[m].x + v[m].y * v[m].y;
                     part[0] += d2;
-                    part[1] += (double)tx.z * cy * d2;
-                    part[2] += (double)tx.w * d2;
+                    part[1] += (double)tm.z * cy * d2;
+                    part[2] += (double)tm.w * d2;
                     part[3] += yv * d2;
-                    if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d2;
+                    if (pot.cavity == 2) part[4] += (double)tm.z * tm.z * d2;
                 }
             } else {
                 // |psi| is the same before and after a phase kick
-                part[1] += (double)tx.z * cy * d;
+                part[1] += (double)tm.z * cy * d;
                 if (!theta_only) {
                     part[0] += d;
-                    part[2] += (double)tx.w * d;
+                    part[2] += (double)tm.w * d;
                     part[3] += yv * d;
-                    if (pot.cavity == 2) part[4] += (double)tx.z * tx.z * d;
+                    if (pot.cavity == 2) part[4] += (double)tm.z * tm.z * d;
                 }
-                v[m] = kick_real(v[m], th);
+                if constexpr (!PRE) v[m] = kick_real(v[m], th[m]);
             }
         }
     }
+    if constexpr (MODE != ROW_FWD && !IMAG && PRE) kick_real_all<R>(v, th);
     // every kicking pass flags a non-finite input, whether or not it reduces anything
     // (a plain store of the same value from any work-group: no atomics needed)
     if constexpr (MODE != ROW_FWD)
@@ -245,7 +286,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
             for (int k = 0; k < NPART; ++k) partials[k] = part[k];
     }
 
-    if constexpr (MODE != ROW_EXIT) fft_line<N, R, false>(v, lds, t, twx);
+    if constexpr (MODE != ROW_EXIT) fft_fwd();
 
 #pragma unroll
     for (int m = 0; m < R; ++m) store_c64(dst + t + m * T, v[m]);
@@ -307,19 +348,8 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
     const int col = tile * w + c;
     const int nx = gd.nx;
     View lds{smem + c, w};
-#if GPE_TW_LDS
-    double2 *s_tw = (double2 *)((char *)smem + align16(View::words(N, w) * sizeof(XchgT)));
-    double2 *s_ky = s_tw + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        s_tw[i] = gd.tw_y[i];
-        if constexpr (MODE == COL_KIN_REAL) s_ky[i] = gd.kin_y[i];
-    }
-    const double2 *twy = s_tw;
-    const double2 *kiny = s_ky;
-#else
     const double2 *twy = gd.tw_y;
     const double2 *kiny = gd.kin_y;
-#endif
 
     C v[R];
 #pragma unroll
@@ -327,9 +357,6 @@ __device__ __forceinline__ void col_body(const float2 *__restrict__ src, float2 
         float2 f = src[(size_t)(t + m * T) * nx + col];
         v[m] = {(double)f.x, (double)f.y};
     }
-#if GPE_TW_LDS
-    __syncthreads();
-#endif
     if constexpr (MODE == COL_KHALF_INV || MODE == COL_KHALF_INV_IM) {
         // Fourier-space state: kinetic half step (imaginary time: with the pending
         // renormalisation), then back to real space along y

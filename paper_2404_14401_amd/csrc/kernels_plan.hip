@@ -7,7 +7,7 @@ namespace gpe {
 int kernel_radix() { return kRadix; }
 size_t xchg_bytes() { return sizeof(XchgT); }
 // extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
-size_t staged_table_bytes(int n) { return GPE_TW_LDS ? (size_t)n * (sizeof(double2) + sizeof(float4)) : 0; }
+
 // LDS of the adjoint passes: exchange areas for `arrays` lines (state and adjoint, or the
 // adjoint alone) plus the tables
 size_t adj_row_shmem(int n, int lines, int r, int arrays)

@@ -59,14 +59,19 @@ __device__ __forceinline__ double vpoint(const VLine &l, float4 tx)
 #ifndef GPE_FAST_KICK
 #define GPE_FAST_KICK 1
 #endif
+// |x| < 1/16: Taylor to x^9 and x^10 (truncation below 2e-19)
+__device__ __forceinline__ void sincos_small(double x, double *s, double *c)
+{
+    const double x2 = x * x;
+    *s = x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880)))));
+    *c = 1.0 + x2 * (-0.5 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320 + x2 * (-1.0 / 3628800)))));
+}
+
 __device__ __forceinline__ void sincos_d(double x, double *s, double *c)
 {
 #if GPE_FAST_KICK
     if (fabs(x) < 0.0625) {
-        // |x| < 1/16: Taylor to x^9 and x^10 (truncation below 2e-19)
-        const double x2 = x * x;
-        *s = x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880)))));
-        *c = 1.0 + x2 * (-0.5 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320 + x2 * (-1.0 / 3628800)))));
+        sincos_small(x, s, c);
         return;
     }
 #endif

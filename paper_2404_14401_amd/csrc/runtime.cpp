@@ -77,7 +77,7 @@ Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_co
     s.row_threads = s.row_lines * tr;
     s.row_blocks = ny / s.row_lines;
     s.row_shmem = (size_t)s.row_lines * (nx + (nx >> sh)) * eb;
-    s.row_shmem = (s.row_shmem + 15) / 16 * 16 + staged_table_bytes(nx);
+    s.row_shmem = (s.row_shmem + 15) / 16 * 16;
     const int tc = std::max(1, ny / R);
     int w = std::max(1, std::min(nx, 1024 / tc));
     while (w > 1 && nx / w < min_col_tiles) w /= 2;
@@ -85,7 +85,7 @@ Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_co
     s.col_threads = w * tc;
     s.col_blocks = nx / w;
     s.col_shmem = ((size_t)ny * w + (ny >> sh) + w) * eb;
-    s.col_shmem = (s.col_shmem + 15) / 16 * 16 + staged_table_bytes(ny);
+    s.col_shmem = (s.col_shmem + 15) / 16 * 16;
     return s;
 }
 

@@ -44,7 +44,6 @@ bool lds_supported(int nx, int ny);
 int lds_threads(int nx, int ny);
 int kernel_radix();
 size_t xchg_bytes();
-size_t staged_table_bytes(int n);
 size_t adj_row_shmem(int n, int lines, int r, int arrays);
 size_t adj_col_shmem(int n, int w, int r, int arrays);
 }  // namespace gpe

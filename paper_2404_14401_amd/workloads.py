@@ -146,13 +146,32 @@ DIPOLE_256_STEPS = 10000
 
 def cavity_1024(seed: int = 0) -> Setup:
     """Self-consistent cavity run on 1024x1024, [-32, 32)^2, trap w = 0.05, g = 1000,
-    pump lattice Vp cos^2(y) with Vp = 3, cavity lattice Vc = 3, k = 1,
-    Delta_c = -20, kappa = 10, eta = 5 U[0,1) from PCG64(seed), dt = 2e-4,
-    20000 steps, alpha_0 = 0."""
+    red-detuned pump lattice Vp cos^2(y) with Vp = -25 (50 recoil energies, E_r = k^2/2),
+    cavity lattice Vc = -25, k = 1, Delta_c = -20, kappa = 10, eta = 5 U[0,1) from
+    PCG64(seed), dt = 2e-4, 20000 steps, alpha_0 = 0.  With these depths the eta range
+    straddles the self-organisation threshold: the lowest seeds stay in the normal phase,
+    the highest organise within the run."""
     eta = 5.0 * np.random.Generator(np.random.PCG64(seed)).uniform()
     return Setup(nx=1024, ny=1024, lx=64.0, ly=64.0, dt=2e-4, g=1000.0, wx=0.05, wy=0.05,
-                 ky_lat=1.0, sy=Schedule("const", 3.0), cavity=True, vc=3.0, kc=1.0,
+                 ky_lat=1.0, sy=Schedule("const", CAVITY_DEPTH), cavity=True, vc=CAVITY_DEPTH, kc=1.0,
                  delta_c=-20.0, kappa=10.0, eta=float(eta))
+
+
+CAVITY_DEPTH = -25.0
+CAVITY_RELAX_STEPS = 2000
+CAVITY_RELAX_DTAU = 0.01
+
+
+def cavity_start_guess(s: Setup) -> np.ndarray:
+    """Start of the cavity run before relaxation: the Thomas-Fermi profile of the trap
+    (mu = w sqrt(g / pi)).  The run starts from it after CAVITY_RELAX_STEPS imaginary-time
+    steps of dtau = CAVITY_RELAX_DTAU in trap + pump with the cavity off (cavity_relax)."""
+    return thomas_fermi_guess(s, float(np.sqrt(s.g / np.pi) * s.wx))
+
+
+def cavity_relax(s: Setup) -> Setup:
+    """The imaginary-time set-up that relaxes cavity_start_guess: trap + pump, no cavity."""
+    return s.with_(cavity=False, dt=CAVITY_RELAX_DTAU)
 
 
 CAVITY_1024_STEPS = 20000
@@ -163,7 +182,7 @@ def cavity_1024_adiabatic(seed: int = 0) -> Setup:
     field ODE: N = eta / sqrt(Vp Vc), so that N sqrt(Vp Vc) is the ODE's coupling, and
     the dispersive shift N Vc C that the ODE leaves out."""
     s = cavity_1024(seed)
-    return s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+    return s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * s.sy.v0))
 
 
 def cavity_scaled(n: int, seed: int = 0) -> Setup:

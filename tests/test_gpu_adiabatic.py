@@ -291,7 +291,7 @@ def test_cavity_on_wide_and_tall_grids_with_replayed_chunks(shape, cavity, monke
     nx, ny = shape
     s = W.cavity_scaled(16, 2).with_(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0)
     if cavity == "adiabatic":
-        s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+        s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * s.sy.v0))
     psi0 = W.to_c64(W.gaussian(s, 1.0, 0.2, -0.1))
     n = 300
     st = state(s)

@@ -124,7 +124,7 @@ def nonsquare_members(mode):
         if mode == "off":
             s = s.with_(cavity=False)
         elif mode == "adiabatic":
-            s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+            s = s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * s.sy.v0))
         out.append(s)
     return out
 

@@ -2,8 +2,9 @@
 
 * dipole + lattice ramp, 256^2, 1e4 steps: psi and energy vs the oracle, norm, the
   Kohn dipole closed form, energy drift once the Hamiltonian is constant;
-* cavity, 1024^2, 2e4 steps: sampled final state, energy and the cavity field vs the
-  stored oracle run (tests/golden, written by make_cavity_1024.py);
+* cavity, 1024^2, 2e4 steps: the whole final state (an organising seed) or a subsampled
+  one (a seed in the normal phase), energy, the cavity field and the overlap history vs
+  the stored oracle runs (tests/golden, written by make_cavity_1024.py);
 * 208-member sweep, 5000 steps: sampled members vs the plain solver and the oracle;
 * 16 x 512^2 control gradient, 5000 steps: GPU finite differences, reconstruction drift,
   and the oracle adjoint on a shorter horizon; the stored trajectory at full size against
@@ -66,37 +67,57 @@ def test_dipole_lattice_256_full_length(dipole_start):
     assert np.abs(o[:, 5] - robs[:, 5]).max() < 1e-5
 
 
-def test_cavity_1024_full_length_against_stored_oracle_run():
+def cavity_golden(seed):
+    """The stored oracle run of the cavity workload for `seed` and its start state
+    (written by tests/golden/make_cavity_1024.py, which calls only the oracle)."""
+    path = os.path.join(HERE, "golden", f"cavity_1024_seed{seed}.npz")
+    start = os.path.join(HERE, "golden", "cavity_1024_start.npz")
+    if not (os.path.exists(path) and os.path.exists(start)):
+        pytest.skip("reference not generated (tests/golden/make_cavity_1024.py)")
+    g = np.load(path)
+    st = np.load(start)
+    return g, (st["re"] + 1j * st["im"]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("seed", [4, 3])
+def test_cavity_1024_full_length_against_stored_oracle_run(seed):
+    """The cavity workload at full size and length (1024^2, 2e4 steps) against the FP64
+    oracle's run from the same start: seed 4 (eta = 4.72) organises within the run,
+    |alpha| reaching ~1.5e-2, and is compared on the whole final grid; seed 3 (eta = 0.43)
+    stays in the normal phase and is compared through its field and overlap history and a
+    subsampled final state.  Field and overlap are bounded relative to the run's own scale."""
     torch = torch_cuda()
     from paper_2404_14401_amd import gpe
 
-    path = os.path.join(HERE, "golden", "cavity_1024_seed0.npz")
-    if not os.path.exists(path):
-        pytest.skip("reference not generated (tests/golden/make_cavity_1024.py)")
-    import importlib.util
-
-    spec = importlib.util.spec_from_file_location("make_cavity_1024", os.path.join(HERE, "golden", "make_cavity_1024.py"))
-    mk = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mk)
-    g = np.load(path)
-    s = W.cavity_1024(int(g["seed"]))
+    g, psi0 = cavity_golden(seed)
+    s = W.cavity_1024(seed)
+    assert float(g["eta"]) == s.eta and float(g["depth"]) == W.CAVITY_DEPTH  # reference of this workload
     n = int(g["nsteps"])
-    psi0 = mk.start_state(s)
     plan = gpe.Plan.from_setup(s)
     d = to_dev(psi0)
     obs = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
     plan.step_real(d, n, 0.0, obs)
     out = to_host(d)
-    sub = int(g["sub"])
-    assert rel_l2(out[::sub, ::sub], g["psi_sub"]) < 1e-4
-    alpha = plan.cavity()["alpha"]
+    if "psi" in g.files:
+        ref = g["psi"].astype(np.complex128)
+        assert rel_l2(out, ref) < 1e-4
+        assert np.abs(out - ref).max() < 1e-4 * np.abs(ref).max()
+    else:
+        sub = int(g["sub"])
+        assert rel_l2(out[::sub, ::sub], g["psi_sub"]) < 1e-4
     e = plan.energy(d, n * s.dt)
     assert rel_e(e["e"], g["energy"][3]) < 1e-5
     o = obs.cpu().numpy()
+    a_ref, th_ref = g["alpha"], g["theta"]
     a_gpu = o[99::100, 2] + 1j * o[99::100, 3]
-    assert np.abs(a_gpu - g["alpha"]).max() <= 1e-4 * max(np.abs(g["alpha"]).max(), 1e-3)
-    assert abs(alpha - g["alpha"][-1]) <= 1e-4 * max(abs(g["alpha"][-1]), 1e-3)
-    assert np.abs(o[99::100, 1] - g["theta"]).max() < 1e-5
+    assert np.abs(a_gpu - a_ref).max() <= 1e-4 * np.abs(a_ref).max()
+    assert np.abs(o[99::100, 1] - th_ref).max() <= 1e-4 * np.abs(th_ref).max()
+    assert abs(plan.cavity()["alpha"] - a_ref[-1]) <= 1e-4 * np.abs(a_ref).max()
+    # the reading puts the eta range across the threshold: organised vs normal phase
+    if seed == 4:
+        assert np.abs(a_ref).max() > 1e-2
+    else:
+        assert np.abs(a_ref).max() < 1e-5
 
 
 def test_sweep_208_full_length_sampled_members():
@@ -173,8 +194,7 @@ def test_cavity_1024_eta_sweep_batched_equals_plain_runs():
     from paper_2404_14401_amd import gpe
 
     setups = [W.cavity_1024(seed) for seed in range(4)]
-    s0 = setups[0]
-    psi0 = W.to_c64(W.thomas_fermi_guess(s0, float(np.sqrt(s0.g / np.pi) * s0.wx)))
+    _, psi0 = cavity_golden(4)
     n = 300
     b = gpe.Batch(setups)
     devs = [to_dev(psi0) for _ in setups]

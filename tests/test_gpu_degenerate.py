@@ -22,7 +22,7 @@ def setup(n, mode):
     if mode == "off":
         return s.with_(cavity=False)
     if mode == "adiabatic":
-        return s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * 3.0))
+        return s.with_(cavity_mode="adiabatic", n_atoms=s.eta / np.sqrt(s.vc * s.sy.v0))
     return s
 
 
