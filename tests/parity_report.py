@@ -185,6 +185,18 @@ def c5():
     l_o, g_o, _ = O.adjoint(problem(sh), 0.0, p0, tg, ns)
     row(f"C5 gradient vs the oracle adjoint (512^2, {ns} steps, 20 knots)",
         grad_rel_L2=float(np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o)), loss_abs=abs(float(l_g[0]) - l_o))
+    here = os.path.dirname(os.path.abspath(__file__))
+    g = np.load(os.path.join(here, "golden", "control_512_member3.npz"))
+    sm = W.control_512(int(g["member"]))
+    p0 = (g["psi0_re"] + 1j * g["psi0_im"]).astype(np.complex64)
+    tg = (g["target_re"] + 1j * g["target_im"]).astype(np.complex64)
+    bm = gpe.Batch([sm])
+    for mode in ("reconstruct", "checkpoint", "store"):
+        l_g, g_g, _ = gpe.adjoint(bm, [dev(p0)], [dev(tg)], n, sm.sx.knots[None, :], mode=mode)
+        row(f"C5 member {int(g['member'])} vs the stored oracle adjoint ({n} steps, 200 knots, {mode})",
+            grad_rel_L2=float(np.linalg.norm(g_g[0] - g["grad"]) / np.linalg.norm(g["grad"])),
+            loss_rel=abs(float(l_g[0]) - float(g["loss"])) / float(g["loss"]),
+            fd_rel=float(max(abs(g_g[0, m] - f) for m, f in zip(g["fd_knots"], g["fd"])) / np.abs(g["grad"]).max()))
 
 
 def widened_1024():

@@ -7,7 +7,8 @@
   the stored oracle runs (tests/golden, written by make_cavity_1024.py);
 * 208-member sweep, 5000 steps: sampled members vs the plain solver and the oracle;
 * 16 x 512^2 control gradient, 5000 steps: GPU finite differences, reconstruction drift,
-  and the oracle adjoint on a shorter horizon; the stored trajectory at full size against
+  and the oracle adjoint on a shorter horizon; one member at the full horizon against the
+  stored oracle adjoint and its central differences; the stored trajectory at full size against
   reconstruction, and the energy loss against GPU finite differences;
 * the cavity workload's eta sweep as one batch of four 1024^2 runs against plain runs.
 """
@@ -185,6 +186,33 @@ def test_control_512_full_size_gradient():
     l_o, g_o, _ = O.adjoint(problem(sh), 0.0, p0, t0, ns)
     assert abs(l_g[0] - l_o) < 1e-5
     assert np.linalg.norm(g_g[0] - g_o) / np.linalg.norm(g_o) < 1e-3
+
+
+def test_control_512_member_gradient_against_oracle_adjoint_full_horizon():
+    """One member of the control workload at full size and horizon (512^2, 5000 steps,
+    200 knots) against the FP64 oracle's discrete adjoint from the same start and target
+    (tests/golden/make_control_512.py): loss, the whole 200-knot gradient (rel-L2 <= 1e-3),
+    and the oracle's central differences (h = 1e-3) on three seeded knots; every mode."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    path = os.path.join(HERE, "golden", "control_512_member3.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated (tests/golden/make_control_512.py)")
+    g = np.load(path)
+    s = W.control_512(int(g["member"]))
+    n = int(g["nsteps"])
+    psi0 = (g["psi0_re"] + 1j * g["psi0_im"]).astype(np.complex64)
+    tgt = (g["target_re"] + 1j * g["target_im"]).astype(np.complex64)
+    ref = g["grad"]
+    b = gpe.Batch([s])
+    for mode in ("reconstruct", "checkpoint", "store"):
+        loss, grad, info = gpe.adjoint(b, [to_dev(psi0)], [to_dev(tgt)], n, s.sx.knots[None, :], mode=mode)
+        assert info["mode"] == mode
+        assert abs(loss[0] - float(g["loss"])) < 1e-5 * float(g["loss"]) + 1e-6, mode
+        assert np.linalg.norm(grad[0] - ref) / np.linalg.norm(ref) <= 1e-3, mode
+        for m, fd in zip(g["fd_knots"], g["fd"]):
+            assert abs(grad[0, m] - fd) <= 1e-3 * np.abs(ref).max(), (mode, int(m), grad[0, m], fd)
 
 
 def test_cavity_1024_eta_sweep_batched_equals_plain_runs():

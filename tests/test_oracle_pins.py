@@ -453,6 +453,23 @@ def test_adjoint_matches_central_differences(loss):
     assert np.abs(grad - fd).max() / np.abs(fd).max() < 1e-6
 
 
+def test_full_size_control_reference_gradient_matches_its_central_differences():
+    """The stored full-size control reference (512^2, 5000 steps, 200 knots; written by
+    tests/golden/make_control_512.py from the oracle alone): the discrete adjoint's
+    gradient equals the oracle's own central differences (h = 1e-3, truncation ~h^2) on
+    the three seeded knots to 1e-6 relative -- the adjoint pinned at the workload's size."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "control_512_member3.npz")
+    g = np.load(path)
+    grad = g["grad"]
+    assert grad.size == 200 and int(g["nsteps"]) == W.CONTROL_STEPS
+    for m, fd in zip(g["fd_knots"], g["fd"]):
+        assert abs(grad[m] - fd) <= 1e-6 * abs(fd), (int(m), grad[m], fd)
+    # the sampled knots carry gradient of the size of the whole vector (not a trivial pin)
+    assert np.abs(g["fd"]).min() > 0.02 * np.abs(grad).max()
+
+
 @pytest.mark.parametrize("loss", ["fidelity", "energy"])
 def test_pump_control_adjoint_matches_central_differences_and_transposition(loss):
     """Control of the y (pump) lattice depth with a static x lattice present: central
