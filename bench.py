@@ -412,7 +412,7 @@ def bench_grid_sweep(steps: int, runs: int, side_steps: int):
     """The paper's timing experiment reshaped for this library (Sec. 4.1): imaginary time
     for a non-interacting condensate in a fixed harmonic trap, Nx = Ny = 2^n on
     [-8, 8)^2, dtau = 1e-3, `steps` steps per run, the mean over `runs` runs; n from 6 to
-    12, the plan's largest grid.  Small grids take the LDS-resident path.  Beside it, on
+    13 (the paper's range; 8192^2 is the plan's largest grid).  Small grids take the LDS-resident path.  Beside it, on
     bounded samples of `side_steps` steps scaled to `steps`: the paper's route (torch.fft
     and elementwise ops) on the GPU in complex128 and complex64.  (The oracle's times for
     the same sweep are part of the cpu_baseline leg.)"""
@@ -423,7 +423,7 @@ def bench_grid_sweep(steps: int, runs: int, side_steps: int):
     from paper_2404_14401_amd import workloads as W
 
     rows = []
-    for n in range(6, 13):
+    for n in range(6, 14):
         s = sweep_setup(n)
         p = gpe.Plan.from_setup(s)
         psi = torch.from_numpy(W.to_c64(W.gaussian(s, 1.5))).to("cuda")

@@ -68,7 +68,7 @@ typedef struct {
     float re, im;
 } gpe_c64;
 
-/* Plan description.  nx, ny: powers of two in [16, 4096]; lx, ly > 0: box lengths;
+/* Plan description.  nx, ny: powers of two in [16, 8192]; lx, ly > 0: box lengths;
  * dt > 0: time step (imaginary time: dtau); g >= 0: interaction strength (already the
  * effective 2D, norm-absorbing value, Sec. 3.2); stream: a hipStream_t, NULL for the
  * null stream; max_bytes: cap on the plan's own device memory (0: none). */
@@ -295,13 +295,13 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
  * without a plan.  The call does what gpe_step_real does on a fresh plan created from
  * desc with potential pot (same kernels, same launch shapes): the cavity field starts at
  * alpha0 with no overlap history.  Instead of plan memory it uses one static device array
- * of 1 MiB (per device, held until the process ends): every call rebuilds the tables in
+ * of 2 MiB (per device, held until the process ends): every call rebuilds the tables in
  * it with kernels and issues only kernel launches on desc->stream -- no hipMalloc, no
  * hipFree, no memset, no host-to-device copy, no graph of its own.  Calls on one device
  * share the array, so calls that overlap on one device (other streams or threads) race.
  * desc, pot: as for gpe_plan_create / gpe_set_potential (host, read during the call);
  * knot schedules hold at most 256 knots; every grid the plan takes (powers of two 16 to
- * 4096 per side) fits the array.  psi: device [ny][nx] gpe_c64, updated in place,
+ * 8192 per side) fits the array.  psi: device [ny][nx] gpe_c64, updated in place,
  * asynchronously.  nonfinite: optional device int that receives 1 if a kick met a NaN or
  * an infinity in psi, else 0 (the call itself cannot wait for the device); untouched when
  * nsteps = 0.  No observables.  Errors: GPE_ERR_INVALID for bad descriptors, negative

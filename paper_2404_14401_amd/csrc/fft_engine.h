@@ -172,19 +172,23 @@ __device__ __forceinline__ void fft_pass(C (&v)[R], const View &lds, int t, cons
             if constexpr (Ns > 1) {
                 constexpr int stride = N / (Ns * Rp);
 #if GPE_TW_POW2
-                // powers w^1, w^2, w^4 from the table, the others as FP64 products
-                // (rounding ~1e-16 per product, far below the complex64 storage)
+                // powers w^1, w^2, w^4 (and w^8) from the table, the others as FP64
+                // products (rounding ~1e-16 per product, far below the complex64 storage)
                 C w[Rp];
                 w[1] = tw[j * stride];
                 if constexpr (Rp > 2) w[2] = tw[2 * j * stride];
                 if constexpr (Rp > 4) w[4] = tw[4 * j * stride];
+                if constexpr (Rp > 8) w[8 % Rp] = tw[8 * j * stride];
                 if constexpr (Rp > 2) w[3] = cmul(w[1], w[2]);
                 if constexpr (Rp > 4) {
                     w[5] = cmul(w[1], w[4]);
                     w[6] = cmul(w[2], w[4]);
                     w[7] = cmul(w[3], w[4]);
                 }
-                static_assert(Rp <= 8, "power-of-two twiddle reconstruction is written for radix <= 8");
+                if constexpr (Rp > 8)
+#pragma unroll
+                    for (int r = 9; r < Rp; ++r) w[r] = cmul(w[r - 8], w[8 % Rp]);
+                static_assert(Rp <= 16, "power-of-two twiddle reconstruction is written for radix <= 16");
 #pragma unroll
                 for (int r = 1; r < Rp; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
 #else

@@ -292,12 +292,17 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     for (int m = 0; m < R; ++m) store_c64(dst + t + m * T, v[m]);
 }
 
+// Points per thread of the plan's row passes: kRadix, except for 8192-point lines, whose
+// 512 threads at radix 16 stay within the row pass's 512-thread bound (radix 8 would need
+// 1024 threads, which caps a thread at 128 registers; the fused row pass holds more).
+template <int N> constexpr int kRowRadix = N >= 8192 ? 16 : kRadix;
+
 template <int N, int MODE, bool IMAG>
 __global__ void __launch_bounds__(512) row_pass(RowArgs a)
 {
     extern __shared__ XchgT smem[];
     __shared__ double red[8 * NPART];
-    row_body<N, kRadix, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
+    row_body<N, kRowRadix<N>, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
                                      a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
                                      a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe, a.reduce == 2);
 }

@@ -5,6 +5,7 @@
 namespace gpe {
 
 int kernel_radix() { return kRadix; }
+int row_radix(int n) { return n >= 8192 ? kRowRadix<8192> : kRadix; }
 size_t xchg_bytes() { return sizeof(XchgT); }
 // extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
 
@@ -169,6 +170,7 @@ hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, 
     case 1024: return row_dispatch<1024>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
     case 2048: return row_dispatch<2048>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
     case 4096: return row_dispatch<4096>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
+    case 8192: return row_dispatch<8192>(mode, imag, a, blocks, threads, shmem, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -216,6 +218,7 @@ hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads
     case 1024: return col_dispatch<1024>(mode, a, blocks, threads, shmem, s, e0, e1);
     case 2048: return col_dispatch<2048>(mode, a, blocks, threads, shmem, s, e0, e1);
     case 4096: return col_dispatch<4096>(mode, a, blocks, threads, shmem, s, e0, e1);
+    case 8192: return col_dispatch<8192>(mode, a, blocks, threads, shmem, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

@@ -17,9 +17,9 @@
 
 #include "runtime_internal.h"
 
-// Largest grid: 4096 x 4096 needs 6 tables of 4096 16-byte entries (384 KiB), two knot
-// arrays and three partial buffers of 4096 work-groups x NPART doubles (480 KiB).
-static constexpr size_t kScratchBytes = size_t(1) << 20;
+// Largest grid: 8192 x 8192 needs 6 tables of 8192 16-byte entries (768 KiB), two knot
+// arrays and three partial buffers of 8192 work-groups x NPART doubles (960 KiB).
+static constexpr size_t kScratchBytes = size_t(2) << 20;
 
 // Host code never uses this name as an address: it stands for the array only in
 // hipGetSymbolAddress; kernels get the per-device address that call returns.
@@ -180,7 +180,7 @@ extern "C" int gpe_step_real_noalloc(const gpe_plan_desc *d, const gpe_potential
     const int npart = std::max(std::max(sh.row_blocks, sh.col_blocks), 256);
     const Layout L = layout(nx, ny, npart);
     if (L.total > kScratchBytes)
-        return fail(GPE_ERR_INVALID, "gpe_step_real_noalloc: the grid's tables exceed the 1 MiB static scratch");
+        return fail(GPE_ERR_INVALID, "gpe_step_real_noalloc: the grid's tables exceed the 2 MiB static scratch");
     unsigned char *base = nullptr;
     if ((rc = scratch_base(&base))) return rc;
     if (nsteps == 0) return GPE_OK;

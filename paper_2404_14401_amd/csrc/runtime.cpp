@@ -65,18 +65,20 @@ static int env_int(const char *name, int dflt)
 // work-group has about 128 threads (one 1024-point line at radix 8; measured best at
 // 1024^2, where more work-groups spread the pass's latency over more CUs).  Columns: tiles of W adjacent columns, W chosen
 // so that there are at least 256 tiles (one per CU) when the grid allows it.
-Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles)
+Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles, int row_r)
 {
     Shape s{};
-    int sh = 0;
+    if (row_r <= 0) row_r = R;
+    int sh = 0, shr = 0;
     while ((1 << sh) < R) ++sh;
-    const int tr = std::max(1, nx / R);
+    while ((1 << shr) < row_r) ++shr;
+    const int tr = std::max(1, nx / row_r);
     s.row_lines = std::max(1, row_threads / tr);
     if (s.row_lines > ny) s.row_lines = ny;
     if (s.row_lines * tr > 512) s.row_lines = std::max(1, 512 / tr);
     s.row_threads = s.row_lines * tr;
     s.row_blocks = ny / s.row_lines;
-    s.row_shmem = (size_t)s.row_lines * (nx + (nx >> sh)) * eb;
+    s.row_shmem = (size_t)s.row_lines * (nx + (nx >> shr)) * eb;
     s.row_shmem = (s.row_shmem + 15) / 16 * 16;
     const int tc = std::max(1, ny / R);
     int w = std::max(1, std::min(nx, 1024 / tc));
@@ -92,10 +94,11 @@ Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_co
 static Shape make_shape(int nx, int ny)
 {
     Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128),
-                           env_int("GPE_MIN_COL_TILES", 256));
+                           env_int("GPE_MIN_COL_TILES", 256), row_radix(nx));
     const int w = env_int("GPE_COL_W", 0);
     if (w > 0 && w <= nx && (w & (w - 1)) == 0 && w * s.col_threads / s.col_cols <= 1024) {
-        Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128), nx / w);
+        Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128), nx / w,
+                               row_radix(nx));
         s = t;
     }
     return s;
@@ -260,8 +263,8 @@ DevState initial_state(const gpe_potential_desc *v)
 
 int check_plan_desc(const gpe_plan_desc *d)
 {
-    if (!pow2_in(d->nx, 16, 4096) || !pow2_in(d->ny, 16, 4096))
-        return fail(GPE_ERR_INVALID, "nx, ny must be powers of two in [16, 4096]");
+    if (!pow2_in(d->nx, 16, 8192) || !pow2_in(d->ny, 16, 8192))
+        return fail(GPE_ERR_INVALID, "nx, ny must be powers of two in [16, 8192]");
     if (!(d->lx > 0) || !(d->ly > 0) || !(d->dt > 0) || !(d->g >= 0) || !std::isfinite(d->dt) ||
         !std::isfinite(d->g) || !std::isfinite(d->lx) || !std::isfinite(d->ly))
         return fail(GPE_ERR_INVALID, "need lx, ly, dt > 0 and g >= 0, all finite");

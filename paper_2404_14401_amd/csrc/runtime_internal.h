@@ -43,6 +43,8 @@ hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, cons
 bool lds_supported(int nx, int ny);
 int lds_threads(int nx, int ny);
 int kernel_radix();
+// points per thread of the plan's row passes for n-point lines
+int row_radix(int n);
 size_t xchg_bytes();
 size_t adj_row_shmem(int n, int lines, int r, int arrays);
 size_t adj_col_shmem(int n, int w, int r, int arrays);
@@ -126,7 +128,8 @@ int dalloc(gpe_plan *p, void **ptr, size_t bytes);
 // with the plan's own partial buffers and rpart (ny doubles); returns after a sync.
 int energy_terminal(gpe_plan *p, const float2 *psi, float2 *lam, double t, int axis, double *rpart, hipStream_t s,
                     double *loss, double *lat);
-Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles);
+// launch shape at R points per thread (row passes at row_r, when > 0)
+Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_col_tiles, int row_r = 0);
 // the launch shape a plan of this size takes (environment overrides included)
 Shape plan_shape(int nx, int ny);
 // descriptor checks and device views shared by gpe_plan_create / gpe_set_potential and

@@ -36,7 +36,7 @@ def _desc(nx=64, ny=64, lx=8.0, ly=8.0, dt=0.01, g=1.0):
 def test_invalid_plans_are_rejected_before_any_device_call():
     lib = gpe.lib()
     h = ctypes.c_void_p()
-    for d in (_desc(nx=15), _desc(ny=8192), _desc(nx=96), _desc(dt=0.0), _desc(dt=-1e-3), _desc(g=-1.0),
+    for d in (_desc(nx=15), _desc(ny=16384), _desc(nx=96), _desc(dt=0.0), _desc(dt=-1e-3), _desc(g=-1.0),
               _desc(lx=0.0), _desc(dt=float("nan"))):
         rc = lib.gpe_plan_create(ctypes.byref(h), ctypes.byref(d))
         assert rc == gpe.ERR_INVALID

@@ -163,6 +163,32 @@ def test_full_spectrum_states_on_the_headline_launch_shapes(shape, mode, monkeyp
         assert abs(plan.cavity()["alpha"] - st.alpha) <= 1e-6 * abs(st.alpha)
 
 
+@pytest.mark.parametrize("shape", [(8192, 64), (64, 8192), (8192, 512)])
+@pytest.mark.parametrize("mode", ["real", "imag"])
+def test_8192_point_lines(shape, mode, monkeypatch):
+    """Lines of 8192 points, the longest a plan takes: row passes at radix 16 (512 threads
+    per line), column passes at radix 8 with one column per tile.  White-noise states with
+    the field ODE and every potential term, three real or two imaginary steps against the
+    oracle, pointwise; the energy functional on the same grid."""
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0, dt=2e-4, g=800.0, wx=0.05, wy=0.07, x0=0.7,
+                kx_lat=1.0, ky_lat=2.0, sx=W.Schedule("ramp", 0.0, 3.0, 0.0, 1e-3), sy=W.Schedule("const", 1.5),
+                cavity=True, vc=1.5, kc=1.0, delta_c=-20.0, kappa=10.0, eta=4.0, alpha0=0.2 + 0.1j)
+    psi0 = W.random_state(s, 17)
+    n = 3 if mode == "real" else 2
+    st = state(s)
+    ref, _ = (O.step_real if mode == "real" else O.step_imag)(problem(s), st, psi0, n)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    (plan.step_real if mode == "real" else plan.step_imag)(d, n, 0.0)
+    out = to_host(d)
+    _assert_pointwise(out, ref)
+    if mode == "real":
+        assert abs(plan.cavity()["alpha"] - st.alpha) <= 1e-6 * abs(st.alpha)
+    else:
+        assert rel_e(plan.energy(d, 0.0)["e"], O.energy(problem(s), ref, 0.0, st.alpha)["e"]) < 1e-7
+
+
 # ----------------------------------------------- imaginary-time ground state
 
 @pytest.mark.parametrize("path", ["lds", "multipass"])
