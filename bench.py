@@ -663,7 +663,8 @@ def main() -> int:
     plan.sync()
     torch.cuda.synchronize()
 
-    plan.set_timing(args.timing_every)
+    # pass timing on the last step of every window (one window in a 20-step run)
+    plan.set_timing(max(1, min(args.timing_every, args.steps - 1)))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()

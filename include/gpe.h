@@ -199,10 +199,12 @@ int gpe_set_cavity(gpe_plan *plan, const double state[4], int have_history);
 int gpe_sync(gpe_plan *plan);
 
 /* Instrumentation for roofline measurements.  gpe_set_timing(plan, every): when
- * every > 0, gpe_step_real launches the column pass and the middle row pass of every
- * `every`-th step with a pair of HIP events that record the kernel's own start and end
- * on the plan's stream (hipExtLaunchKernel; every = 0 turns it off and clears the record).  gpe_get_timing (synchronous) returns
- * {mean column-pass ms, column launches timed, mean row-pass ms, row launches timed}. */
+ * every > 0, gpe_step_real launches the column pass and the middle row pass of the last
+ * step of every window of `every` steps (steps every-1, 2 every-1, ... of a call, never its
+ * last) with a pair of HIP events that record the kernel's own start and end on the
+ * plan's stream (hipExtLaunchKernel); every = 0 turns it off and clears the record.
+ * gpe_get_timing (synchronous) returns {mean column-pass ms, column launches timed, mean
+ * row-pass ms, row launches timed}. */
 int gpe_set_timing(gpe_plan *plan, int every);
 int gpe_get_timing(gpe_plan *plan, double out[4]);
 

@@ -94,6 +94,10 @@ struct RowArgs {
     double t_shift;    // -dt/2 for the midpoint kick of the Fourier-space ordering
     const double *probe;  // adiabatic field: partials of the density about to be kicked
     int nprobe;           // (0: take the field from the state)
+    // imaginary-time entry pass: the previous exit pass's partials [nscale][NPART], from
+    // whose norm every work-group forms the pending 1/sqrt(norm) itself (null: st->scale)
+    const double *scale_partials;
+    int nscale;
 };
 
 // Work done by work-group 0 of a column pass before its own columns: reduce the

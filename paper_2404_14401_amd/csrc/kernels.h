@@ -112,7 +112,8 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
                                          const PotDev &pot, DevState *st, double *partials, int n, int lb,
                                          int lines, XchgT *smem, double *red, double t_shift = 0.0,
                                          const double *probe = nullptr, int nprobe = 0, bool theta_only = false,
-                                         float2 *traj = nullptr)
+                                         float2 *traj = nullptr, const double *scale_partials = nullptr,
+                                         int nscale = 0)
 {
     using C = double2;
     constexpr int T = N / R;
@@ -219,7 +220,20 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     double part[NPART] = {};
     double fin = 0.0;  // sum of this thread's densities: non-finite iff one of its points is
     if constexpr (MODE == ROW_ENTRY && IMAG) {
-        const double sc = st->scale;
+        // the pending renormalisation: 1/sqrt(norm) of the previous step's exit state,
+        // from its partials (the same fixed-order sum in every work-group) or the state
+        double sc;
+        if (scale_partials) {
+            double s1[1] = {0.0};
+            for (int i = threadIdx.x; i < nscale; i += blockDim.x) s1[0] += scale_partials[i * NPART];
+            block_sum<1>(s1, red);
+            if (threadIdx.x == 0) red[0] = sqrt(1.0 / (s1[0] * gd.dA));
+            __syncthreads();
+            sc = red[0];
+            __syncthreads();
+        } else {
+            sc = st->scale;
+        }
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = {v[m].x * sc, v[m].y * sc};
     }
@@ -303,8 +317,9 @@ __global__ void __launch_bounds__(512) row_pass(RowArgs a)
     extern __shared__ XchgT smem[];
     __shared__ double red[8 * NPART];
     row_body<N, kRowRadix<N>, MODE, IMAG>(a.src, a.dst, a.grid, a.pot, a.st,
-                                     a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
-                                     a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe, a.reduce == 2);
+                                          a.reduce ? a.partials + blockIdx.x * NPART : nullptr, a.n, blockIdx.x,
+                                          a.lines_per_wg, smem, red, a.t_shift, a.probe, a.nprobe, a.reduce == 2,
+                                          nullptr, a.scale_partials, a.nscale);
 }
 
 // Batched: work-group b serves instance b / blocks_per_inst (real time, no reductions).

@@ -606,7 +606,9 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         ta.imag = 0;
         ta.advance_alpha = cav ? 1 : 0;
         ca.do_tail = (ta.npartials > 0 || ta.advance_alpha) ? 1 : 0;
-        const bool timed = p->timing_every > 0 && n % p->timing_every == 0 && n + 1 < nsteps;
+        // the last step of every window of timing_every steps (never a call's first or
+        // last step, whose row passes are the entry and exit kicks)
+        const bool timed = p->timing_every > 0 && (n + 1) % p->timing_every == 0 && n + 1 < nsteps;
         hipEvent_t *ec = timed ? timing_pair(p, 0) : nullptr;
         LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s,
                              ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
@@ -740,16 +742,16 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
     RowArgs ra = row_args(p, f);
     // one step: entry kick (with the pending scale), columns, exit kick with the norm
     // partials, tail (renormalisation scale, field); the potential is frozen at t, so
-    // every step without observables is the same launch sequence
-    auto step = [&](int64_t n, hipStream_t s) -> int {
-        ra.n = (int)n;
-        ra.reduce = 0;
-        LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
-        ColArgs ca = col_args(p, f);
-        ca.do_tail = 0;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s));
-        ra.reduce = 1;
-        LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
+    // every step without observables is the same launch sequence.  Without observables
+    // or the adiabatic field, and with at most kFoldRows row work-groups, the tail between
+    // steps is left out: every work-group of the next entry kick forms the scale from the
+    // exit partials itself, and one tail after the last step leaves the scale for the
+    // final renormalisation.  (Each entry work-group reads every partial, so the reads
+    // grow with the square of the row work-groups: measured, per 10^3 steps, 128^2 17.1 ->
+    // 14.7 ms, 1024^2 37.1 -> 36.1 ms, but 4096^2 326 -> 343 ms and 8192^2 3.0 s.)
+    constexpr int kFoldRows = 1024;
+    const bool fold = !obs && !adia && sh.row_blocks <= kFoldRows;
+    auto tail = [&](int64_t n, hipStream_t s) -> int {
         TailArgs ta{};
         ta.partials = p->partials;
         ta.npartials = sh.row_blocks;
@@ -759,15 +761,29 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
         LAUNCH_OK(launch_tail(ta, p->grid, p->pot, p->st, s));
         return GPE_OK;
     };
+    auto step = [&](int64_t n, hipStream_t s, bool after_step) -> int {
+        ra.n = (int)n;
+        ra.reduce = 0;
+        ra.scale_partials = (fold && after_step) ? p->partials : nullptr;
+        ra.nscale = sh.row_blocks;
+        LAUNCH_OK(launch_row(p->nx, ROW_ENTRY, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
+        ra.scale_partials = nullptr;
+        ColArgs ca = col_args(p, f);
+        ca.do_tail = 0;
+        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s));
+        ra.reduce = 1;
+        LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
+        return fold ? GPE_OK : tail(n, s);
+    };
     int rc;
     int64_t done = 0;
     if (replay_ok(p, nsteps, obs)) {
         // the first step directly (its launches set up the kernels), then chunks
-        if ((rc = step(0, p->stream))) return rc;
+        if ((rc = step(0, p->stream, false))) return rc;
         done = 1;
         if ((rc = capture_chunk(p, 1, f, [&](hipStream_t s) -> int {
                  for (int j = 0; j < kChunk; ++j) {
-                     int r = step(0, s);
+                     int r = step(0, s, true);
                      if (r) return r;
                  }
                  return GPE_OK;
@@ -776,7 +792,8 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
         for (; nsteps - done >= kChunk; done += kChunk) HIP_OK(hipGraphLaunch(p->graph[1], p->stream));
     }
     for (int64_t n = done; n < nsteps; ++n)
-        if ((rc = step(n, p->stream))) return rc;
+        if ((rc = step(n, p->stream, n > 0))) return rc;
+    if (fold && (rc = tail(nsteps - 1, p->stream))) return rc;
     LAUNCH_OK(launch_scale(f, (size_t)p->nx * p->ny, p->st, p->stream));
     LAUNCH_OK(launch_set_call(p->st, t, 1, 0, p->stream));
     return GPE_OK;
