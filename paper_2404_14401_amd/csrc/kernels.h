@@ -107,6 +107,9 @@ template <int R> __device__ __forceinline__ void kick_real_all(double2 (&v)[R], 
 // lengths (256 and 512: -19% on the mixed 208-member batch; 4096: -12%), which load
 // tables and twiddles where they are used.  Same arithmetic either way.
 constexpr int kPreloadLine = 1024;
+#ifndef GPE_PROBE_DEPTH
+#define GPE_PROBE_DEPTH 4
+#endif
 template <int N, int R, int MODE, bool IMAG>
 __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, float2 *dst_base, const GridDev &gd,
                                          const PotDev &pot, DevState *st, double *partials, int n, int lb,
@@ -193,14 +196,15 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
     double tk = st->t0;
     if (!IMAG && MODE != ROW_FWD) tk += (MODE == ROW_ENTRY ? n : n + 1) * gd.dt + t_shift;
     double are, aim;
+    // (probe partials reach the real-time kicks only: other modes keep their registers)
+    constexpr int KD = (!IMAG && MODE != ROW_FWD) ? GPE_PROBE_DEPTH : 1;
     if (probe) {
-        // adiabatic field of the probed density, the same sum in every work-group
-        double s[NPART] = {};
-        for (int i = threadIdx.x; i < nprobe; i += blockDim.x)
-#pragma unroll
-            for (int k = 0; k < NPART; ++k) s[k] += probe[i * NPART + k];
-        block_sum<NPART>(s, red);
-        if (threadIdx.x == 0) alpha_adiabatic(pot, tk, s[0], s[1], s[4], &red[0], &red[1]);
+        // adiabatic field of the probed density, the same sum in every work-group, of the
+        // three integrals it needs (norm, Theta, C)
+        double s[3] = {};
+        strided_sum<KD>(probe, nprobe, NPART, {0, 1, 4}, s);
+        block_sum<3>(s, red);
+        if (threadIdx.x == 0) alpha_adiabatic(pot, tk, s[0], s[1], s[2], &red[0], &red[1]);
         __syncthreads();
         are = red[0];
         aim = red[1];
@@ -225,7 +229,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
         double sc;
         if (scale_partials) {
             double s1[1] = {0.0};
-            for (int i = threadIdx.x; i < nscale; i += blockDim.x) s1[0] += scale_partials[i * NPART];
+            strided_sum(scale_partials, nscale, NPART, {0}, s1);
             block_sum<1>(s1, red);
             if (threadIdx.x == 0) red[0] = sqrt(1.0 / (s1[0] * gd.dA));
             __syncthreads();
@@ -862,9 +866,7 @@ __device__ __forceinline__ void row_adj_body(const AdjInst &I, int lb, int lines
     double are = 0.0, aim = 0.0, bth = 0.0, bc = 0.0, thn = 0.0, c2n = 0.0, inv0 = 0.0, extra = 0.0;
     if (I.aprobe) {
         double sm[NPART] = {};
-        for (int i = threadIdx.x; i < nprobe; i += blockDim.x)
-#pragma unroll
-            for (int k = 0; k < NPART; ++k) sm[k] += I.aprobe[i * NPART + k];
+        strided_sum(I.aprobe, nprobe, NPART, {0, 1, 2, 3, 4}, sm);
         block_sum<NPART>(sm, red);
         if (threadIdx.x == 0) {
             const PotDev &p = I.pot;
@@ -954,7 +956,7 @@ __global__ void __launch_bounds__(512) row_adj_b(AdjPassArgs a)
 __device__ __forceinline__ void adj_tail(const AdjInst &I, int nrow, int k, double *red)
 {
     double s[1] = {0.0};
-    for (int i = threadIdx.x; i < nrow; i += blockDim.x) s[0] += I.partials[i];
+    strided_sum(I.partials, nrow, 1, {0}, s);
     block_sum<1>(s, red);
     if (threadIdx.x == 0) I.kick_grad[k] += s[0];
 }

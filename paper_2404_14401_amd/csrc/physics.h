@@ -126,6 +126,32 @@ template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], dou
     __syncthreads();
 }
 
+// Thread-strided sum of the components comp[] of records [n][stride]: thread t adds
+// records t, t + b, t + 2b, ... (b = blockDim.x) in that order, whatever the timing, so
+// that with block_sum the result is the same fixed-order sum everywhere; the loads go out
+// D records at a time rather than as a chain of single L2 round trips.
+template <int D = 8, int NK>
+__device__ __forceinline__ void strided_sum(const double *p, int n, int stride, const int (&comp)[NK],
+                                            double (&s)[NK])
+{
+    const int b = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (D - 1) * b < n; i += D * b) {
+        double q[D][NK];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < NK; ++k) q[j][k] = p[(size_t)(i + j * b) * stride + comp[k]];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < NK; ++k) s[k] += q[j][k];
+    }
+    for (; i < n; i += b)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) s[k] += p[(size_t)i * stride + comp[k]];
+}
+
 // Adiabatic cavity field (Sec. 5.3, Eqs. 14-15) of a density with integrals nrm,
 // Theta = th and C = c2 at time t, with the on-axis probe of Sec. 5.4 (Eq. 17):
 //   [N sqrt(Vp(t) U0) (th/nrm) + Omega_c e^{i (Delta_p t + phi)}] / (Delta_c - N U0 c2/nrm + i kappa).
@@ -166,6 +192,7 @@ __device__ __forceinline__ void cavity_advance(const PotDev &p, DevState *st)
 __device__ __forceinline__ void run_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot,
                                          DevState *st, double *red)
 {
+    // (one load at a time: the column passes that inline this keep their register count)
     double s[NPART] = {};
     if (ta.npartials > 0 && ta.theta_only) {
         for (int i = threadIdx.x; i < ta.npartials; i += blockDim.x) s[1] += ta.partials[i * NPART + 1];
