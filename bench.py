@@ -255,12 +255,14 @@ def bench_adjoint(steps: int, nb: int, tune_cache: str | None = None):
     ref = None
     for mode in ("reconstruct", "checkpoint", "store"):
         try:
+            # the first call of a mode sizes its workspace (checkpoint slots, the trajectory),
+            # which later calls reuse: the figure is the second call, the first reported beside it
             first = run(b, mode, t_fwd, knots)
-            out[mode] = run(b, mode, t_fwd, knots) if mode == "store" else first
+            out[mode] = run(b, mode, t_fwd, knots) if mode in ("checkpoint", "store") else first
         except gpe.GpeError as e:  # the stored trajectory may not fit the device
             out[mode] = {"error": str(e)}
             continue
-        if mode == "store":
+        if mode in ("checkpoint", "store"):
             out[mode]["first_call_s"] = first["forward_plus_reverse_s"]
         g = out[mode].pop("grad")
         if ref is None:

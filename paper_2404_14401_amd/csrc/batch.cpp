@@ -38,6 +38,8 @@ struct BGroup {
     std::vector<LdsArgs> h_lds;
 };
 
+constexpr int kCopyBlocks = 64;  // work-groups per member of a checkpoint save or restore
+
 struct AdjWork {
     int nx = 0, ny = 0, nb = 0;
     int64_t cap_steps = 0;
@@ -45,8 +47,11 @@ struct AdjWork {
     std::vector<double *> kick_grad, partials;
     std::vector<double *> probe, aprobe;  // adiabatic field: forward and adjoint probe partials
     bool any_adia = false;                // some member has the adiabatic field
-    std::vector<float2 *> ckpt;  // [slot * nb + member]
+    float2 *ckpt_buf = nullptr;  // checkpoint slots, [slot][member][ny][nx]
+    std::vector<float2 *> ckpt;  // [slot * nb + member] into ckpt_buf
     int ckpt_slots = 0;
+    float2 **d_ckpt = nullptr;   // device copy of ckpt
+    float2 **d_psi = nullptr;    // device copy of psi (nb pointers)
     std::vector<float2 *> traj;  // per member: post-kick states [kick][ny][nx] (stored mode)
     int64_t traj_steps = 0;
     AdjInst *d_adj = nullptr;
@@ -635,6 +640,8 @@ static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t n
         if ((rc = balloc(b, (void **)&w->d_dst, sizeof(void *) * nb))) return rc;
         if ((rc = balloc(b, (void **)&w->d_coef, sizeof(double2) * nb))) return rc;
         if ((rc = balloc(b, (void **)&w->d_sums, sizeof(double) * 4 * 64 * nb))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_psi, sizeof(void *) * nb))) return rc;
+        HIP_OK(hipMemcpy(w->d_psi, w->psi.data(), sizeof(void *) * nb, hipMemcpyHostToDevice));
     }
     if (nsteps + 1 > w->cap_steps) {
         for (int i = 0; i < nb; ++i) {
@@ -644,15 +651,29 @@ static int adj_alloc(gpe_batch *b, AdjWork *w, int nx, int ny, int nb, int64_t n
         }
         w->cap_steps = nsteps + 1;
     }
-    while (w->ckpt_slots < slots) {
-        for (int i = 0; i < nb; ++i) {
-            float2 *c = nullptr;
-            int rc;
-            if ((rc = balloc(b, (void **)&c, sizeof(float2) * npts))) return rc;
-            w->ckpt.push_back(c);
-            w->bytes += sizeof(float2) * npts;
+    if (w->ckpt_slots < slots) {
+        // every slot of every member in one allocation (a first call pays one hipMalloc, not
+        // one per member and slot), replaced by a larger one when a call needs more slots;
+        // slots hold nothing from call to call
+        const size_t slot_bytes = sizeof(float2) * npts * nb;
+        bfree(b, w->ckpt_buf);
+        bfree(b, w->d_ckpt);
+        w->bytes -= std::min(w->bytes, (size_t)w->ckpt_slots * slot_bytes);
+        w->ckpt_buf = nullptr;
+        w->d_ckpt = nullptr;
+        w->ckpt.clear();
+        w->ckpt_slots = 0;
+        int rc;
+        if ((rc = balloc(b, (void **)&w->ckpt_buf, slot_bytes * slots))) return rc;
+        if ((rc = balloc(b, (void **)&w->d_ckpt, sizeof(void *) * (size_t)slots * nb))) {
+            bfree(b, w->ckpt_buf);
+            w->ckpt_buf = nullptr;
+            return rc;
         }
-        w->ckpt_slots++;
+        for (size_t k = 0; k < (size_t)slots * nb; ++k) w->ckpt.push_back(w->ckpt_buf + k * npts);
+        HIP_OK(hipMemcpy(w->d_ckpt, w->ckpt.data(), sizeof(void *) * w->ckpt.size(), hipMemcpyHostToDevice));
+        w->ckpt_slots = slots;
+        w->bytes += slot_bytes * slots;
     }
     if (traj_steps > w->traj_steps) {
         // one buffer per member, replaced (not kept alongside) when a longer run needs more
@@ -862,9 +883,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         int r;
         if (checkpoint) {
             for (int64_t s = 0; s < nseg; ++s) {
-                for (int i = 0; i < nb; ++i)
-                    HIP_OK(hipMemcpyAsync(w->ckpt[(size_t)s * nb + i], w->psi[i], sizeof(float2) * npts,
-                                          hipMemcpyDeviceToDevice, b->work));
+                // every member's psi into slot s: one launch
+                LAUNCH_OK(launch_copy_members(w->d_ckpt + (size_t)s * nb, w->d_psi, npts, nb, kCopyBlocks, b->work));
                 if ((r = adj_forward(b, w, sh, t0, s * seg, std::min(nsteps, (s + 1) * seg)))) return r;
             }
         } else if ((r = adj_forward(b, w, sh, t0, 0, nsteps, store))) {
@@ -910,9 +930,8 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
             for (int64_t s = nseg - 1; s >= 0; --s) {
                 const int64_t e = std::min(nsteps, (s + 1) * seg);
                 if (s < nseg - 1)  // restart the state from the stored psi at the segment end
-                    for (int i = 0; i < nb; ++i)
-                        HIP_OK(hipMemcpyAsync(w->psi[i], w->ckpt[(size_t)(s + 1) * nb + i], sizeof(float2) * npts,
-                                              hipMemcpyDeviceToDevice, b->work));
+                    LAUNCH_OK(launch_copy_members(w->d_psi, w->d_ckpt + (size_t)(s + 1) * nb, npts, nb, kCopyBlocks,
+                                                  b->work));
                 if ((r = adj_reverse(b, w, sh, t0, s * seg, e))) return r;
             }
         } else if ((r = adj_reverse(b, w, sh, t0, 0, nsteps, store))) {

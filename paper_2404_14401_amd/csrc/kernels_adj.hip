@@ -64,6 +64,18 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(float2 *const *dst, co
     }
 }
 
+// dst_i = src_i for every member, npts points each (checkpoint save and restore).
+__global__ void __launch_bounds__(256) copy_members_kernel(float2 *const *dst, const float2 *const *src, size_t npts,
+                                                           int per_inst)
+{
+    const int inst = blockIdx.x / per_inst, lb = blockIdx.x % per_inst;
+    float4 *d = reinterpret_cast<float4 *>(dst[inst]);
+    const float4 *s = reinterpret_cast<const float4 *>(src[inst]);
+    const size_t n4 = npts / 2;
+    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < n4; i += (size_t)per_inst * blockDim.x) d[i] = s[i];
+    if ((npts & 1) && lb == 0 && threadIdx.x == 0) dst[inst][npts - 1] = src[inst][npts - 1];
+}
+
 template <int N, int R, bool TRAJ> static hipError_t rowadj_mode(int mode, const AdjPassArgs &a, int blocks,
                                                                  int threads, size_t shmem, hipStream_t s)
 {
@@ -154,6 +166,13 @@ hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, cons
                               int count, int per_inst, hipStream_t s)
 {
     hipLaunchKernelGGL(scaled_copy_kernel, dim3(count * per_inst), dim3(256), 0, s, dst, src, coef, npts, per_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_members(float2 *const *dst, const float2 *const *src, size_t npts, int count, int per_inst,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_members_kernel, dim3(count * per_inst), dim3(256), 0, s, dst, src, npts, per_inst);
     return hipGetLastError();
 }
 

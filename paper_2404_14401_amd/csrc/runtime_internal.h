@@ -40,6 +40,8 @@ hipError_t launch_pair_sums(const float2 *const *a, const float2 *const *b, size
                             double *out, hipStream_t s);
 hipError_t launch_scaled_copy(float2 *const *dst, const float2 *const *src, const double2 *coef, size_t npts,
                               int count, int per_inst, hipStream_t s);
+hipError_t launch_copy_members(float2 *const *dst, const float2 *const *src, size_t npts, int count, int per_inst,
+                               hipStream_t s);
 bool lds_supported(int nx, int ny);
 int lds_threads(int nx, int ny);
 int kernel_radix();

@@ -94,6 +94,32 @@ def test_auto_falls_back_to_checkpoints_when_drift_tolerance_is_zero():
     assert np.linalg.norm(a[1] - r[1]) / np.linalg.norm(r[1]) < 1e-4
 
 
+def test_checkpoint_slots_grow_and_are_reused_between_calls():
+    """Calls of 16, 100 and 16 steps on one batch: the checkpoint workspace grows from 4 to
+    10 slots (one allocation replaced by a larger one) and is reused; each gradient matches
+    the oracle's."""
+    torch_cuda()
+    from paper_2404_14401_amd import gpe
+
+    nb = 2
+    setups = [control_setup(b, nsteps=100) for b in range(nb)]
+    batch = gpe.Batch(setups)
+    p0, tg = zip(*[states(s, b) for b, s in enumerate(setups)])
+    knots = np.stack([s.sx.knots for s in setups])
+    sizes = []
+    for nsteps in (16, 100, 16):
+        loss, grad, info = gpe.adjoint(batch, [to_dev(p) for p in p0], [to_dev(t) for t in tg], nsteps, knots,
+                                       mode="checkpoint")
+        assert info["mode"] == "checkpoint"
+        sizes.append(info["workspace_bytes"])
+        for b, s in enumerate(setups):
+            l_ref, g_ref, _ = O.adjoint(problem(s), 0.0, p0[b], tg[b], nsteps)
+            assert abs(loss[b] - l_ref) < 1e-5, (nsteps, b)
+            assert np.linalg.norm(grad[b] - g_ref) / np.linalg.norm(g_ref) < 1e-3, (nsteps, b)
+    slot = nb * 64 * 64 * 8
+    assert sizes[1] - sizes[0] == (10 - 4) * slot and sizes[2] == sizes[1]
+
+
 def pump_setup(b, n=64, nknots=8, nsteps=60, dt=0.005):
     """The pump (y lattice) as the control, with a static x lattice present."""
     knots = np.random.Generator(np.random.PCG64(200 + b)).uniform(0.0, 15.0, size=nknots)
