@@ -454,7 +454,9 @@ static double time_group(gpe_batch *b, BGroup &g, int steps)
 {
     std::vector<gpe_c64 *> psis(b->n, nullptr);
     for (int i = 0; i < b->n; ++i) psis[i] = (gpe_c64 *)b->plans[i]->scratch;
-    for (auto &p : b->plans) (void)hipMemsetAsync(p->scratch, 0, sizeof(float2) * (size_t)p->nx * p->ny, b->work);
+    for (int i : g.members)  // the timed group's arrays: finite contents
+        (void)hipMemsetAsync(b->plans[i]->scratch, 0, sizeof(float2) * (size_t)b->plans[i]->nx * b->plans[i]->ny,
+                             b->work);
     if (bind_psis(b, psis.data(), 1)) return 1e30;
     for (int it = 0; it < 2; ++it) {
         auto t = std::chrono::steady_clock::now();
