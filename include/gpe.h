@@ -202,7 +202,8 @@ int gpe_sync(gpe_plan *plan);
  * every > 0, gpe_step_real launches the column pass and the middle row pass of the last
  * step of every window of `every` steps (steps every-1, 2 every-1, ... of a call, never its
  * last) with a pair of HIP events that record the kernel's own start and end on the
- * plan's stream (hipExtLaunchKernel); every = 0 turns it off and clears the record.
+ * plan's stream (hipExtLaunchKernel; where 4096- or 8192-point columns take the column
+ * step as three passes, the pair spans all three); every = 0 turns it off and clears the record.
  * gpe_get_timing (synchronous) returns {mean column-pass ms, column launches timed, mean
  * row-pass ms, row launches timed}. */
 int gpe_set_timing(gpe_plan *plan, int every);

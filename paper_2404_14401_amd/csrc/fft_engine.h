@@ -147,8 +147,9 @@ template <int N, int R> struct FftShape {
 };
 
 // One Stockham pass.  Ns = product of the radices before this pass.  View: LDS line
-// accessor with operator()(int idx) -> C& (exchange storage of N points).
-template <int N, int R, bool INV, int PASS, typename C, typename View>
+// accessor with operator()(int idx) -> C& (exchange storage of N points).  tw holds
+// W_{TS N}^m: an N-point transform takes every TS-th entry of a longer line's table.
+template <int N, int R, bool INV, int PASS, int TS = 1, typename C, typename View>
 __device__ __forceinline__ void fft_pass(C (&v)[R], const View &lds, int t, const C *__restrict__ tw)
 {
     using S = FftShape<N, R>;
@@ -170,7 +171,7 @@ __device__ __forceinline__ void fft_pass(C (&v)[R], const View &lds, int t, cons
 #pragma unroll
             for (int r = 0; r < Rp; ++r) a[r] = v[q + r * Q];
             if constexpr (Ns > 1) {
-                constexpr int stride = N / (Ns * Rp);
+                constexpr int stride = TS * (N / (Ns * Rp));
 #if GPE_TW_POW2
                 // powers w^1, w^2, w^4 (and w^8) from the table, the others as FP64
                 // products (rounding ~1e-16 per product, far below the complex64 storage)
@@ -214,17 +215,17 @@ __device__ __forceinline__ void fft_pass(C (&v)[R], const View &lds, int t, cons
                 for (int r = 0; r < Rp; ++r) lds.st(base + r * Ns, v[q + r * Q]);
             }
             __syncthreads();
-            fft_pass<N, R, INV, PASS + 1>(v, lds, t, tw);
+            fft_pass<N, R, INV, PASS + 1, TS>(v, lds, t, tw);
         }
     }
 }
 
 // Full transform of one line: in v[m] = x[t + m*T], out v[m] = X[t + m*T], unscaled.
 // Every thread of the work-group must call this (it contains work-group barriers).
-template <int N, int R, bool INV, typename C, typename View>
+template <int N, int R, bool INV, int TS = 1, typename C, typename View>
 __device__ __forceinline__ void fft_line(C (&v)[R], const View &lds, int t, const C *__restrict__ tw)
 {
-    fft_pass<N, R, INV, 0>(v, lds, t, tw);
+    fft_pass<N, R, INV, 0, TS>(v, lds, t, tw);
 }
 
 

@@ -531,6 +531,77 @@ __global__ void __launch_bounds__(1024) col_pass_b(BatchPassArgs a)
 }
 
 
+// ------------------------------------------------- long columns in three passes
+// The column step on lines of NY = NA * NB points as a four-step transform (k = k2 + NA k1,
+// n = n1 + NB n2), so that every pass moves whole 128-byte lines where a single pass would
+// hold a one-column tile and fetch each line once per column:
+//   PHASE 0: for a residue n1 < NB, the NA-point transform of rows n1 + NB n2 (over n2),
+//            times W_NY^{n1 k2}, back to row n1 + NB k2;
+//   PHASE 1: for a k2 < NA, the NB-point transform of the NB contiguous rows NB k2 + n1
+//            (over n1, output index k1 = frequency k2 + NA k1), the kinetic factor, the
+//            inverse NB-point transform, back in place;
+//   PHASE 2: for a residue n1, times W_NY^{-n1 k2}, the inverse NA-point transform over
+//            k2, back to rows n1 + NB n2.
+// The sub-transforms take every (NY/NA)-th or (NY/NB)-th twiddle of the line's table.
+// Work-group b: tile b % (nx / w) of w columns, group (n1 or k2) b / (nx / w); work-group
+// 0 of PHASE 0 runs the tail, as the single column pass does.
+constexpr int kSplitA = 128;
+template <int NY, int PHASE, int MODE>
+__global__ void __launch_bounds__(256) col_split(ColArgs a)
+{
+    using C = double2;
+    constexpr int NA = kSplitA, NB = NY / NA, R = kRadix;
+    constexpr int N = PHASE == 1 ? NB : NA;
+    constexpr int T = N / R;
+    using View = LineTile<XchgT, ilog2(R)>;
+    extern __shared__ XchgT smem[];
+    __shared__ double red[16 * NPART];
+    if (PHASE == 0 && a.do_tail && blockIdx.x == 0) run_tail(a.tail, a.grid, a.pot, a.st, red);
+    const GridDev &gd = a.grid;
+    const int nx = gd.nx, w = a.cols_per_wg;
+    const int ntiles = nx / w;
+    const int tile = blockIdx.x % ntiles, grp = blockIdx.x / ntiles;
+    const int c = threadIdx.x % w, t = threadIdx.x / w;
+    const int col = tile * w + c;
+    View lds{smem + c, w};
+    const double2 *tw = gd.tw_y;
+    // row of element j of this work-group's line
+    auto row = [&](int j) -> size_t { return PHASE == 1 ? (size_t)NB * grp + j : (size_t)grp + (size_t)NB * j; };
+
+    C v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const float2 f = a.src[row(t + m * T) * nx + col];
+        v[m] = {(double)f.x, (double)f.y};
+    }
+    if constexpr (PHASE == 0) {
+        fft_line<NA, R, false, NY / NA>(v, lds, t, tw);
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = cmul(v[m], tw[grp * (t + m * T)]);  // n1 k2 < NY
+    } else if constexpr (PHASE == 1) {
+        fft_line<NB, R, false, NY / NB>(v, lds, t, tw);
+        if constexpr (MODE == COL_KIN_REAL) {
+            const C kx = gd.kin_x[col];
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = cmul(v[m], cmul(kx, gd.kin_y[grp + NA * (t + m * T)]));
+        } else {
+            const double kx = gd.kim_x[col];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const double f = kx * gd.kim_y[grp + NA * (t + m * T)];
+                v[m] = {v[m].x * f, v[m].y * f};
+            }
+        }
+        fft_line<NB, R, true, NY / NB>(v, lds, t, tw);
+    } else {
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = cmulc(v[m], tw[grp * (t + m * T)]);
+        fft_line<NA, R, true, NY / NA>(v, lds, t, tw);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) store_c64(a.dst + row(t + m * T) * nx + col, v[m]);
+}
+
 // ------------------------------------------------------------- whole grid in LDS
 // One work-group owns one grid for all steps; psi stays in LDS as complex64 (row pitch
 // NX + 1), each transform line is lifted to double registers.  Steps follow the

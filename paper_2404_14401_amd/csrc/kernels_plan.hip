@@ -223,6 +223,44 @@ hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads
     }
 }
 
+template <int NY> static hipError_t split_dispatch(int phase, int mode, const ColArgs &a, int blocks, int threads,
+                                                   size_t shmem, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+#define GPE_SPLIT(P, M)                                                                            \
+    do {                                                                                           \
+        if (e0 || e1)                                                                              \
+            hipExtLaunchKernelGGL((col_split<NY, P, M>), dim3(blocks), dim3(threads), (uint32_t)shmem, s, e0, e1, 0, \
+                                  a);                                                              \
+        else                                                                                       \
+            hipLaunchKernelGGL((col_split<NY, P, M>), dim3(blocks), dim3(threads), shmem, s, a);   \
+    } while (0)
+#define GPE_SPLIT_MODE(M)                                                                          \
+    do {                                                                                           \
+        if (phase == 0) GPE_SPLIT(0, M);                                                           \
+        else if (phase == 1) GPE_SPLIT(1, M);                                                      \
+        else GPE_SPLIT(2, M);                                                                      \
+    } while (0)
+    if (phase < 0 || phase > 2) return hipErrorInvalidValue;
+    if (mode == COL_KIN_REAL) GPE_SPLIT_MODE(COL_KIN_REAL);
+    else if (mode == COL_KIN_IMAG) GPE_SPLIT_MODE(COL_KIN_IMAG);
+    else return hipErrorInvalidValue;
+#undef GPE_SPLIT_MODE
+#undef GPE_SPLIT
+    return hipGetLastError();
+}
+
+int col_split_a() { return kSplitA; }
+
+hipError_t launch_col_split(int ny, int phase, int mode, const ColArgs &a, int blocks, int threads, size_t shmem,
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    switch (ny) {
+    case 4096: return split_dispatch<4096>(phase, mode, a, blocks, threads, shmem, s, e0, e1);
+    case 8192: return split_dispatch<8192>(phase, mode, a, blocks, threads, shmem, s, e0, e1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s)
 {
     hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(256), 0, s, ta, gd, pot, st);

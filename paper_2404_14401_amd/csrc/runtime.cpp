@@ -91,6 +91,28 @@ Shape make_shape_r(int nx, int ny, int R, size_t eb, int row_threads, int min_co
     return s;
 }
 
+// The three-pass column step (col_split) for columns of ny points: outer passes of
+// split_a-point transforms on tiles of up to 16 columns (one 128-byte line of complex64 per
+// row), the middle pass of (ny / split_a)-point transforms on tiles of up to 256 threads.
+static void set_split(Shape &s, int nx, int ny)
+{
+    const int r = kernel_radix(), na = col_split_a(), nb = ny / na;
+    int sh = 0;
+    while ((1 << sh) < r) ++sh;
+    const size_t eb = xchg_bytes();
+    s.split_a = na;
+    s.split_ta = na / r;
+    s.split_wa = std::min(nx, std::max(1, 256 / s.split_ta));
+    s.split_ba = (nx / s.split_wa) * nb;
+    s.split_sha = ((size_t)na * s.split_wa + (na >> sh) + s.split_wa) * eb;
+    s.split_sha = (s.split_sha + 15) / 16 * 16;
+    s.split_tb = nb / r;
+    s.split_wb = std::min(nx, std::max(1, 256 / s.split_tb));
+    s.split_bb = (nx / s.split_wb) * na;
+    s.split_shb = ((size_t)nb * s.split_wb + (nb >> sh) + s.split_wb) * eb;
+    s.split_shb = (s.split_shb + 15) / 16 * 16;
+}
+
 static Shape make_shape(int nx, int ny)
 {
     Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128),
@@ -101,7 +123,33 @@ static Shape make_shape(int nx, int ny)
                                row_radix(nx));
         s = t;
     }
+    // columns of at least GPE_COL_SPLIT_MIN points take the three-pass column step (built
+    // for 4096 and 8192; measured at 8192^2: 2.47 -> 1.65 ms per real-time step, at 4096^2:
+    // 0.319 -> 0.304 ms)
+    const int split_min = env_int("GPE_COL_SPLIT_MIN", 4096);
+    if ((ny == 4096 || ny == 8192) && ny >= split_min) set_split(s, nx, ny);
     return s;
+}
+
+// The column step (FFT_y, kinetic factor, IFFT_y) of real or imaginary time: one pass, or
+// on long columns the three of col_split; timing events around the whole step.
+static hipError_t col_step(const gpe_plan *p, int mode, const ColArgs &ca, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr)
+{
+    const Shape &sh = p->shape;
+    if (!sh.split_a || (mode != COL_KIN_REAL && mode != COL_KIN_IMAG))
+        return launch_col(p->ny, mode, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s, e0, e1);
+    ColArgs c = ca;
+    c.cols_per_wg = sh.split_wa;
+    hipError_t e = launch_col_split(p->ny, 0, mode, c, sh.split_ba, sh.split_wa * sh.split_ta, sh.split_sha, s, e0);
+    if (e != hipSuccess) return e;
+    c.src = c.dst;  // the later passes work on the first one's output
+    c.do_tail = 0;
+    c.cols_per_wg = sh.split_wb;
+    e = launch_col_split(p->ny, 1, mode, c, sh.split_bb, sh.split_wb * sh.split_tb, sh.split_shb, s);
+    if (e != hipSuccess) return e;
+    c.cols_per_wg = sh.split_wa;
+    return launch_col_split(p->ny, 2, mode, c, sh.split_ba, sh.split_wa * sh.split_ta, sh.split_sha, s, nullptr, e1);
 }
 
 static Sched to_sched(const gpe_schedule &s, const double *dev_knots)
@@ -519,7 +567,7 @@ static int step_real_adiabatic(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double
         ta.npartials = (n >= 1 && obs) ? sh.row_blocks : 0;
         ta.obs = (n >= 1 && obs) ? obs + (n - 1) * NOBS : nullptr;
         ca.do_tail = ta.npartials > 0 ? 1 : 0;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, p->stream));
+        LAUNCH_OK(col_step(p, COL_KIN_REAL, ca, p->stream));
         pa.n = (int)n;
         LAUNCH_OK(launch_row(p->nx, ROW_PROBE_MID, false, pa, sh.row_blocks, sh.row_threads, sh.row_shmem, p->stream));
         ra.n = (int)n;
@@ -610,8 +658,7 @@ int gpe_step_real(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t0, double *
         // last step, whose row passes are the entry and exit kicks)
         const bool timed = p->timing_every > 0 && (n + 1) % p->timing_every == 0 && n + 1 < nsteps;
         hipEvent_t *ec = timed ? timing_pair(p, 0) : nullptr;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_REAL, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s,
-                             ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
+        LAUNCH_OK(col_step(p, COL_KIN_REAL, ca, s, ec ? ec[0] : nullptr, ec ? ec[1] : nullptr));
         RowArgs rb = ra;
         rb.n = (int)rel;
         rb.reduce = red ? (obs ? 1 : 2) : 0;
@@ -682,8 +729,7 @@ int gpe_step_real_k(gpe_plan *p, gpe_c64 *psik, int64_t nsteps, double t0, doubl
         ta.npartials = obs ? sh.row_blocks : 0;
         ta.obs = obs ? obs + n * NOBS : nullptr;
         cb.do_tail = obs ? 1 : 0;
-        LAUNCH_OK(launch_col(p->ny, n + 1 < nsteps ? COL_KIN_REAL : COL_FWD_KHALF, cb, sh.col_blocks, sh.col_threads,
-                             sh.col_shmem, p->stream));
+        LAUNCH_OK(col_step(p, n + 1 < nsteps ? COL_KIN_REAL : COL_FWD_KHALF, cb, p->stream));
     }
     return GPE_OK;
 }
@@ -770,7 +816,7 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
         ra.scale_partials = nullptr;
         ColArgs ca = col_args(p, f);
         ca.do_tail = 0;
-        LAUNCH_OK(launch_col(p->ny, COL_KIN_IMAG, ca, sh.col_blocks, sh.col_threads, sh.col_shmem, s));
+        LAUNCH_OK(col_step(p, COL_KIN_IMAG, ca, s));
         ra.reduce = 1;
         LAUNCH_OK(launch_row(p->nx, ROW_EXIT, true, ra, sh.row_blocks, sh.row_threads, sh.row_shmem, s));
         return fold ? GPE_OK : tail(n, s);

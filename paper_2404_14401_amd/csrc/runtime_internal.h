@@ -15,6 +15,11 @@ hipError_t launch_row(int n, int mode, bool imag, const RowArgs &a, int blocks, 
                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_col(int n, int mode, const ColArgs &a, int blocks, int threads, size_t shmem, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The column step of real or imaginary time (COL_KIN_REAL / COL_KIN_IMAG) on columns of
+// ny = 4096 or 8192 points in three passes (phase 0, 1, 2; a's cols_per_wg per phase).
+hipError_t launch_col_split(int ny, int phase, int mode, const ColArgs &a, int blocks, int threads, size_t shmem,
+                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int col_split_a();
 hipError_t launch_tail(const TailArgs &ta, const GridDev &gd, const PotDev &pot, DevState *st, hipStream_t s);
 hipError_t launch_scale(float2 *psi, size_t n, const DevState *st, hipStream_t s);
 hipError_t launch_set_call(DevState *st, double t0, int reset_scale, int clear_history, hipStream_t s);
@@ -82,6 +87,12 @@ struct Shape {
     size_t row_shmem;
     int col_cols, col_threads, col_blocks;
     size_t col_shmem;
+    // long columns: the column step in three passes when split_a > 0 (transform lengths
+    // split_a and ny / split_a; tile widths, threads, work-groups and LDS of the outer
+    // passes (a) and of the middle one (b))
+    int split_a = 0;
+    int split_wa = 0, split_ta = 0, split_ba = 0, split_wb = 0, split_tb = 0, split_bb = 0;
+    size_t split_sha = 0, split_shb = 0;
 };
 
 struct gpe_plan {

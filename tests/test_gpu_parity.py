@@ -167,7 +167,8 @@ def test_full_spectrum_states_on_the_headline_launch_shapes(shape, mode, monkeyp
 @pytest.mark.parametrize("mode", ["real", "imag"])
 def test_8192_point_lines(shape, mode, monkeypatch):
     """Lines of 8192 points, the longest a plan takes: row passes at radix 16 (512 threads
-    per line), column passes at radix 8 with one column per tile.  White-noise states with
+    per line), the column step in three passes (the single pass, one column per tile, in
+    test_long_columns_in_three_passes).  White-noise states with
     the field ODE and every potential term, three real or two imaginary steps against the
     oracle, pointwise; the energy functional on the same grid."""
     nx, ny = shape
@@ -188,6 +189,31 @@ def test_8192_point_lines(shape, mode, monkeypatch):
     else:
         assert rel_e(plan.energy(d, 0.0)["e"], O.energy(problem(s), ref, 0.0, st.alpha)["e"]) < 1e-7
 
+
+@pytest.mark.parametrize("shape", [(64, 8192), (16, 4096), (512, 4096)])
+@pytest.mark.parametrize("mode", ["real", "imag"])
+@pytest.mark.parametrize("split", ["three", "one"])
+def test_long_columns_in_three_passes(shape, mode, split, monkeypatch):
+    """The column step on 4096- and 8192-point columns as three passes (128-point transforms
+    of rows strided by ny/128 with the cross twiddles; (ny/128)-point transforms of contiguous
+    rows with the kinetic factor and back; the inverse 128-point transforms) and as the
+    single pass, on white noise with the field ODE (its tail rides on the first of the three
+    passes), against the oracle pointwise."""
+    monkeypatch.setenv("GPE_COL_SPLIT_MIN", "4096" if split == "three" else str(1 << 30))
+    nx, ny = shape
+    s = W.Setup(nx=nx, ny=ny, lx=nx / 16.0, ly=ny / 16.0, dt=2e-4, g=800.0, wx=0.05, wy=0.07, y0=0.4,
+                kx_lat=1.0, ky_lat=2.0, sx=W.Schedule("const", 2.0), sy=W.Schedule("ramp", 0.0, 3.0, 0.0, 1e-3),
+                cavity=True, vc=1.5, kc=1.0, delta_c=-20.0, kappa=10.0, eta=4.0, alpha0=0.1 - 0.2j)
+    psi0 = W.random_state(s, 23)
+    n = 3 if mode == "real" else 2
+    st = state(s)
+    ref, _ = (O.step_real if mode == "real" else O.step_imag)(problem(s), st, psi0, n)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    (plan.step_real if mode == "real" else plan.step_imag)(d, n, 0.0)
+    _assert_pointwise(to_host(d), ref)
+    if mode == "real":
+        assert abs(plan.cavity()["alpha"] - st.alpha) <= 1e-6 * abs(st.alpha)
 
 # ----------------------------------------------- imaginary-time ground state
 
