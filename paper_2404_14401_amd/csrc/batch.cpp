@@ -447,29 +447,24 @@ int gpe_step_batched(gpe_batch *b, gpe_c64 *const *psis, int64_t nsteps, double 
     return GPE_OK;
 }
 
-// Time `steps` middle steps of group g on its members' scratch arrays (device-side
-// contents are irrelevant to the timing; the members' cavity states are restored by
-// the caller).
-static double time_group(gpe_batch *b, BGroup &g, int steps)
+// Time batched calls of `steps` steps over every member's scratch array (contents
+// irrelevant to the timing): all groups at once, the LDS-resident ones on their side
+// stream, as a call runs them.  Best of two calls after one that loads kernels and
+// captures the step graph; microseconds per step, or 1e30 when a shape cannot launch.
+// The members' device states and history flags are restored by the caller.
+static double time_batch(gpe_batch *b, int steps)
 {
     std::vector<gpe_c64 *> psis(b->n, nullptr);
     for (int i = 0; i < b->n; ++i) psis[i] = (gpe_c64 *)b->plans[i]->scratch;
-    for (int i : g.members)  // the timed group's arrays: finite contents
-        (void)hipMemsetAsync(b->plans[i]->scratch, 0, sizeof(float2) * (size_t)b->plans[i]->nx * b->plans[i]->ny,
-                             b->work);
-    if (bind_psis(b, psis.data(), 1)) return 1e30;
+    drop_graph(b);
+    if (gpe_step_batched(b, psis.data(), steps, 0.0) || hipStreamSynchronize(b->work) != hipSuccess) return 1e30;
+    double best = 1e30;
     for (int it = 0; it < 2; ++it) {
         auto t = std::chrono::steady_clock::now();
-        for (int k = 0; k < steps; ++k) {
-            if (group_col(b, g, b->work) || (g.adia && group_row(b, g, ROW_PROBE_MID, k, b->work)) ||
-                group_row(b, g, ROW_MID, k, b->work))
-                return 1e30;
-        }
-        if (hipStreamSynchronize(b->work) != hipSuccess) return 1e30;
-        double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count();
-        if (it == 1) return us / steps;
+        if (gpe_step_batched(b, psis.data(), steps, 0.0) || hipStreamSynchronize(b->work) != hipSuccess) return 1e30;
+        best = std::min(best, std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count());
     }
-    return 1e30;
+    return best / steps;
 }
 
 int gpe_batch_tune(gpe_batch *b, const char *cache_path)
@@ -486,20 +481,32 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path)
         std::string l;
         while (std::getline(f, l)) lines.push_back(l);
     }
-    // the timing runs advance the members' cavity states: keep them and put them back
+    // the timing runs advance the members' cavity states and history flags: keep them and
+    // put them back
     std::vector<DevState> saved(b->n);
+    std::vector<char> had_theta(b->n);
     HIP_OK(hipStreamSynchronize(b->work));
-    for (int i = 0; i < b->n; ++i)
+    for (int i = 0; i < b->n; ++i) {
         HIP_OK(hipMemcpy(&saved[i], b->plans[i]->st, sizeof(DevState), hipMemcpyDeviceToHost));
-    bool changed = false;
+        had_theta[i] = b->plans[i]->have_theta ? 1 : 0;
+    }
+    // the shapes interact (the multi-pass groups run one after another beside the LDS
+    // groups on the side stream, and share the caches), so they are tuned on whole batched
+    // steps, one group at a time with the others held, and cached for this composition
+    std::ostringstream comp;
+    for (auto &g : b->groups) comp << (g.lds ? " L" : " M") << g.nx << "x" << g.ny << "x" << g.members.size();
+    auto key_of = [&](const BGroup &g) {
+        std::ostringstream key;
+        key << arch << " " << g.nx << " " << g.ny << " " << g.members.size() << " in" << comp.str() << " :";
+        return key.str();
+    };
+    bool all_cached = true;
     for (auto &g : b->groups) {
         if (g.lds) continue;
-        std::ostringstream key;
-        key << arch << " " << g.nx << " " << g.ny << " " << g.members.size();
         bool found = false;
         for (auto &l : lines) {
-            if (l.rfind(key.str() + " ", 0) == 0) {
-                std::istringstream is(l.substr(key.str().size()));
+            if (l.rfind(key_of(g) + " ", 0) == 0) {
+                std::istringstream is(l.substr(key_of(g).size()));
                 Tuning t;
                 double us;
                 if (is >> t.radix >> t.row_threads >> t.min_col_tiles >> us) {
@@ -509,32 +516,53 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path)
                 }
             }
         }
-        if (found) continue;
-        Tuning best = g.tune;
-        double best_us = 1e30;
-        for (int r : {8, 4})
-            for (int rt : {128, 256, 512})
-                for (int mt : {128, 256, 512}) {
-                    if (g.nx / r > 512 || g.ny / r > 1024 || g.nx > 2048 || g.ny > 2048) continue;
-                    g.tune = {r, rt, mt};
-                    g.shape = group_shape(g);
-                    if (g.shape.row_threads > 512 || g.shape.col_threads > 1024) continue;
-                    const double us = time_group(b, g, 10);
-                    if (us < best_us) {
-                        best_us = us;
-                        best = g.tune;
+        all_cached = all_cached && found;
+    }
+    bool changed = false;
+    if (!all_cached) {
+        for (int i = 0; i < b->n; ++i)
+            (void)hipMemsetAsync(b->plans[i]->scratch, 0, sizeof(float2) * (size_t)b->plans[i]->nx * b->plans[i]->ny,
+                                 b->work);
+        const int steps = 2 * b->chunk + 8;
+        std::vector<double> best_us(b->groups.size(), 1e30);
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            BGroup &g = b->groups[gi];
+            if (g.lds) continue;
+            Tuning best = g.tune;
+            // column tiles per member from whole-line tiles (16 columns of complex64, at
+            // 16..64 tiles) to narrow ones that spread a member over more work-groups
+            for (int r : {8, 4})
+                for (int rt : {128, 256, 512})
+                    for (int mt : {16, 32, 64, 128, 256, 512}) {
+                        if (g.nx / r > 512 || g.ny / r > 1024 || g.nx > 2048 || g.ny > 2048) continue;
+                        g.tune = {r, rt, mt};
+                        g.shape = group_shape(g);
+                        if (g.shape.row_threads > 512 || g.shape.col_threads > 1024) continue;
+                        const double us = time_batch(b, steps);
+                        if (us < best_us[gi]) {
+                            best_us[gi] = us;
+                            best = g.tune;
+                        }
                     }
-                }
-        g.tune = best;
-        g.shape = group_shape(g);
-        std::ostringstream l;
-        l << key.str() << " " << best.radix << " " << best.row_threads << " " << best.min_col_tiles << " " << best_us;
-        lines.push_back(l.str());
+            g.tune = best;
+            g.shape = group_shape(g);
+        }
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            const BGroup &g = b->groups[gi];
+            if (g.lds) continue;
+            std::ostringstream l;
+            l << key_of(g) << " " << g.tune.radix << " " << g.tune.row_threads << " " << g.tune.min_col_tiles << " "
+              << best_us[gi];
+            lines.push_back(l.str());
+        }
         changed = true;
     }
     HIP_OK(hipStreamSynchronize(b->work));
-    for (int i = 0; i < b->n; ++i)
+    HIP_OK(hipStreamSynchronize(b->side));
+    for (int i = 0; i < b->n; ++i) {
         HIP_OK(hipMemcpy(b->plans[i]->st, &saved[i], sizeof(DevState), hipMemcpyHostToDevice));
+        b->plans[i]->have_theta = had_theta[i] != 0;
+    }
     drop_graph(b);
     b->warmed = false;
     if (changed && cache_path && *cache_path) {
