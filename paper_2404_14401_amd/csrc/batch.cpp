@@ -860,12 +860,14 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
     if (nx < 64 || ny < 64 || nx > 1024 || ny > 1024) return fail(GPE_ERR_UNSUPPORTED, "adjoint grid sizes 64..1024");
     // launch shape of the adjoint's passes: 256 threads per row work-group and at least
     // 128 column tiles per member, measured best at 16 x 512^2 against row 128/512 and
-    // 32..512 tiles (environment GPE_ADJ_ROW_THREADS, GPE_ADJ_MIN_COL_TILES for tuning runs)
+    // 32..512 tiles; the stored trajectory's passes (the adjoint alone) at least 64, which
+    // there took 0.244 s against 0.253 s for 2000 steps, where reconstruction lost 3%
+    // (environment GPE_ADJ_ROW_THREADS, GPE_ADJ_MIN_COL_TILES for tuning runs)
     auto env = [](const char *name, int dflt) {
         const char *v = getenv(name);
         return v && *v ? atoi(v) : dflt;
     };
-    const int art = env("GPE_ADJ_ROW_THREADS", 256), act = env("GPE_ADJ_MIN_COL_TILES", 128);
+    const int art = env("GPE_ADJ_ROW_THREADS", 256), act = env("GPE_ADJ_MIN_COL_TILES", store ? 64 : 128);
     Shape sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, act);
     if (sh.col_threads > 512) sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, nx / std::max(1, 512 / (ny / 8)));
     if (sh.col_threads > 512) return fail(GPE_ERR_UNSUPPORTED, "column shape");
