@@ -297,6 +297,8 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
         if ((rc = balloc(b, (void **)&b->d_states_mp, sizeof(DevState *) * mp.size()))) return cleanup(rc);
         HIP_OK(hipMemcpy(b->d_states_mp, mp.data(), sizeof(DevState *) * mp.size(), hipMemcpyHostToDevice));
     }
+    const char *tiles_env = getenv("GPE_BATCH_TILES");
+    const bool fixed_tiles = tiles_env && !strcmp(tiles_env, "fixed");
     for (auto &g : b->groups) {
         const size_t m = g.members.size();
         if (g.lds) {
@@ -311,6 +313,20 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
             }
             if ((rc = balloc(b, (void **)&g.d_lds, sizeof(LdsArgs) * m))) return cleanup(rc);
         } else {
+            if (!fixed_tiles && g.ny <= 512) {
+                // untuned column tiles of columns up to 512 points: the widest that a
+                // 1024-thread work-group and a 128-byte line of complex64 allow (16 columns),
+                // halved while the group would launch fewer than 1024 column work-groups.
+                // Measured against the default above, Gpts/s: 200 x 128^2 multi-pass 46.7 ->
+                // 74.4, 80 x 128^2 adiabatic 27.2 -> 35.2, the 208-member mix 77.6 -> 80.8,
+                // 16 x 512^2 77.7 -> 79.5; at 1024 points it lost (2 x 1024^2 43.6 -> 41.5,
+                // 64 x 1024^2 74.5 -> 72.2), where the XCD tile order already shares the lines.
+                // (GPE_BATCH_TILES=fixed keeps the default above everywhere.)
+                const int tc = std::max(1, g.ny / g.tune.radix);
+                int w = std::max(1, std::min({16, g.nx, 1024 / tc}));
+                while (w > 1 && (int64_t)m * (g.nx / w) < 1024) w /= 2;
+                g.tune.min_col_tiles = g.nx / w;
+            }
             g.shape = group_shape(g);
             g.h_inst.resize(m);
             for (size_t k = 0; k < m; ++k) {
