@@ -789,14 +789,15 @@ int gpe_step_imag(gpe_plan *p, gpe_c64 *psi, int64_t nsteps, double t, double *o
     // one step: entry kick (with the pending scale), columns, exit kick with the norm
     // partials, tail (renormalisation scale, field); the potential is frozen at t, so
     // every step without observables is the same launch sequence.  Without observables
-    // or the adiabatic field, and with at most kFoldRows row work-groups, the tail between
-    // steps is left out: every work-group of the next entry kick forms the scale from the
-    // exit partials itself, and one tail after the last step leaves the scale for the
-    // final renormalisation.  (Each entry work-group reads every partial, so the reads
-    // grow with the square of the row work-groups: measured, per 10^3 steps, 128^2 17.1 ->
-    // 14.7 ms, 1024^2 37.1 -> 36.1 ms, but 4096^2 326 -> 343 ms and 8192^2 3.0 s.)
-    constexpr int kFoldRows = 1024;
-    const bool fold = !obs && !adia && sh.row_blocks <= kFoldRows;
+    // or the adiabatic field, and with at most GPE_FOLD_ROWS (2048) row work-groups, the
+    // tail between steps is left out: every work-group of the next entry kick forms the
+    // scale from the exit partials itself, and one tail after the last step leaves the
+    // scale for the final renormalisation.  (Each entry work-group reads every partial, so
+    // the reads grow with the square of the row work-groups: measured, per step, 128^2
+    // 17.1 -> 14.7 us, 1024^2 37.1 -> 36.1 us, 2048^2 91.7 -> 90.0 us, but 4096^2 323.5 ->
+    // 332.8 us and 8192^2 1992 -> 2085 us.)
+    const int fold_rows = env_int("GPE_FOLD_ROWS", 2048);
+    const bool fold = !obs && !adia && sh.row_blocks <= fold_rows;
     auto tail = [&](int64_t n, hipStream_t s) -> int {
         TailArgs ta{};
         ta.partials = p->partials;

@@ -61,6 +61,22 @@ def test_free_flow_extreme_aspect_ratios(shape, monkeypatch):
     assert rel_l2(to_host(d), ref) < 2e-6
 
 
+@pytest.mark.parametrize("fold", ["fold", "tail"])
+def test_imag_fold_at_2048_row_work_groups(fold, monkeypatch):
+    """Imaginary time on 1024 x 2048 (2048 row work-groups of one line): with the tail between
+    steps left out (every entry work-group sums the 2048 exit norm partials itself) and with
+    the tail kernel, against the oracle pointwise on white noise in a trap and lattice."""
+    monkeypatch.setenv("GPE_FOLD_ROWS", "2048" if fold == "fold" else "1024")
+    s = W.Setup(nx=1024, ny=2048, lx=64.0, ly=128.0, dt=0.002, g=300.0, wx=0.08, wy=0.05,
+                kx_lat=1.0, sx=W.Schedule("const", 2.0))
+    psi0 = W.random_state(s, 31)
+    ref, _ = O.step_imag(problem(s), state(s), psi0, 4)
+    plan = make_plan(s, "multipass", monkeypatch)
+    d = to_dev(psi0)
+    plan.step_imag(d, 4, 0.0)
+    _assert_pointwise(to_host(d), ref)
+    assert abs(plan.norm(d) - 1.0) < 1e-6
+
 def test_largest_grid_steps_with_every_potential_term(monkeypatch):
     """4096^2, the plan's largest grid: two real steps and one imaginary step with the
     trap, both lattices, g and the cavity field ODE, against the oracle."""
