@@ -313,10 +313,7 @@ __device__ __forceinline__ void row_body(const float2 *__restrict__ src_base, fl
 // Points per thread of the plan's row passes: kRadix, except for 8192-point lines, whose
 // 512 threads at radix 16 stay within the row pass's 512-thread bound (radix 8 would need
 // 1024 threads, which caps a thread at 128 registers; the fused row pass holds more).
-#ifndef GPE_ROW_RADIX_1024
-#define GPE_ROW_RADIX_1024 kRadix
-#endif
-template <int N> constexpr int kRowRadix = N >= 8192 ? 16 : N == 1024 ? GPE_ROW_RADIX_1024 : kRadix;
+template <int N> constexpr int kRowRadix = N >= 8192 ? 16 : kRadix;
 
 template <int N, int MODE, bool IMAG>
 __global__ void __launch_bounds__(512) row_pass(RowArgs a)

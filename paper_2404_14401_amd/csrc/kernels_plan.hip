@@ -5,7 +5,7 @@
 namespace gpe {
 
 int kernel_radix() { return kRadix; }
-int row_radix(int n) { return n >= 8192 ? kRowRadix<8192> : n == 1024 ? kRowRadix<1024> : kRadix; }
+int row_radix(int n) { return n >= 8192 ? kRowRadix<8192> : kRadix; }
 size_t xchg_bytes() { return sizeof(XchgT); }
 // extra LDS bytes per work-group for the staged tables (twiddles + one axis table)
 
