@@ -304,3 +304,29 @@ def test_cavity_on_wide_and_tall_grids_with_replayed_chunks(shape, cavity, monke
     t = n * s.dt
     e_ref = O.energy(problem(s), ref, t, st.alpha)["e"]
     assert abs(plan.energy(d, t)["e"] - e_ref) <= 1e-5 * abs(e_ref)
+
+
+@pytest.mark.parametrize("records", [True, False])
+def test_adiabatic_field_on_4096_point_columns(records, monkeypatch):
+    """The adiabatic field on a tall grid whose 4096-point columns take the column step in
+    three passes, white noise, three real-time steps with and without per-step records (the
+    records' reduction tail rides on the first of the three passes): psi and alpha against
+    the oracle."""
+    s = W.Setup(nx=64, ny=4096, lx=8.0, ly=256.0, dt=0.01, g=30.0, wx=1.1, wy=0.02, y0=0.5,
+                kx_lat=1.3, ky_lat=2.1, sx=W.Schedule("const", 1.5), sy=W.Schedule("ramp", -1.0, -6.0, 0.0, 0.2),
+                cavity=True, cavity_mode="adiabatic", vc=-0.3, kc=1.7, delta_c=-4.0, kappa=2.0, n_atoms=30.0)
+    psi0 = W.random_state(s, 11)
+    st = state(s, 0.05)
+    ref, robs = O.step_real(problem(s), st, psi0, 3, want_obs=True)
+    plan = make_plan(s, "multipass", monkeypatch)
+    import torch
+
+    d = to_dev(psi0)
+    obs = torch.zeros((3, 6), dtype=torch.float64, device="cuda") if records else None
+    plan.step_real(d, 3, 0.05, obs)
+    assert rel_l2(to_host(d), ref) < 2e-6
+    if records:
+        o = obs.cpu().numpy()
+        for n in range(3):
+            assert close_alpha(o[n, 2] + 1j * o[n, 3], robs[n, 2] + 1j * robs[n, 3], 1e-5), n
+    assert close_alpha(plan.cavity()["alpha"], st.alpha, 1e-5)
