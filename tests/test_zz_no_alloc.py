@@ -12,13 +12,14 @@ pytestmark = pytest.mark.gpu
 
 
 def cases():
-    # the longest lines a plan takes (8192, the largest tables) with the field ODE;
-    # multi-pass with the field ODE; multi-pass, non-square, lattice knots, no cavity;
+    # the longest lines a plan takes (8192, the largest tables) with the field ODE, along x
+    # and along y (whose column step then runs as three passes); multi-pass with the field ODE; multi-pass, non-square, lattice knots, no cavity;
     # whole grid in LDS (real time at 32^2) with the adiabatic field
     rng = np.random.default_rng(5)
     knots = W.Schedule("knots", t0=0.0, t1=0.05, knots=rng.uniform(0.0, 8.0, 40))
     return [
         ("wide_8192x32", W.cavity_scaled(32, seed=2).with_(nx=8192, lx=512.0), 12),
+        ("tall_16x8192", W.cavity_scaled(32, seed=4).with_(nx=16, lx=1.0, ny=8192, ly=512.0), 12),
         ("cavity_256", W.cavity_scaled(256, seed=1), 40),
         ("knots_128x64", W.Setup(nx=128, ny=64, lx=16.0, ly=8.0, dt=1e-3, g=150.0, kx_lat=2.0, sx=knots), 30),
         ("adiabatic_32", W.self_organisation_128(8.0, -20.0).with_(nx=32, ny=32, lx=8.0, ly=8.0), 25),
