@@ -231,6 +231,39 @@ def test_long_columns_in_three_passes(shape, mode, split, monkeypatch):
     if mode == "real":
         assert abs(plan.cavity()["alpha"] - st.alpha) <= 1e-6 * abs(st.alpha)
 
+def test_8192_squared_three_pass_columns_match_the_single_pass(monkeypatch):
+    """The largest grid, 8192^2, with every potential term and white noise: two real and two
+    imaginary steps with the column step in three passes and in one (the one-pass column
+    step is checked against the oracle at smaller sizes; the oracle takes minutes here).
+    The two agree to their rounding, and real time keeps the norm."""
+    import torch
+
+    from paper_2404_14401_amd import gpe
+
+    s = W.Setup(nx=8192, ny=8192, lx=512.0, ly=512.0, dt=2e-4, g=800.0, wx=0.01, wy=0.012, x0=0.7,
+                kx_lat=1.0, ky_lat=2.0, sx=W.Schedule("ramp", 0.0, 3.0, 0.0, 1e-3), sy=W.Schedule("const", 1.5))
+    rng = np.random.Generator(np.random.PCG64(41))
+    z = torch.from_numpy((rng.standard_normal((8192, 8192), dtype=np.float32)
+                          + 1j * rng.standard_normal((8192, 8192), dtype=np.float32)).astype(np.complex64))
+    torch_cuda()
+    psi0 = z.to("cuda")
+    psi0 /= torch.sqrt(torch.sum(torch.abs(psi0) ** 2) * (s.lx / s.nx) * (s.ly / s.ny))
+    out = {}
+    for split in ("three", "one"):
+        monkeypatch.setenv("GPE_COL_SPLIT_MIN", "4096" if split == "three" else str(1 << 30))
+        monkeypatch.setenv("GPE_PATH", "multipass")
+        p = gpe.Plan.from_setup(s)
+        r = psi0.clone()
+        p.step_real(r, 2, 0.0)
+        i = psi0.clone()
+        p.step_imag(i, 2, 0.0)
+        out[split] = (r, i, p.norm(r))
+        p.close()
+    for k in (0, 1):
+        a, b = out["three"][k], out["one"][k]
+        assert float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) < 1e-6, k
+    assert abs(out["three"][2] - 1.0) < 1e-5 and abs(out["one"][2] - 1.0) < 1e-5
+
 # ----------------------------------------------- imaginary-time ground state
 
 @pytest.mark.parametrize("path", ["lds", "multipass"])
