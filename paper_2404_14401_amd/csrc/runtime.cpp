@@ -115,8 +115,14 @@ static void set_split(Shape &s, int nx, int ny)
 
 static Shape make_shape(int nx, int ny)
 {
+    // column tiles: at least 256 per grid, and up to 2048-point columns work-groups of at
+    // most 512 threads (2048-point columns: two columns per tile rather than four, 87.9
+    // against 89.9 us per 2048^2 imaginary step; at 1024 points 512 threads is the 256-tile
+    // shape already; longer columns take the three-pass column step)
+    const int tc = std::max(1, ny / kernel_radix());
+    const int min_tiles = ny <= 2048 ? std::max(256, (int)std::min<int64_t>((int64_t)nx * tc / 512, nx)) : 256;
     Shape s = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128),
-                           env_int("GPE_MIN_COL_TILES", 256), row_radix(nx));
+                           env_int("GPE_MIN_COL_TILES", min_tiles), row_radix(nx));
     const int w = env_int("GPE_COL_W", 0);
     if (w > 0 && w <= nx && (w & (w - 1)) == 0 && w * s.col_threads / s.col_cols <= 1024) {
         Shape t = make_shape_r(nx, ny, kernel_radix(), xchg_bytes(), env_int("GPE_ROW_THREADS", 128), nx / w,
