@@ -263,12 +263,13 @@ int gpe_batch_create(gpe_batch **out, int n, const gpe_plan_desc *descs, const g
             BGroup g;
             g.nx = p->nx;
             g.ny = p->ny;
-            // untuned shape: 128 threads per row work-group, and column tiles at least two
-            // columns wide up to 512 points per row (128 tiles), 256 tiles beyond.  Measured on
-            // the MI355X in us per batch step against the former 256/256: 64 x 256^2 56.1 vs
-            // 75.3, 16 x 512^2 53.0 vs 56.3, 2 x 1024^2 49.8 vs 50.5, 4 x 1024^2 76.9 vs 76.9,
-            // 200 x 128^2 66.4 vs 67.8 (gpe_batch_tune can still do better per group)
-            g.tune = Tuning{8, 128, g.nx <= 512 ? 128 : 256};
+            // untuned shape: 64 threads per row work-group (several lines each up to 512
+            // points per row, one line from 1024 on; 2-3% faster than 128 on the 208-member mix,
+            // 80 x 128^2 and 16 x 512^2), and 128 column tiles per member up to 512 points per
+            // row, 256 beyond (which the member-count rule below refines up to 512 points;
+            // against the 256/256 shape before it, us per batch step: 64 x 256^2 56.1 vs 75.3,
+            // 16 x 512^2 53.0 vs 56.3, 2 x 1024^2 49.8 vs 50.5, 4 x 1024^2 76.9 vs 76.9)
+            g.tune = Tuning{8, 64, g.nx <= 512 ? 128 : 256};
             b->groups.push_back(g);
             it = b->groups.end() - 1;
         }
@@ -548,7 +549,7 @@ int gpe_batch_tune(gpe_batch *b, const char *cache_path)
             // column tiles per member from whole-line tiles (16 columns of complex64, at
             // 16..64 tiles) to narrow ones that spread a member over more work-groups
             for (int r : {8, 4})
-                for (int rt : {128, 256, 512})
+                for (int rt : {64, 128, 256, 512})
                     for (int mt : {16, 32, 64, 128, 256, 512}) {
                         if (g.nx / r > 512 || g.ny / r > 1024 || g.nx > 2048 || g.ny > 2048) continue;
                         g.tune = {r, rt, mt};
