@@ -764,7 +764,7 @@ static int pair_sums(gpe_batch *b, AdjWork *w, const std::vector<const float2 *>
 
 // Forward real-time steps [n0, n1) of every member on the adjoint workspace (batched
 // multi-pass kernels, time base st->t0 = t0 + n0 dt).
-static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int64_t n0, int64_t n1,
+static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, int radix, double t0, int64_t n0, int64_t n1,
                        bool record = false)
 {
     const int nb = w->nb;
@@ -783,14 +783,14 @@ static int adj_forward(gpe_batch *b, AdjWork *w, const Shape &sh, double t0, int
     const int64_t k = n1 - n0;
     ra.n = 0;
     if (w->any_adia)
-        LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_PROBE_REAL, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
-    LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_ENTRY, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+        LAUNCH_OK(launch_row_batched(w->nx, radix, ROW_PROBE_REAL, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+    LAUNCH_OK(launch_row_batched(w->nx, radix, ROW_ENTRY, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
     for (int64_t j = 0; j < k; ++j) {
-        LAUNCH_OK(launch_col_batched(w->ny, 8, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
+        LAUNCH_OK(launch_col_batched(w->ny, radix, ca, cblocks, sh.col_threads, sh.col_shmem, b->work));
         ra.n = (int)j;
         if (w->any_adia)
-            LAUNCH_OK(launch_row_batched(w->nx, 8, ROW_PROBE_MID, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
-        LAUNCH_OK(launch_row_batched(w->nx, 8, j + 1 < k ? ROW_MID : ROW_EXIT, ra, rblocks, sh.row_threads,
+            LAUNCH_OK(launch_row_batched(w->nx, radix, ROW_PROBE_MID, ra, rblocks, sh.row_threads, sh.row_shmem, b->work));
+        LAUNCH_OK(launch_row_batched(w->nx, radix, j + 1 < k ? ROW_MID : ROW_EXIT, ra, rblocks, sh.row_threads,
                                      sh.row_shmem, b->work));
     }
     return GPE_OK;
@@ -894,6 +894,16 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
         sh = make_shape_r(nx, ny, 8, xchg_bytes(), art, tiles);
     if (adj_col_shmem(ny, sh.col_cols, 8, 2) > 158 * 1024 || adj_row_shmem(nx, sh.row_lines, 8, 2) > 158 * 1024)
         return fail(GPE_ERR_UNSUPPORTED, "adjoint passes exceed the LDS of a work-group");
+    // the forward sweep takes the batch's own (tuned) shape of this grid size where the
+    // group runs the batched passes, at radix 8 for the stored trajectory (whose recording
+    // kernels are radix 8 only); else the adjoint's shape
+    Shape fsh = sh;
+    int fr = 8;
+    for (auto &g : b->groups)
+        if (!g.lds && g.nx == nx && g.ny == ny && (g.tune.radix == 8 || !store)) {
+            fsh = g.shape;
+            fr = g.tune.radix;
+        }
     AdjWork *w = adj_work(b);
     const int64_t seg = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
     const int64_t nseg = (nsteps + seg - 1) / seg;
@@ -934,9 +944,9 @@ int gpe_adjoint(gpe_batch *b, const gpe_c64 *const *psi0, const gpe_c64 *const *
             for (int64_t s = 0; s < nseg; ++s) {
                 // every member's psi into slot s: one launch
                 LAUNCH_OK(launch_copy_members(w->d_ckpt + (size_t)s * nb, w->d_psi, npts, nb, kCopyBlocks, b->work));
-                if ((r = adj_forward(b, w, sh, t0, s * seg, std::min(nsteps, (s + 1) * seg)))) return r;
+                if ((r = adj_forward(b, w, fsh, fr, t0, s * seg, std::min(nsteps, (s + 1) * seg)))) return r;
             }
-        } else if ((r = adj_forward(b, w, sh, t0, 0, nsteps, store))) {
+        } else if ((r = adj_forward(b, w, fsh, fr, t0, 0, nsteps, store))) {
             return r;
         }
         if (psi_final)
